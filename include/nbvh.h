@@ -1,0 +1,297 @@
+/*
+ * nbvh.h -- C ABI of the MI355X (gfx950) N-BVH library: neural ray queries
+ * through a shallow BVH whose leaves are neural nodes, and the training step
+ * of that network.
+ *
+ * Paper: "N-BVH: Neural ray queries with bounding volume hierarchies"
+ * (Weier et al., SIGGRAPH 2024). Section references below are to it.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Pointers named *_dev are device (HBM) pointers; *_host are host
+ *    pointers. The caller allocates and owns ALL device memory: nodes,
+ *    parameters, optimiser state, workspace, inputs and outputs. The library
+ *    keeps pointers and host metadata in its context and never frees caller
+ *    memory.
+ *  - `stream` is a hipStream_t (NULL = the null stream). Every call except
+ *    nbvh_build and nbvh_read_state only enqueues work on that stream and
+ *    returns; none of them synchronises the host, so the sequences are
+ *    capturable in a HIP graph.
+ *  - Return value: NBVH_OK or an error code. Argument errors are detected on
+ *    the host before anything is enqueued; nbvh_last_error() then holds a
+ *    message (per thread). Launch failures return NBVH_ERR_HIP.
+ *  - Device-side conditions (segment capacity exceeded, non-finite
+ *    gradients) set bits in the state block; nbvh_read_state reports them.
+ *  - Structs are plain 4-byte-aligned records, laid out exactly as declared.
+ */
+#ifndef NBVH_H
+#define NBVH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NBVH_OK = 0,
+  NBVH_ERR_INVALID_ARG = 1, /* bad pointer, size or configuration */
+  NBVH_ERR_CAPACITY = 2,    /* a caller buffer is too small */
+  NBVH_ERR_NOT_BOUND = 3,   /* parameters not bound (nbvh_bind_params) */
+  NBVH_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
+  NBVH_ERR_UNSUPPORTED = 5  /* valid but not implemented shape/precision */
+} nbvh_status;
+
+/* Arithmetic of the MLP and of the feature reads in queries and training.
+ * FP32: FP32 table reads and FP32 matrix-core products.
+ * BF16: BF16 table shadow, BF16 activations and weights, FP32 accumulation.
+ * FP8 : (query only) E4M3 weights and activations with per-layer scales. */
+typedef enum { NBVH_FP32 = 0, NBVH_BF16 = 1, NBVH_FP8 = 2 } nbvh_precision;
+
+/* Device-state flag bits (nbvh_state_host.flags). */
+#define NBVH_FLAG_CAPACITY 1u  /* a traversal produced more segments than seg_capacity */
+#define NBVH_FLAG_NONFINITE 2u /* a training step saw a non-finite loss/gradient and was skipped */
+
+#define NBVH_MAX_LEVELS 32
+#define NBVH_MISS 0xFFFFFFFFu
+
+/* A ray: origin, [tmin, tmax], direction (not necessarily unit length).
+ * Direction components must be 0 or normal floats. 32 bytes. */
+typedef struct {
+  float o[3];
+  float tmin;
+  float d[3];
+  float tmax;
+} nbvh_ray;
+
+/* One ray/leaf crossing: [t0, t1] is the part of the ray's [tmin, tmax]
+ * inside the leaf box (Sec. 5: inference queries the model on each leaf a
+ * ray reaches). 16 bytes. */
+typedef struct {
+  uint32_t ray;
+  uint32_t leaf;
+  float t0;
+  float t1;
+} nbvh_segment;
+
+/* A training/forward segment: ray origin o, direction d and the leaf
+ * interval [t0, t1] to sample (Sec. 4, "Encoding, inference & training").
+ * 32 bytes. */
+typedef struct {
+  float o[3];
+  float t0;
+  float d[3];
+  float t1;
+} nbvh_probe;
+
+/* Ground truth of a probe (Sec. 5.2): tau = (t_hit - t0)/(t1 - t0) in [0,1]
+ * (local distance), unit normal n, hit = 1.0f if the geometry is hit inside
+ * the segment else 0.0f, albedo (unused unless n_out >= 8). 32 bytes. */
+typedef struct {
+  float tau;
+  float n[3];
+  float hit;
+  float albedo[3];
+} nbvh_label;
+
+/* Result of a neural ray query: the closest predicted hit over the leaves
+ * the ray crosses. t is along the ray; n is the raw (linear) normal output;
+ * albedo is the sigmoid output when n_out >= 8, else 0; leaf = NBVH_MISS
+ * when no segment is predicted hit (then the other fields are 0). 32 bytes. */
+typedef struct {
+  float t;
+  float n[3];
+  float albedo[3];
+  uint32_t leaf;
+} nbvh_hit;
+
+/* Network and training description (Sec. 3, Sec. 6). Level l has
+ * resolution level_res[l] (N_l); a level whose (N_l+1)^3 entries fit in
+ * T = 2^log2_T is indexed densely, otherwise by the spatial hash
+ * (x*1 xor y*2654435761 xor z*805459861) mod T. Each segment is sampled at
+ * n_samples stratum midpoints; the MLP input is the concatenation
+ * n_in = n_samples * n_levels * n_features (sample-major, then level, then
+ * feature), followed by mlp_hidden ReLU layers of mlp_width and a linear
+ * output layer of n_out (hit logit, local-distance logit, normal xyz
+ * [, albedo logits rgb]). Sample positions are mapped into the cube
+ * [scene_lo, scene_lo + scene_side]^3 and clamped to it.
+ * Supported: n_features in {2, 4}; n_in % 32 == 0; mlp_width in
+ * {32, 64, 128, 256}; 1 <= mlp_hidden <= 8; 5 <= n_out <= 16;
+ * 1 <= n_levels <= 32; 1 <= n_samples <= 16; 1 <= log2_T <= 24.
+ * Loss weights w_* (Sec. 5.2 "Combined loss": 2, 2, 1, 1) and Adam
+ * hyper-parameters (Sec. 6: learning rate 0.01) drive nbvh_train_step;
+ * loss_scale multiplies dL/dz before back-propagation and is divided out
+ * in the optimiser. */
+typedef struct {
+  int32_t n_levels, n_features, log2_T, n_samples;
+  int32_t level_res[NBVH_MAX_LEVELS];
+  int32_t mlp_width, mlp_hidden, n_out;
+  int32_t precision; /* nbvh_precision */
+  float scene_lo[3];
+  float scene_side;
+  float w_hit, w_t, w_normal, w_albedo;
+  float lr, beta1, beta2, eps, loss_scale;
+} nbvh_config;
+
+/* Caller-owned device buffers of the learnable state. All FP32 arrays have
+ * n_params = n_table + n_mlp entries laid out as [hash table | W_0 | ... |
+ * W_H]: the table level-major, then entry, then feature; each W_k row-major
+ * [fan_out][fan_in] (no biases); each block starts on a 64-element
+ * boundary and the gaps are zero (nbvh_param_layout gives the offsets).
+ * params_lp is the BF16 shadow of params in
+ * the same layout (written by nbvh_sync_shadow and by every Adam step);
+ * it may be NULL only if precision is FP32. grad accumulates dL/dparams
+ * (times loss_scale) and is cleared by each optimiser step. state_dev is
+ * nbvh_state_bytes() bytes. */
+typedef struct {
+  float* params_dev;
+  void* params_lp_dev;
+  float* adam_m_dev;
+  float* adam_v_dev;
+  float* grad_dev;
+  void* state_dev;
+  void* aux_dev; /* nbvh_aux_bytes(cfg) bytes: transposed weight copies read by back-propagation */
+} nbvh_params;
+
+/* Host copy of the device state block. */
+typedef struct {
+  int64_t step;        /* optimiser steps applied */
+  int64_t skipped;     /* steps skipped because of non-finite gradients */
+  float loss_scale;    /* current loss scale */
+  uint32_t flags;      /* NBVH_FLAG_* bits, sticky until nbvh_clear_flags */
+  float last_loss[4];  /* last train step: total, BCE, distance L1, normal L1 (unweighted) */
+  uint64_t last_n_segments; /* segments produced by the last traversal */
+} nbvh_state_host;
+
+typedef struct nbvh_ctx nbvh_ctx; /* opaque host handle */
+
+/* Parameter counts for a configuration (no context needed). Returns
+ * NBVH_ERR_INVALID_ARG for unsupported configurations. */
+nbvh_status nbvh_param_count(const nbvh_config* cfg, uint64_t* n_table, uint64_t* n_mlp);
+
+/* Offsets (elements) of the parameter blocks: offsets[0] = 0 is the hash
+ * table, offsets[1 + k] the start of W_k (k = 0..mlp_hidden), and
+ * offsets[mlp_hidden + 2] the total n_params. `offsets` must hold
+ * mlp_hidden + 3 entries. */
+nbvh_status nbvh_param_layout(const nbvh_config* cfg, uint64_t* offsets);
+
+/* Bytes of the auxiliary buffer (transposed FP32 and BF16 weight copies,
+ * rewritten by nbvh_sync_shadow and every optimiser step). */
+size_t nbvh_aux_bytes(const nbvh_config* cfg);
+
+/* Bytes of the node buffer nbvh_build writes for n_leaves leaves. */
+size_t nbvh_nodes_bytes(uint32_t n_leaves);
+
+/* Bytes of the device state block. */
+size_t nbvh_state_bytes(void);
+
+/* Build the N-BVH over the neural leaves (Sec. 5, Fig. "pipeline": a
+ * shallow BVH whose leaves are hollow boxes). leaf_boxes_host is
+ * [n_leaves][6] floats (lo.xyz, hi.xyz), leaf ids are row indices. The
+ * tree is a median split of leaf centroids on the widest axis; every inner
+ * box is the exact min/max union of its children, so the tree visits
+ * exactly the leaves an every-leaf slab test would. Nodes are copied to
+ * nodes_dev (nbvh_nodes_bytes(n_leaves) bytes, caller-owned) and the call
+ * synchronises `stream` once. *out receives a new context (nbvh_destroy). */
+nbvh_status nbvh_build(const nbvh_config* cfg, const float* leaf_boxes_host, uint32_t n_leaves,
+                       void* nodes_dev, size_t nodes_bytes, void* stream, nbvh_ctx** out);
+
+/* Attach the learnable state. Pointers are kept until the next bind. */
+nbvh_status nbvh_bind_params(nbvh_ctx* ctx, const nbvh_params* p);
+
+/* Reset optimiser state: m = v = grad = 0, step = 0, loss scale =
+ * cfg.loss_scale, flags cleared; and write the BF16 shadow of params. */
+nbvh_status nbvh_reset_optimizer(nbvh_ctx* ctx, void* stream);
+
+/* Rewrite the BF16 shadow from the FP32 params (after the caller edits
+ * params directly). */
+nbvh_status nbvh_sync_shadow(nbvh_ctx* ctx, void* stream);
+
+/* Workspace bytes for queries of up to max_rays rays producing up to
+ * max_segments segments, and for training/forward/backward batches of up to
+ * max_batch probes. One workspace may serve all calls (not concurrently). */
+size_t nbvh_workspace_bytes(const nbvh_ctx* ctx, uint64_t max_rays, uint64_t max_segments,
+                            uint64_t max_batch);
+
+/* Traversal only (Sec. 5: front-to-back N-BVH traversal with empty-space
+ * skipping): writes seg_offsets_dev[n_rays + 1] (exclusive prefix sum of
+ * per-ray counts) and, if the total fits seg_capacity, segs_dev[total] with
+ * each ray's run sorted by (t0, leaf id). Slab tests are binary32, one
+ * rounding per operation, correctly rounded reciprocals. On overflow the
+ * offsets are still complete, segments are not written and
+ * NBVH_FLAG_CAPACITY is set. */
+nbvh_status nbvh_traverse(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_rays,
+                          uint32_t* seg_offsets_dev, nbvh_segment* segs_dev, uint64_t seg_capacity,
+                          void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Neural ray query (Sec. 5; Fig. "neural ray query pipeline"): traversal,
+ * then for each ray its segments front to back: sample, encode, MLP,
+ * predicted hit when the hit logit z0 > 0 at t = t0 + sigmoid(z1)(t1 - t0).
+ * The ray's answer is the smallest such t (ties: earlier segment); a ray
+ * stops evaluating once its next segment starts at or after its best t,
+ * which cannot change the answer. seg_capacity bounds the segment queue in
+ * the workspace (see nbvh_traverse for overflow). Writes hits_dev[n_rays]. */
+nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_rays, nbvh_hit* hits_dev,
+                       uint64_t seg_capacity, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Query over a caller-given segment queue (offsets/segments as written by
+ * nbvh_traverse): evaluation and resolve only. */
+nbvh_status nbvh_query_segments(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_rays,
+                                const uint32_t* seg_offsets_dev, const nbvh_segment* segs_dev,
+                                nbvh_hit* hits_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Encoding only (Sec. 3/4): u_dev[n][n_in] FP32 features of each probe's
+ * samples, read from the FP32 table (precision FP32) or the BF16 shadow. */
+nbvh_status nbvh_encode(nbvh_ctx* ctx, const nbvh_probe* probes_dev, uint64_t n, float* u_dev,
+                        void* stream);
+
+/* Network outputs z_dev[n][n_out] (raw: logits and linear normal) for
+ * probe segments, in the configured precision. */
+nbvh_status nbvh_forward(nbvh_ctx* ctx, const nbvh_probe* probes_dev, uint64_t n, float* z_dev,
+                         void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Back-propagate dz_dev[n][n_out] (= dL/dz) into grad_dev (ADDED to it,
+ * scaled by the current loss scale), recomputing encodings and activations
+ * instead of storing them (Sec. 4: the loss is back-propagated into the
+ * MLP weights and the hash-table features). */
+nbvh_status nbvh_backward(nbvh_ctx* ctx, const nbvh_probe* probes_dev, uint64_t n,
+                          const float* dz_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Adam step over all parameters from grad_dev (Sec. 6: Adam, lr 0.01):
+ * unscale by the loss scale, bias-corrected moments, update params, write
+ * the BF16 shadow, clear grad. If the gradient holds a non-finite value
+ * the update is skipped, the loss scale halves and NBVH_FLAG_NONFINITE is
+ * set. */
+nbvh_status nbvh_optimizer_step(nbvh_ctx* ctx, void* stream);
+
+/* One training step (Sec. 4, Sec. 5.2): forward on the probes, combined
+ * loss L = (1/B) sum [w_hit BCE(z0, hit) + hit (w_t |sigmoid(z1) - tau| +
+ * w_normal/3 sum |z2..4 - n|)], back-propagation into grad and an
+ * optimiser step. loss_dev (nullable) receives [total, bce, dist, normal]
+ * as FP32 (unweighted terms; total weighted). */
+nbvh_status nbvh_train_step(nbvh_ctx* ctx, const nbvh_probe* probes_dev, const nbvh_label* labels_dev,
+                            uint64_t n, float* loss_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Loss and dL/dz only (no back-propagation): dz_dev may be NULL. */
+nbvh_status nbvh_loss(nbvh_ctx* ctx, const float* z_dev, const nbvh_label* labels_dev, uint64_t n,
+                      float* loss_dev, float* dz_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Copy the device state block to the host (synchronises `stream`). */
+nbvh_status nbvh_read_state(nbvh_ctx* ctx, nbvh_state_host* out, void* stream);
+
+/* Clear the sticky flag bits. */
+nbvh_status nbvh_clear_flags(nbvh_ctx* ctx, void* stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char* nbvh_last_error(void);
+
+/* Library version string. */
+const char* nbvh_version(void);
+
+void nbvh_destroy(nbvh_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBVH_H */

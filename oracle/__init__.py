@@ -63,6 +63,7 @@ def _lib():
             L.oc_loss.argtypes = [P, P, P, I, D, D, D, P, P]
             L.oc_backward.argtypes = [P, P, P, I, P, P]
             L.oc_adam.argtypes = [I, P, P, P, P, I, D, D, D, D, D]
+            L.oc_min_abs_preact.argtypes = [P, P, P, I, P]
             L.oc_resolve.argtypes = [I, P, P, P, P, P, ctypes.c_int, P]
             L.oc_num_threads.restype = ctypes.c_int
             _LIB = L
@@ -177,6 +178,15 @@ def forward(cfg, params, segs):
     params = _c(params, np.float64)
     nt = n_table_params(cfg)
     return mlp_forward(cfg, params[nt:], encode(cfg, params[:nt], segs))
+
+
+def min_abs_preact(cfg, params, segs):
+    """Per segment, the smallest |pre-activation| of any hidden unit."""
+    params = _c(params, np.float64)
+    segs = _c(segs, np.float32)
+    out = np.zeros(segs.shape[0], dtype=np.float64)
+    _lib().oc_min_abs_preact(ctypes.byref(cfg), _p(params), _p(segs), segs.shape[0], _p(out))
+    return out
 
 
 # -- training ---------------------------------------------------------------------

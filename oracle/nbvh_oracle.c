@@ -313,6 +313,34 @@ void oc_mlp_forward(const oc_cfg* c, const double* W, const double* u, int64_t n
   }
 }
 
+/* Smallest |pre-activation| over the hidden units of each segment: where it
+ * is within rounding of 0 the ReLU derivative (a 0/1 decision) is not fixed
+ * by the arithmetic, so gradient comparisons leave such segments out. */
+void oc_min_abs_preact(const oc_cfg* c, const double* params, const float* segs, int64_t n, double* out) {
+  int64_t n_tab = oc_table_params(c);
+  int n_in = oc_n_in(c), width = c->mlp_width, H = c->mlp_hidden;
+  int maxw = n_in > width ? n_in : width;
+#pragma omp parallel
+  {
+    double* u = (double*)malloc(sizeof(double) * (size_t)n_in);
+    double* pre = (double*)malloc(sizeof(double) * (size_t)H * width);
+    double* buf = (double*)malloc(sizeof(double) * 2 * (size_t)maxw);
+    double* z = (double*)malloc(sizeof(double) * (size_t)c->n_out);
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      oc_encode_one(c, params, segs + 8 * i, u);
+      oc_mlp_one(c, params + n_tab, u, z, pre, buf);
+      double m = INFINITY;
+      for (int j = 0; j < H * width; ++j) m = fabs(pre[j]) < m ? fabs(pre[j]) : m;
+      out[i] = m;
+    }
+    free(u);
+    free(pre);
+    free(buf);
+    free(z);
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Losses (Sec. 5.2): visibility is a binary cross-entropy on a sigmoid;     */
 /* the local distance (distance along the segment relative to its length,    */

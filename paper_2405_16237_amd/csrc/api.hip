@@ -1,0 +1,535 @@
+// C ABI of the library (include/nbvh.h): argument checking, the N-BVH build
+// on the host, parameter layout, workspace carve-up and kernel sequencing.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "launch.h"
+
+struct nbvh_ctx {
+  nbvh_config cfg;
+  nbvh::DevCfg dev;
+  uint32_t n_leaves;
+  nbvh::Node* nodes;
+  nbvh_params p;
+  bool bound;
+  int n_cu;
+};
+
+namespace nbvh {
+
+static thread_local char g_err[512];
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+nbvh_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return NBVH_ERR_HIP;
+  }
+  return NBVH_OK;
+}
+
+__global__ void k_zero_u32(uint32_t* p, uint32_t n) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+__global__ void k_zero_f32(float* p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+static uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// Validates cfg and fills the device description (no context needed).
+static nbvh_status make_devcfg(const nbvh_config* c, DevCfg* d) {
+  if (!c) {
+    set_error("cfg is NULL");
+    return NBVH_ERR_INVALID_ARG;
+  }
+  const int L = c->n_levels, F = c->n_features, S = c->n_samples;
+  if (L < 1 || L > NBVH_MAX_LEVELS) return set_error("n_levels %d not in [1, 32]", L), NBVH_ERR_INVALID_ARG;
+  if (F != 2 && F != 4) return set_error("n_features %d not in {2, 4}", F), NBVH_ERR_INVALID_ARG;
+  if (S < 1 || S > 16) return set_error("n_samples %d not in [1, 16]", S), NBVH_ERR_INVALID_ARG;
+  if (c->log2_T < 1 || c->log2_T > 24) return set_error("log2_T %d not in [1, 24]", c->log2_T), NBVH_ERR_INVALID_ARG;
+  const int n_in = S * L * F;
+  if (n_in % 32 != 0) return set_error("n_in = %d is not a multiple of 32", n_in), NBVH_ERR_INVALID_ARG;
+  if (n_in > 512) return set_error("n_in = %d exceeds 512", n_in), NBVH_ERR_UNSUPPORTED;
+  const int W = c->mlp_width;
+  if (W != 32 && W != 64 && W != 128 && W != 256) return set_error("mlp_width %d not in {32,64,128,256}", W), NBVH_ERR_INVALID_ARG;
+  if (c->mlp_hidden < 1 || c->mlp_hidden > 8) return set_error("mlp_hidden %d not in [1, 8]", c->mlp_hidden), NBVH_ERR_INVALID_ARG;
+  if (c->n_out < 5 || c->n_out > 16) return set_error("n_out %d not in [5, 16]", c->n_out), NBVH_ERR_INVALID_ARG;
+  if (c->precision != NBVH_FP32 && c->precision != NBVH_BF16 && c->precision != NBVH_FP8)
+    return set_error("precision %d unknown", c->precision), NBVH_ERR_INVALID_ARG;
+  if (!(c->scene_side > 0.0f) || !std::isfinite(c->scene_side))
+    return set_error("scene_side must be positive and finite"), NBVH_ERR_INVALID_ARG;
+  memset(d, 0, sizeof(*d));
+  d->n_levels = L;
+  d->n_features = F;
+  d->log2_T = c->log2_T;
+  d->n_samples = S;
+  d->n_in = n_in;
+  d->width = W;
+  d->hidden = c->mlp_hidden;
+  d->n_out = c->n_out;
+  const uint64_t T = 1ull << c->log2_T;
+  uint64_t off = 0;
+  for (int l = 0; l < L; ++l) {
+    const int N = c->level_res[l];
+    if (N < 1 || N > (1 << 24)) return set_error("level_res[%d] = %d invalid", l, N), NBVH_ERR_INVALID_ARG;
+    const uint64_t r1 = (uint64_t)N + 1;
+    const bool dense = r1 * r1 * r1 <= T;
+    d->level_res[l] = N;
+    if (dense) d->dense_mask |= 1u << l;
+    d->level_off[l] = (uint32_t)off;
+    off += (dense ? r1 * r1 * r1 : T) * (uint64_t)F;
+    if (off > 0xffffffffull) return set_error("hash table exceeds 2^32 parameters"), NBVH_ERR_UNSUPPORTED;
+  }
+  d->n_table = off;
+  for (int a = 0; a < 3; ++a) d->scene_lo[a] = c->scene_lo[a];
+  d->inv_side = 1.0f / c->scene_side;
+  d->inv_S = 1.0f / (float)S;
+  uint64_t p = round_up(off, kAlign), wt = 0, nm = 0;
+  for (int k = 0; k <= d->hidden; ++k) {
+    d->fan_in[k] = (k == 0) ? n_in : W;
+    d->fan_out[k] = (k == d->hidden) ? c->n_out : W;
+    d->w_off[k] = p;
+    const uint64_t sz = (uint64_t)d->fan_in[k] * d->fan_out[k];
+    nm += sz;
+    p = round_up(p + sz, kAlign);
+    d->wt_off[k] = wt;
+    const int fo_pad = (k == d->hidden) ? 32 : d->fan_out[k];
+    wt = round_up(wt + (uint64_t)d->fan_in[k] * fo_pad, kAlign);
+  }
+  d->n_mlp = nm;
+  d->n_params = p;
+  d->n_wt = wt;
+  return NBVH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// N-BVH over the leaves: median split of leaf centroids on the widest axis
+// (ties by leaf id); inner boxes are exact min/max unions.
+struct Box {
+  float lo[3], hi[3];
+};
+
+static Box unite(const Box& a, const Box& b) {
+  Box r;
+  for (int k = 0; k < 3; ++k) {
+    r.lo[k] = std::min(a.lo[k], b.lo[k]);
+    r.hi[k] = std::max(a.hi[k], b.hi[k]);
+  }
+  return r;
+}
+
+struct Builder {
+  const Box* leaves;
+  std::vector<Node> nodes;
+  int max_depth = 0;
+
+  // returns (child code, box) for the subset idx[b, e)
+  int32_t build(std::vector<uint32_t>& idx, size_t b, size_t e, Box& box, int depth) {
+    if (e - b == 1) {
+      box = leaves[idx[b]];
+      return ~(int32_t)idx[b];
+    }
+    max_depth = std::max(max_depth, depth + 1);
+    float clo[3], chi[3];
+    for (int k = 0; k < 3; ++k) {
+      clo[k] = INFINITY;
+      chi[k] = -INFINITY;
+    }
+    for (size_t i = b; i < e; ++i) {
+      const Box& l = leaves[idx[i]];
+      for (int k = 0; k < 3; ++k) {
+        const float cc = 0.5f * (l.lo[k] + l.hi[k]);
+        clo[k] = std::min(clo[k], cc);
+        chi[k] = std::max(chi[k], cc);
+      }
+    }
+    int axis = 0;
+    for (int k = 1; k < 3; ++k)
+      if (chi[k] - clo[k] > chi[axis] - clo[axis]) axis = k;
+    std::sort(idx.begin() + b, idx.begin() + e, [&](uint32_t x, uint32_t y) {
+      const float cx = 0.5f * (leaves[x].lo[axis] + leaves[x].hi[axis]);
+      const float cy = 0.5f * (leaves[y].lo[axis] + leaves[y].hi[axis]);
+      return cx < cy || (cx == cy && x < y);
+    });
+    const size_t mid = b + (e - b) / 2;
+    const int32_t me = (int32_t)nodes.size();
+    nodes.emplace_back();
+    Box b0, b1;
+    const int32_t c0 = build(idx, b, mid, b0, depth + 1);
+    const int32_t c1 = build(idx, mid, e, b1, depth + 1);
+    Node& n = nodes[me];
+    memset(&n, 0, sizeof(n));
+    for (int k = 0; k < 3; ++k) {
+      n.lo0[k] = b0.lo[k];
+      n.hi0[k] = b0.hi[k];
+      n.lo1[k] = b1.lo[k];
+      n.hi1[k] = b1.hi[k];
+    }
+    n.c0 = c0;
+    n.c1 = c1;
+    box = unite(b0, b1);
+    return me;
+  }
+};
+
+static nbvh_status require_bound(const nbvh_ctx* ctx) {
+  if (!ctx) return set_error("ctx is NULL"), NBVH_ERR_INVALID_ARG;
+  if (!ctx->bound) return set_error("parameters not bound (nbvh_bind_params)"), NBVH_ERR_NOT_BOUND;
+  return NBVH_OK;
+}
+
+static LaunchCtx make_launch(const nbvh_ctx* ctx, void* stream) {
+  LaunchCtx L;
+  memset(&L, 0, sizeof(L));
+  L.stream = (hipStream_t)stream;
+  L.nodes = ctx->nodes;
+  L.state = (DevState*)ctx->p.state_dev;
+  L.cfg = ctx->dev;
+  L.precision = ctx->cfg.precision == NBVH_FP8 ? NBVH_BF16 : ctx->cfg.precision;
+  L.params = ctx->p.params_dev;
+  L.params_lp = ctx->p.params_lp_dev;
+  L.adam_m = ctx->p.adam_m_dev;
+  L.adam_v = ctx->p.adam_v_dev;
+  L.grad = ctx->p.grad_dev;
+  L.aux = ctx->p.aux_dev;
+  L.n_cu = ctx->n_cu;
+  L.w_hit = ctx->cfg.w_hit;
+  L.w_t = ctx->cfg.w_t;
+  L.w_normal = ctx->cfg.w_normal;
+  L.w_albedo = ctx->cfg.w_albedo;
+  L.lr = ctx->cfg.lr;
+  L.beta1 = ctx->cfg.beta1;
+  L.beta2 = ctx->cfg.beta2;
+  L.eps = ctx->cfg.eps;
+  L.loss_scale = ctx->cfg.loss_scale;
+  return L;
+}
+
+// query workspace carve-up
+struct QueryLayout {
+  size_t offsets, counts, active, sums, misc, segs, total;
+};
+
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static QueryLayout query_layout(uint64_t n_rays, uint64_t cap) {
+  QueryLayout Q;
+  size_t off = 0;
+  Q.offsets = off;
+  off = a256(off + (n_rays + 1) * 4);
+  Q.counts = off;
+  off = a256(off + n_rays * 4);
+  Q.active = off;
+  off = a256(off + n_rays * 4);
+  Q.sums = off;
+  off = a256(off + (n_rays / 1024 + 2) * 4);
+  Q.misc = off;
+  off = a256(off + 16 * 4);
+  Q.segs = off;
+  off = a256(off + cap * sizeof(nbvh_segment));
+  Q.total = off;
+  return Q;
+}
+
+}  // namespace nbvh
+
+using namespace nbvh;
+
+extern "C" {
+
+const char* nbvh_last_error(void) { return g_err; }
+
+const char* nbvh_version(void) { return "nbvh-gfx950 0.1"; }
+
+nbvh_status nbvh_param_count(const nbvh_config* cfg, uint64_t* n_table, uint64_t* n_mlp) {
+  DevCfg d;
+  nbvh_status s = make_devcfg(cfg, &d);
+  if (s != NBVH_OK) return s;
+  if (n_table) *n_table = d.n_table;
+  if (n_mlp) *n_mlp = d.n_mlp;
+  return NBVH_OK;
+}
+
+nbvh_status nbvh_param_layout(const nbvh_config* cfg, uint64_t* offsets) {
+  DevCfg d;
+  nbvh_status s = make_devcfg(cfg, &d);
+  if (s != NBVH_OK) return s;
+  if (!offsets) return set_error("offsets is NULL"), NBVH_ERR_INVALID_ARG;
+  offsets[0] = 0;
+  for (int k = 0; k <= d.hidden; ++k) offsets[1 + k] = d.w_off[k];
+  offsets[d.hidden + 2] = d.n_params;
+  return NBVH_OK;
+}
+
+size_t nbvh_aux_bytes(const nbvh_config* cfg) {
+  DevCfg d;
+  if (make_devcfg(cfg, &d) != NBVH_OK) return 0;
+  return (size_t)d.n_wt * 6;
+}
+
+size_t nbvh_nodes_bytes(uint32_t n_leaves) { return (size_t)(n_leaves > 1 ? n_leaves - 1 : 1) * sizeof(Node); }
+
+size_t nbvh_state_bytes(void) { return sizeof(DevState); }
+
+nbvh_status nbvh_build(const nbvh_config* cfg, const float* leaf_boxes_host, uint32_t n_leaves, void* nodes_dev,
+                       size_t nodes_bytes, void* stream, nbvh_ctx** out) {
+  if (!out) return set_error("out is NULL"), NBVH_ERR_INVALID_ARG;
+  *out = nullptr;
+  DevCfg d;
+  nbvh_status s = make_devcfg(cfg, &d);
+  if (s != NBVH_OK) return s;
+  if (!leaf_boxes_host || n_leaves == 0) return set_error("no leaves"), NBVH_ERR_INVALID_ARG;
+  if (n_leaves > (1u << 30)) return set_error("too many leaves"), NBVH_ERR_UNSUPPORTED;
+  if (!nodes_dev) return set_error("nodes_dev is NULL"), NBVH_ERR_INVALID_ARG;
+  if (nodes_bytes < nbvh_nodes_bytes(n_leaves))
+    return set_error("nodes buffer too small: need %zu", nbvh_nodes_bytes(n_leaves)), NBVH_ERR_CAPACITY;
+  const Box* boxes = (const Box*)leaf_boxes_host;
+  for (uint32_t i = 0; i < n_leaves; ++i)
+    for (int k = 0; k < 3; ++k)
+      if (!(boxes[i].lo[k] <= boxes[i].hi[k]) || !std::isfinite(boxes[i].lo[k]) || !std::isfinite(boxes[i].hi[k]))
+        return set_error("leaf %u has an invalid box", i), NBVH_ERR_INVALID_ARG;
+  Builder B;
+  B.leaves = boxes;
+  std::vector<Node> host;
+  if (n_leaves == 1) {
+    Node n;
+    memset(&n, 0, sizeof(n));
+    for (int k = 0; k < 3; ++k) {
+      n.lo0[k] = boxes[0].lo[k];
+      n.hi0[k] = boxes[0].hi[k];
+    }
+    n.c0 = ~0;
+    n.c1 = kEmptyChild;
+    host.push_back(n);
+  } else {
+    std::vector<uint32_t> idx(n_leaves);
+    std::iota(idx.begin(), idx.end(), 0u);
+    Box root;
+    B.nodes.reserve(n_leaves);
+    B.build(idx, 0, n_leaves, root, 0);
+    if (B.max_depth >= kMaxDepth) return set_error("tree depth %d too large", B.max_depth), NBVH_ERR_UNSUPPORTED;
+    host.swap(B.nodes);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (hipMemcpyAsync(nodes_dev, host.data(), host.size() * sizeof(Node), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    set_error("copying nodes: %s", hipGetErrorString(hipGetLastError()));
+    return NBVH_ERR_HIP;
+  }
+  nbvh_ctx* ctx = new nbvh_ctx;
+  memset(ctx, 0, sizeof(*ctx));
+  ctx->cfg = *cfg;
+  ctx->dev = d;
+  ctx->n_leaves = n_leaves;
+  ctx->nodes = (Node*)nodes_dev;
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  ctx->n_cu = (hipGetDeviceProperties(&prop, dev) == hipSuccess) ? prop.multiProcessorCount : 256;
+  if (ctx->n_cu <= 0) ctx->n_cu = 256;
+  *out = ctx;
+  return NBVH_OK;
+}
+
+nbvh_status nbvh_bind_params(nbvh_ctx* ctx, const nbvh_params* p) {
+  if (!ctx || !p) return set_error("ctx or params NULL"), NBVH_ERR_INVALID_ARG;
+  if (!p->params_dev || !p->adam_m_dev || !p->adam_v_dev || !p->grad_dev || !p->state_dev || !p->aux_dev)
+    return set_error("a parameter buffer is NULL"), NBVH_ERR_INVALID_ARG;
+  if (ctx->cfg.precision != NBVH_FP32 && !p->params_lp_dev)
+    return set_error("params_lp_dev is required for BF16/FP8 precision"), NBVH_ERR_INVALID_ARG;
+  if (((uintptr_t)p->params_dev | (uintptr_t)p->params_lp_dev | (uintptr_t)p->aux_dev) & 15)
+    return set_error("parameter buffers must be 16-byte aligned"), NBVH_ERR_INVALID_ARG;
+  ctx->p = *p;
+  ctx->bound = true;
+  return NBVH_OK;
+}
+
+nbvh_status nbvh_reset_optimizer(nbvh_ctx* ctx, void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  LaunchCtx L = make_launch(ctx, stream);
+  const uint64_t n = ctx->dev.n_params;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096);
+  k_zero_f32<<<grid, 256, 0, L.stream>>>(L.adam_m, n);
+  k_zero_f32<<<grid, 256, 0, L.stream>>>(L.adam_v, n);
+  k_zero_f32<<<grid, 256, 0, L.stream>>>(L.grad, n);
+  k_zero_f32<<<grid, 256, 0, L.stream>>>((float*)L.aux, (ctx->dev.n_wt * 6 + 3) / 4);
+  return launch_optimizer(L, true, true);
+}
+
+nbvh_status nbvh_sync_shadow(nbvh_ctx* ctx, void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  LaunchCtx L = make_launch(ctx, stream);
+  return launch_optimizer(L, false, true);
+}
+
+size_t nbvh_workspace_bytes(const nbvh_ctx* ctx, uint64_t max_rays, uint64_t max_segments, uint64_t max_batch) {
+  if (!ctx) return 0;
+  size_t q = query_layout(max_rays, max_segments).total;
+  const int prec = ctx->cfg.precision == NBVH_FP8 ? NBVH_BF16 : ctx->cfg.precision;
+  size_t t = train_ws_bytes(ctx->dev, prec, max_batch, ctx->n_cu);
+  size_t l = a256((max_batch / 256 + 2) * 16);
+  return std::max(q, std::max(t, l));
+}
+
+nbvh_status nbvh_traverse(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, uint32_t* seg_offsets,
+                          nbvh_segment* segs, uint64_t seg_capacity, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return set_error("ctx is NULL"), NBVH_ERR_INVALID_ARG;
+  if (!ctx->p.state_dev) return set_error("state buffer not bound"), NBVH_ERR_NOT_BOUND;
+  if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
+  if ((n_rays && !rays) || !seg_offsets || (seg_capacity && !segs) || !ws)
+    return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  const QueryLayout Q = query_layout(n_rays, 0);
+  if (ws_bytes < Q.segs) return set_error("workspace too small: need %zu", Q.segs), NBVH_ERR_CAPACITY;
+  LaunchCtx L = make_launch(ctx, stream);
+  char* w = (char*)ws;
+  uint32_t* misc = (uint32_t*)(w + Q.misc);
+  return launch_traverse(L, rays, (uint32_t)n_rays, seg_offsets, segs, seg_capacity, nullptr, nullptr, nullptr,
+                         (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 2);
+}
+
+nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbvh_hit* hits, uint64_t seg_capacity,
+                       void* ws, size_t ws_bytes, void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
+  if ((n_rays && (!rays || !hits)) || !ws) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  if (seg_capacity > 0xffffffffull) seg_capacity = 0xffffffffull;
+  const QueryLayout Q = query_layout(n_rays, seg_capacity);
+  if (ws_bytes < Q.total) return set_error("workspace too small: need %zu, got %zu", Q.total, ws_bytes), NBVH_ERR_CAPACITY;
+  if (n_rays == 0) return NBVH_OK;
+  LaunchCtx L = make_launch(ctx, stream);
+  char* w = (char*)ws;
+  uint32_t* offsets = (uint32_t*)(w + Q.offsets);
+  uint32_t* misc = (uint32_t*)(w + Q.misc);
+  nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
+  s = launch_traverse(L, rays, (uint32_t)n_rays, offsets, segs, seg_capacity, hits, (uint32_t*)(w + Q.active), misc + 0,
+                      (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 2);
+  if (s != NBVH_OK) return s;
+  return launch_query_eval(L, rays, offsets, segs, (const uint32_t*)(w + Q.active), misc + 0, misc + 1, hits,
+                           (uint32_t)n_rays, seg_capacity);
+}
+
+nbvh_status nbvh_query_segments(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, const uint32_t* seg_offsets,
+                                const nbvh_segment* segs, nbvh_hit* hits, void* ws, size_t ws_bytes, void* stream) {
+  (void)ctx;
+  (void)rays;
+  (void)n_rays;
+  (void)seg_offsets;
+  (void)segs;
+  (void)hits;
+  (void)ws;
+  (void)ws_bytes;
+  (void)stream;
+  set_error("nbvh_query_segments is not implemented in this version");
+  return NBVH_ERR_UNSUPPORTED;
+}
+
+nbvh_status nbvh_encode(nbvh_ctx* ctx, const nbvh_probe* probes, uint64_t n, float* u, void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  if (n && (!probes || !u)) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  if (n > 0x7fffffffull) return set_error("batch too large"), NBVH_ERR_UNSUPPORTED;
+  return launch_encode(make_launch(ctx, stream), probes, (uint32_t)n, u);
+}
+
+nbvh_status nbvh_forward(nbvh_ctx* ctx, const nbvh_probe* probes, uint64_t n, float* z, void* ws, size_t ws_bytes,
+                         void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  if (n && (!probes || !z)) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  if (n > 0x7fffffffull) return set_error("batch too large"), NBVH_ERR_UNSUPPORTED;
+  return launch_forward(make_launch(ctx, stream), probes, (uint32_t)n, z);
+}
+
+nbvh_status nbvh_backward(nbvh_ctx* ctx, const nbvh_probe* probes, uint64_t n, const float* dz, void* ws,
+                          size_t ws_bytes, void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  if (ctx->cfg.precision == NBVH_FP8) return set_error("FP8 is an inference precision"), NBVH_ERR_UNSUPPORTED;
+  if (n && (!probes || !dz || !ws)) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  if (n > 0x7fffffffull) return set_error("batch too large"), NBVH_ERR_UNSUPPORTED;
+  return launch_train_fwd_bwd(make_launch(ctx, stream), probes, nullptr, dz, (uint32_t)n, nullptr, ws, ws_bytes, false);
+}
+
+nbvh_status nbvh_optimizer_step(nbvh_ctx* ctx, void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  return launch_optimizer(make_launch(ctx, stream), false, false);
+}
+
+nbvh_status nbvh_train_step(nbvh_ctx* ctx, const nbvh_probe* probes, const nbvh_label* labels, uint64_t n,
+                            float* loss_dev, void* ws, size_t ws_bytes, void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  if (ctx->cfg.precision == NBVH_FP8) return set_error("FP8 is an inference precision"), NBVH_ERR_UNSUPPORTED;
+  if (n == 0) return set_error("empty batch"), NBVH_ERR_INVALID_ARG;
+  if (!probes || !labels || !ws) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  if (n > 0x7fffffffull) return set_error("batch too large"), NBVH_ERR_UNSUPPORTED;
+  LaunchCtx L = make_launch(ctx, stream);
+  s = launch_train_fwd_bwd(L, probes, labels, nullptr, (uint32_t)n, loss_dev, ws, ws_bytes, true);
+  if (s != NBVH_OK) return s;
+  return launch_optimizer(L, false, false);
+}
+
+nbvh_status nbvh_loss(nbvh_ctx* ctx, const float* z, const nbvh_label* labels, uint64_t n, float* loss_dev,
+                      float* dz, void* ws, size_t ws_bytes, void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  if (n == 0) return set_error("empty batch"), NBVH_ERR_INVALID_ARG;
+  if (!z || !labels || !ws) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  if (n > 0x7fffffffull) return set_error("batch too large"), NBVH_ERR_UNSUPPORTED;
+  return launch_loss(make_launch(ctx, stream), z, labels, (uint32_t)n, loss_dev, dz, ws, ws_bytes);
+}
+
+nbvh_status nbvh_read_state(nbvh_ctx* ctx, nbvh_state_host* out, void* stream) {
+  if (!ctx || !out) return set_error("NULL argument"), NBVH_ERR_INVALID_ARG;
+  if (!ctx->p.state_dev) return set_error("state buffer not bound"), NBVH_ERR_NOT_BOUND;
+  DevState st;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(&st, ctx->p.state_dev, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    set_error("reading state: %s", hipGetErrorString(hipGetLastError()));
+    return NBVH_ERR_HIP;
+  }
+  out->step = st.step;
+  out->skipped = st.skipped;
+  out->loss_scale = st.loss_scale;
+  out->flags = st.flags;
+  for (int i = 0; i < 4; ++i) out->last_loss[i] = st.last_loss[i];
+  out->last_n_segments = st.last_n_segments;
+  return NBVH_OK;
+}
+
+__global__ void k_clear_flags(DevState* s) {
+  if (threadIdx.x == 0) s->flags = 0u;
+}
+
+nbvh_status nbvh_clear_flags(nbvh_ctx* ctx, void* stream) {
+  if (!ctx || !ctx->p.state_dev) return set_error("state buffer not bound"), NBVH_ERR_NOT_BOUND;
+  k_clear_flags<<<1, 64, 0, (hipStream_t)stream>>>((DevState*)ctx->p.state_dev);
+  return check_launch("clear_flags");
+}
+
+void nbvh_destroy(nbvh_ctx* ctx) { delete ctx; }
+
+}  // extern "C"

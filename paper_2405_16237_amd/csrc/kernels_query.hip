@@ -1,0 +1,280 @@
+// Neural ray query evaluation (Sec. 5; Fig. "neural ray query pipeline").
+//
+// One persistent kernel fuses sampling + hash-grid encoding, the MLP and the
+// front-to-back resolve. Each workgroup owns 64 ray slots (wave 0, lane =
+// slot). Per iteration every live slot evaluates its ray's current segment:
+// all four waves gather the features of the 64 segments into an LDS tile
+// (lanes = slots, so a wave's 64 lookups share one level and neighbouring
+// rays share cache lines), the tile goes through the MLP on the matrix cores,
+// and wave 0 updates each ray's best hit. A ray moves on to its next segment
+// only while that segment starts before its best t; otherwise its hit record
+// is written and the slot takes the next ray from the queue of rays with at
+// least one segment. Workgroups exit when the queue is drained and their
+// slots are empty.
+#include "launch.h"
+#include "mlp_tile.h"
+#include "encode_tile.h"
+
+namespace nbvh {
+
+constexpr int kQM = 64;  // slots per workgroup
+
+template <typename AT>
+__host__ __device__ inline size_t query_lds_bytes(int n_in, int width) {
+  const int ld0 = (n_in > width ? n_in : width) + Pad<AT>::v;
+  const int ld1 = width + Pad<AT>::v;
+  return (size_t)kQM * (ld0 + ld1) * sizeof(AT) + (size_t)kQM * kOutPad * 4 + (size_t)kQM * 32 + kQM * 4 + 16;
+}
+
+template <typename AT, int F, bool LP>
+__global__ __launch_bounds__(256) void k_query_eval(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
+                                                    const nbvh_ray* __restrict__ rays,
+                                                    const uint32_t* __restrict__ offsets,
+                                                    const nbvh_segment* __restrict__ segs,
+                                                    const uint32_t* __restrict__ active,
+                                                    const uint32_t* __restrict__ n_active_p,
+                                                    uint32_t* __restrict__ counter, nbvh_hit* __restrict__ hits,
+                                                    const uint32_t* __restrict__ total_segs, uint64_t capacity) {
+  if ((uint64_t)*total_segs > capacity) return;  // segment queue overflowed: flagged, nothing to read
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ld0 = (c.n_in > c.width ? c.n_in : c.width) + Pad<AT>::v;
+  const int ld1 = c.width + Pad<AT>::v;
+  AT* act0 = (AT*)smem;
+  AT* act1 = act0 + (size_t)kQM * ld0;
+  float* z = (float*)(act1 + (size_t)kQM * ld1);
+  float4* sA = (float4*)(z + kQM * kOutPad);
+  float4* sB = sA + kQM;
+  int* s_valid = (int*)(sB + kQM);
+  int* s_any = s_valid + kQM;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t n_active = *n_active_p;
+
+  // slot state of wave 0 (lane = slot)
+  uint32_t ray = NBVH_MISS, cur = 0, end = 0, leaf = 0, best_leaf = NBVH_MISS;
+  float t0 = 0.f, t1 = 0.f, best_t = INFINITY;
+  float bn[3] = {0.f, 0.f, 0.f}, ba[3] = {0.f, 0.f, 0.f};
+  bool exhausted = false;
+
+  while (true) {
+    if (wave == 0) {
+      const bool is_free = (ray == NBVH_MISS);
+      if (!exhausted) {
+        const uint64_t mask = __ballot(is_free);
+        const uint32_t nfree = (uint32_t)__popcll(mask);
+        if (nfree) {
+          const int leader = __ffsll((unsigned long long)mask) - 1;
+          uint32_t base = 0;
+          if (lane == leader) base = atomicAdd(counter, nfree);
+          base = __shfl(base, leader);
+          if (is_free) {
+            const uint32_t idx = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            if (idx < n_active) {
+              ray = active[idx];
+              cur = offsets[ray];
+              end = offsets[ray + 1];
+              best_t = INFINITY;
+              best_leaf = NBVH_MISS;
+              const float4* rp = (const float4*)(rays + ray);
+              const float4 ra = rp[0], rb = rp[1];
+              const nbvh_segment sg = segs[cur];
+              t0 = sg.t0;
+              t1 = sg.t1;
+              leaf = sg.leaf;
+              sA[lane] = make_float4(ra.x, ra.y, ra.z, t0);
+              sB[lane] = make_float4(rb.x, rb.y, rb.z, t1);
+            }
+          }
+          if (base + nfree >= n_active) exhausted = true;
+        }
+      }
+      s_valid[lane] = (ray != NBVH_MISS) ? 1 : 0;
+      const uint64_t live = __ballot(ray != NBVH_MISS);
+      if (lane == 0) *s_any = live ? 1 : 0;
+    }
+    __syncthreads();
+    if (*s_any == 0) break;
+
+    encode_tile<AT, F, LP, 4>(c, table, sA, sB, s_valid, act0, ld0, kQM);
+    __syncthreads();
+    mlp_forward_tile<kQM, 4, AT>(c, W, act0, ld0, act1, ld1, z, kOutPad);
+
+    if (wave == 0 && ray != NBVH_MISS) {
+      const float* zr = z + lane * kOutPad;
+      if (zr[0] > 0.0f) {
+        const float t = t0 + sigmoidf_(zr[1]) * (t1 - t0);
+        if (t < best_t) {
+          best_t = t;
+          best_leaf = leaf;
+          bn[0] = zr[2];
+          bn[1] = zr[3];
+          bn[2] = zr[4];
+          if (c.n_out >= 8) {
+            ba[0] = sigmoidf_(zr[5]);
+            ba[1] = sigmoidf_(zr[6]);
+            ba[2] = sigmoidf_(zr[7]);
+          }
+        }
+      }
+      ++cur;
+      bool more = false;
+      if (cur < end) {
+        const nbvh_segment sg = segs[cur];
+        if (sg.t0 < best_t) {
+          more = true;
+          t0 = sg.t0;
+          t1 = sg.t1;
+          leaf = sg.leaf;
+          sA[lane].w = t0;
+          sB[lane].w = t1;
+        }
+      }
+      if (!more) {
+        float4* h = (float4*)(hits + ray);
+        if (best_leaf == NBVH_MISS) {
+          h[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+          h[1] = make_float4(0.f, 0.f, 0.f, __uint_as_float(NBVH_MISS));
+        } else {
+          h[0] = make_float4(best_t, bn[0], bn[1], bn[2]);
+          h[1] = make_float4(ba[0], ba[1], ba[2], __uint_as_float(best_leaf));
+        }
+        ray = NBVH_MISS;
+        bn[0] = bn[1] = bn[2] = 0.f;
+        ba[0] = ba[1] = ba[2] = 0.f;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Forward of probe segments: tile of 64 probes per workgroup, z -> global.
+template <typename AT, int F, bool LP>
+__global__ __launch_bounds__(256) void k_forward(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
+                                                 const nbvh_probe* __restrict__ probes, uint32_t n,
+                                                 float* __restrict__ zout) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ld0 = (c.n_in > c.width ? c.n_in : c.width) + Pad<AT>::v;
+  const int ld1 = c.width + Pad<AT>::v;
+  AT* act0 = (AT*)smem;
+  AT* act1 = act0 + (size_t)kQM * ld0;
+  float* z = (float*)(act1 + (size_t)kQM * ld1);
+  float4* sA = (float4*)(z + kQM * kOutPad);
+  float4* sB = sA + kQM;
+  int* s_valid = (int*)(sB + kQM);
+  const uint32_t base = blockIdx.x * kQM;
+  if (threadIdx.x < kQM) {
+    const uint32_t i = base + threadIdx.x;
+    const bool v = i < n;
+    const float4* p = (const float4*)(probes + (v ? i : 0));
+    sA[threadIdx.x] = p[0];
+    sB[threadIdx.x] = p[1];
+    s_valid[threadIdx.x] = v ? 1 : 0;
+  }
+  __syncthreads();
+  encode_tile<AT, F, LP, 4>(c, table, sA, sB, s_valid, act0, ld0, kQM);
+  __syncthreads();
+  mlp_forward_tile<kQM, 4, AT>(c, W, act0, ld0, act1, ld1, z, kOutPad);
+  for (int e = threadIdx.x; e < kQM * c.n_out; e += blockDim.x) {
+    const int m = e / c.n_out, o = e - m * c.n_out;
+    if (base + m < n) zout[(size_t)(base + m) * c.n_out + o] = z[m * kOutPad + o];
+  }
+}
+
+// Encoding only: thread per (probe, sample, level), FP32 output.
+template <int F, bool LP>
+__global__ __launch_bounds__(256) void k_encode(DevCfg c, const void* __restrict__ table,
+                                                const nbvh_probe* __restrict__ probes, uint32_t n,
+                                                float* __restrict__ u) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int SL = c.n_samples * c.n_levels;
+  if (t >= (uint64_t)n * SL) return;
+  const uint32_t i = (uint32_t)(t / SL);
+  const int sl = (int)(t - (uint64_t)i * SL);
+  const int s = sl / c.n_levels, l = sl - s * c.n_levels;
+  const float4* p = (const float4*)(probes + i);
+  const float4 a = p[0], b = p[1];
+  const float o[3] = {a.x, a.y, a.z}, d[3] = {b.x, b.y, b.z};
+  float x[3], v[F];
+  sample_position(c, o, d, a.w, b.w, s, x);
+  interp_level<F, LP>(c, table, l, x, v);
+#pragma unroll
+  for (int f = 0; f < F; ++f) u[(size_t)i * c.n_in + s * c.n_levels * F + l * F + f] = v[f];
+}
+
+// ---------------------------------------------------------------------------
+template <typename K>
+static void set_lds(K kernel, size_t bytes) {
+  hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename AT, int F, bool LP>
+static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
+                                const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
+                                uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity) {
+  const DevCfg& c = L.cfg;
+  const size_t lds = query_lds_bytes<AT>(c.n_in, c.width);
+  auto kern = k_query_eval<AT, F, LP>;
+  set_lds(kern, lds);
+  int per_cu = (int)(160 * 1024 / lds);
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 4) per_cu = 4;
+  uint32_t grid = (uint32_t)L.n_cu * per_cu;
+  const uint32_t need = (n_rays_bound + kQM - 1) / kQM;
+  if (need < grid) grid = need > 0 ? need : 1;
+  k_zero_u32<<<1, 64, 0, L.stream>>>(counter, 1);
+  const AT* W = (sizeof(AT) == 2) ? (const AT*)L.params_lp : (const AT*)L.params;
+  const void* table = LP ? (const void*)L.params_lp : (const void*)L.params;
+  kern<<<grid, 256, lds, L.stream>>>(c, table, W, rays, offsets, segs, active, n_active, counter, hits,
+                                     offsets + n_rays_bound, capacity);
+  return check_launch("query_eval");
+}
+
+nbvh_status launch_query_eval(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
+                              const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
+                              uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity) {
+  const int F = L.cfg.n_features;
+  if (L.precision == NBVH_FP32) {
+    if (F == 2) return query_eval_t<float, 2, false>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity);
+    return query_eval_t<float, 4, false>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity);
+  }
+  if (F == 2) return query_eval_t<bf16, 2, true>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity);
+  return query_eval_t<bf16, 4, true>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity);
+}
+
+template <typename AT, int F, bool LP>
+static nbvh_status forward_t(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, float* z) {
+  const DevCfg& c = L.cfg;
+  const size_t lds = query_lds_bytes<AT>(c.n_in, c.width);
+  auto kern = k_forward<AT, F, LP>;
+  set_lds(kern, lds);
+  const AT* W = (sizeof(AT) == 2) ? (const AT*)L.params_lp : (const AT*)L.params;
+  const void* table = LP ? (const void*)L.params_lp : (const void*)L.params;
+  if (n == 0) return NBVH_OK;
+  kern<<<(n + kQM - 1) / kQM, 256, lds, L.stream>>>(c, table, W, probes, n, z);
+  return check_launch("forward");
+}
+
+nbvh_status launch_forward(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, float* z) {
+  const int F = L.cfg.n_features;
+  if (L.precision == NBVH_FP32) return F == 2 ? forward_t<float, 2, false>(L, probes, n, z) : forward_t<float, 4, false>(L, probes, n, z);
+  return F == 2 ? forward_t<bf16, 2, true>(L, probes, n, z) : forward_t<bf16, 4, true>(L, probes, n, z);
+}
+
+nbvh_status launch_encode(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, float* u) {
+  const DevCfg& c = L.cfg;
+  const uint64_t total = (uint64_t)n * c.n_samples * c.n_levels;
+  if (total == 0) return NBVH_OK;
+  const uint32_t grid = (uint32_t)((total + 255) / 256);
+  const bool lp = L.precision != NBVH_FP32;
+  const void* table = lp ? (const void*)L.params_lp : (const void*)L.params;
+  if (c.n_features == 2) {
+    if (lp) k_encode<2, true><<<grid, 256, 0, L.stream>>>(c, table, probes, n, u);
+    else k_encode<2, false><<<grid, 256, 0, L.stream>>>(c, table, probes, n, u);
+  } else {
+    if (lp) k_encode<4, true><<<grid, 256, 0, L.stream>>>(c, table, probes, n, u);
+    else k_encode<4, false><<<grid, 256, 0, L.stream>>>(c, table, probes, n, u);
+  }
+  return check_launch("encode");
+}
+
+}  // namespace nbvh

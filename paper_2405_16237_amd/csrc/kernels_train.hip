@@ -1,0 +1,649 @@
+// Training step (Sec. 4: query the model on probe segments, compare with the
+// ground truth, back-propagate into the MLP weights and the hash-table
+// features; Sec. 5.2: losses; Sec. 6: Adam, learning rate 0.01).
+//
+//  k_train_tile   per 64 probes: encode -> MLP forward (activations in LDS,
+//                 ReLU masks as bits) -> loss and dL/dz (times the loss
+//                 scale) -> dgrad back through the layers on the matrix
+//                 cores. It stores the weight-gradient operands h_k^T and
+//                 g_k^T (feature-major, batch-minor) and dL/du^T.
+//  k_wgrad        dL/dW_k = sum_b g_k[b] h_k[b]^T as split-K MFMA GEMMs into
+//                 per-split partials; k_wgrad_reduce adds them into grad in
+//                 a fixed order.
+//  k_scatter      recomputes every sample's cell corners and weights (no
+//                 stored encodings) and adds w * dL/du into the table
+//                 gradient with hardware FP32 atomics.
+//  k_check_finite / k_adam / k_adam_finalize   dense Adam with loss-scale
+//                 removal and non-finite skip; writes the BF16 shadow and the
+//                 transposed weight copies the dgrad reads.
+#include "launch.h"
+#include "mlp_tile.h"
+#include "encode_tile.h"
+
+namespace nbvh {
+
+constexpr int kTM = 64;
+constexpr int kTWaves = 4;
+constexpr int kGPad = 32;  // gradient rows of the output layer padded to 32
+
+__host__ __device__ inline int fan_out_pad(const DevCfg& c, int k) {
+  return k == c.hidden ? kGPad : c.fan_out[k];
+}
+
+// workspace carve-up (offsets in bytes)
+struct TrainLayout {
+  size_t hT[kMaxLayers], gT[kMaxLayers];
+  size_t duT, wpart, loss_part, total;
+  int nsplit;
+  uint32_t n_tiles;
+};
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_batch, int n_cu) {
+  TrainLayout T;
+  const size_t es = precision == NBVH_FP32 ? 4 : 2;
+  const uint64_t B = (max_batch + kTM - 1) / kTM * kTM;
+  size_t off = 0;
+  for (int k = 0; k <= c.hidden; ++k) {
+    T.hT[k] = off;
+    off = align256(off + (size_t)c.fan_in[k] * B * es);
+  }
+  for (int k = 0; k <= c.hidden; ++k) {
+    T.gT[k] = off;
+    off = align256(off + (size_t)fan_out_pad(c, k) * B * es);
+  }
+  T.duT = off;
+  off = align256(off + (size_t)c.n_in * B * 4);
+  T.nsplit = 32;
+  (void)n_cu;
+  T.wpart = off;
+  off = align256(off + (size_t)T.nsplit * (c.n_params - c.w_off[0]) * 4);
+  T.n_tiles = (uint32_t)(B / kTM);
+  T.loss_part = off;
+  off = align256(off + (size_t)T.n_tiles * 4 * 4);
+  T.total = off;
+  return T;
+}
+
+size_t train_ws_bytes(const DevCfg& c, int precision, uint64_t max_batch, int n_cu) {
+  if (max_batch == 0) return 0;
+  return train_layout(c, precision, max_batch, n_cu).total;
+}
+
+template <typename AT>
+__host__ __device__ inline size_t train_lds_bytes(const DevCfg& c) {
+  const int ld0 = (c.n_in > c.width ? c.n_in : c.width) + Pad<AT>::v;
+  const int ld1 = c.width + Pad<AT>::v;
+  const int ldg = kGPad + Pad<AT>::v;
+  const size_t words = (size_t)c.hidden * kTM * (c.width / 32);
+  return (size_t)kTM * (ld0 + ld1 + ldg) * sizeof(AT) + (size_t)kTM * kOutPad * 4 + words * 4 + (size_t)kTM * 32 +
+         kTM * 4 + 64;
+}
+
+struct TrainPtrs {
+  void* hT[kMaxLayers];
+  void* gT[kMaxLayers];
+  float* duT;
+  float* loss_part;
+  uint64_t ldb;  // batch stride of the feature-major buffers
+};
+
+template <typename AT>
+__device__ inline void put(AT* p, float v) {
+  p[0] = (AT)v;
+}
+
+__device__ inline float bce_logits(float z, float h) {
+  return fmaxf(z, 0.0f) - z * h + log1pf(__expf(-fabsf(z)));
+}
+__device__ inline float sgnf(float v) { return (float)((v > 0.0f) - (v < 0.0f)); }
+
+template <typename AT, int F, bool LP, bool WITH_LABELS>
+__global__ __launch_bounds__(256) void k_train_tile(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
+                                                    const AT* __restrict__ WT, const nbvh_probe* __restrict__ probes,
+                                                    const nbvh_label* __restrict__ labels,
+                                                    const float* __restrict__ dz_in, uint32_t n, TrainPtrs P,
+                                                    DevState* __restrict__ state, float w_hit, float w_t,
+                                                    float w_normal) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ld0 = (c.n_in > c.width ? c.n_in : c.width) + Pad<AT>::v;
+  const int ld1 = c.width + Pad<AT>::v;
+  const int ldg = kGPad + Pad<AT>::v;
+  const int mw = c.width / 32;  // mask words per row and layer
+  AT* act0 = (AT*)smem;
+  AT* act1 = act0 + (size_t)kTM * ld0;
+  AT* gz = act1 + (size_t)kTM * ld1;
+  float* z = (float*)(gz + (size_t)kTM * ldg);
+  uint32_t* masks = (uint32_t*)(z + kTM * kOutPad);
+  float4* sA = (float4*)(masks + (size_t)c.hidden * kTM * mw);
+  float4* sB = sA + kTM;
+  int* s_valid = (int*)(sB + kTM);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t base = blockIdx.x * kTM;
+  const uint64_t ldb = P.ldb;
+  if (tid < kTM) {
+    const uint32_t i = base + tid;
+    const bool v = i < n;
+    const float4* p = (const float4*)(probes + (v ? i : 0));
+    sA[tid] = p[0];
+    sB[tid] = p[1];
+    s_valid[tid] = v ? 1 : 0;
+  }
+  for (int e = tid; e < c.hidden * kTM * mw; e += blockDim.x) masks[e] = 0u;
+  __syncthreads();
+
+  // 1. encode -> act0, and h_0^T (= u^T) to global
+  encode_tile<AT, F, LP, kTWaves>(c, table, sA, sB, s_valid, act0, ld0, kTM);
+  __syncthreads();
+  {
+    AT* h0 = (AT*)P.hT[0];
+    for (int e = tid; e < kTM * c.n_in; e += blockDim.x) {
+      const int i = e / kTM, m = e - i * kTM;
+      h0[(size_t)i * ldb + base + m] = act0[(size_t)m * ld0 + i];
+    }
+  }
+
+  // 2. forward; hidden outputs -> masks + h_{k+1}^T
+  mlp_forward_tile_keep<kTM, kTWaves, AT>(c, W, act0, ld0, act1, ld1, z, kOutPad,
+                                          [&](int k, int m, int col, f32x4 v) {
+                                            uint32_t bits = 0;
+#pragma unroll
+                                            for (int i = 0; i < 4; ++i) bits |= (v[i] > 0.0f ? 1u : 0u) << i;
+                                            atomicOr(&masks[((size_t)k * kTM + m) * mw + (col >> 5)], bits << (col & 31));
+                                            AT* hk = (AT*)P.hT[k + 1];
+                                            const bool ok = s_valid[m] != 0;
+#pragma unroll
+                                            for (int i = 0; i < 4; ++i)
+                                              put<AT>(hk + (size_t)(col + i) * ldb + base + m, ok ? v[i] : 0.0f);
+                                          });
+
+  // 3. loss and dL/dz (scaled) -> gz (LDS) and g_H^T (global)
+  const float scale = state->loss_scale;
+  const float invB = 1.0f / (float)n;
+  float l_bce = 0.f, l_t = 0.f, l_n = 0.f;
+  if (wave == 0) {
+    const int m = lane;
+    const bool ok = s_valid[m] != 0;
+    float g[kGPad];
+#pragma unroll
+    for (int o = 0; o < kGPad; ++o) g[o] = 0.0f;
+    if (ok) {
+      const float* zr = z + m * kOutPad;
+      if (WITH_LABELS) {
+        const nbvh_label lb = labels[base + m];
+        const float h = lb.hit, tau = lb.tau;
+        const float st = sigmoidf_(zr[1]);
+        l_bce = bce_logits(zr[0], h);
+        l_t = h * fabsf(st - tau);
+        float ln = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ln += fabsf(zr[2 + a] - lb.n[a]);
+        l_n = h * ln * (1.0f / 3.0f);
+        const float sB_ = scale * invB;
+        g[0] = w_hit * (sigmoidf_(zr[0]) - h) * sB_;
+        g[1] = h * w_t * sgnf(st - tau) * st * (1.0f - st) * sB_;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[2 + a] = h * w_normal * sgnf(zr[2 + a] - lb.n[a]) * (1.0f / 3.0f) * sB_;
+      } else {
+        for (int o = 0; o < c.n_out; ++o) g[o] = dz_in[(size_t)(base + m) * c.n_out + o] * scale;
+      }
+      bool fin = true;
+#pragma unroll
+      for (int o = 0; o < kGPad; ++o) fin = fin && isfinite(g[o]);
+      if (!fin) atomicOr(&state->nonfinite_pending, 1u);
+    }
+    AT* gH = (AT*)P.gT[c.hidden];
+#pragma unroll
+    for (int o = 0; o < kGPad; ++o) {
+      gz[(size_t)m * ldg + o] = (AT)g[o];
+      gH[(size_t)o * ldb + base + m] = (AT)g[o];
+    }
+    if (WITH_LABELS) {
+      // wave reduction of the per-probe loss terms
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        l_bce += __shfl_xor(l_bce, off);
+        l_t += __shfl_xor(l_t, off);
+        l_n += __shfl_xor(l_n, off);
+      }
+      if (lane == 0) {
+        P.loss_part[blockIdx.x * 4 + 0] = l_bce;
+        P.loss_part[blockIdx.x * 4 + 1] = l_t;
+        P.loss_part[blockIdx.x * 4 + 2] = l_n;
+        P.loss_part[blockIdx.x * 4 + 3] = 0.f;
+      }
+    }
+  }
+  __syncthreads();
+
+  // 4. dgrad: g_in^T = W_k^T g_k^T, masked by h_k > 0 (k >= 1); k = 0 gives du
+  const AT* gcur = gz;
+  int ldcur = ldg;
+  AT* bufs[2] = {act0, act1};
+  int lds_[2] = {ld0, ld1};
+  int which = 0;
+  for (int k = c.hidden; k >= 0; --k) {
+    const int K = (k == c.hidden) ? Pad<AT>::kstep : c.fan_out[k];
+    const int ldw = fan_out_pad(c, k);
+    const AT* Wt = WT + c.wt_off[k];
+    if (k > 0) {
+      AT* out = bufs[which];
+      const int ldo = lds_[which];
+      AT* gk = (AT*)P.gT[k - 1];
+      gemm_tile<kTM, kTWaves, AT>(gcur, ldcur, K, Wt, ldw, c.fan_in[k], [&](int m, int col, f32x4 v) {
+        const uint32_t word = masks[((size_t)(k - 1) * kTM + m) * mw + (col >> 5)] >> (col & 31);
+        const bool ok = s_valid[m] != 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = (ok && ((word >> i) & 1u)) ? v[i] : 0.0f;
+        store4<AT>(out + (size_t)m * ldo + col, v);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) put<AT>(gk + (size_t)(col + i) * ldb + base + m, v[i]);
+      });
+      __syncthreads();
+      gcur = out;
+      ldcur = ldo;
+      which ^= 1;
+    } else {
+      float* du = P.duT;
+      gemm_tile<kTM, kTWaves, AT>(gcur, ldcur, K, Wt, ldw, c.fan_in[0], [&](int m, int col, f32x4 v) {
+        const bool ok = s_valid[m] != 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) du[(size_t)(col + i) * ldb + base + m] = ok ? v[i] : 0.0f;
+      });
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: per (layer tile 64 x 64, split) one workgroup; wave w owns
+// output rows o0 + 16w .. +15 and 64 columns (4 MFMA tiles).
+struct WTile {
+  int16_t layer, o0, i0, pad;
+};
+struct WTiles {
+  WTile t[160];
+  int n;
+};
+
+template <typename AT>
+__global__ __launch_bounds__(256) void k_wgrad(DevCfg c, WTiles tiles, TrainPtrs P, uint32_t kb, int nsplit,
+                                               float* __restrict__ wpart) {
+  const WTile T = tiles.t[blockIdx.x];
+  const int split = blockIdx.y;
+  const int k = T.layer;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int o0 = T.o0 + 16 * wave;
+  const int fo_pad = fan_out_pad(c, k);
+  if (o0 >= fo_pad) return;
+  const int fi = c.fan_in[k];
+  const uint64_t ldb = P.ldb;
+  const uint32_t chunk = (kb / nsplit + 31) / 32 * 32;
+  const uint32_t b_beg = split * chunk;
+  uint32_t b_end = b_beg + chunk;
+  if (b_end > kb) b_end = kb;
+  const AT* gT = (const AT*)P.gT[k];
+  const AT* hT = (const AT*)P.hT[k];
+  f32x4 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const AT* arow = gT + (size_t)(o0 + r16) * ldb;
+  if constexpr (sizeof(AT) == 2) {
+    for (uint32_t b = b_beg; b < b_end; b += 32) {
+      const bf16x8 a = *(const bf16x8*)(arow + b + 8 * q);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = T.i0 + 16 * j + r16;
+        const bf16x8 bv = (i < fi) ? *(const bf16x8*)(hT + (size_t)i * ldb + b + 8 * q) : zero_bf16x8();
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[j], 0, 0, 0);
+      }
+    }
+  } else {
+    for (uint32_t b = b_beg; b < b_end; b += 16) {
+      const float4 a = *(const float4*)(arow + b + 4 * q);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = T.i0 + 16 * j + r16;
+        const float4 bv = (i < fi) ? *(const float4*)(hT + (size_t)i * ldb + b + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bv.x, acc[j], 0, 0, 0);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bv.y, acc[j], 0, 0, 0);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bv.z, acc[j], 0, 0, 0);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bv.w, acc[j], 0, 0, 0);
+      }
+    }
+  }
+  const uint64_t span = c.n_params - c.w_off[0];
+  float* dst = wpart + (size_t)split * span + (c.w_off[k] - c.w_off[0]);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = T.i0 + 16 * j + r16;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int o = o0 + 4 * q + e;
+      if (o < c.fan_out[k] && i < fi) dst[(size_t)o * fi + i] = acc[j][e];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_wgrad_reduce(DevCfg c, const float* __restrict__ wpart, int nsplit,
+                                                      float* __restrict__ grad, DevState* __restrict__ state) {
+  const uint64_t span = c.n_params - c.w_off[0];
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < span; j += (uint64_t)gridDim.x * blockDim.x) {
+    // inside a layer's block (not alignment padding)?
+    const uint64_t abs_i = c.w_off[0] + j;
+    bool inside = false;
+    for (int k = 0; k <= c.hidden; ++k)
+      if (abs_i >= c.w_off[k] && abs_i < c.w_off[k] + (uint64_t)c.fan_in[k] * c.fan_out[k]) inside = true;
+    if (!inside) continue;
+    float s = 0.f;
+    for (int p = 0; p < nsplit; ++p) s += wpart[(size_t)p * span + j];
+    if (!isfinite(s)) atomicOr(&state->nonfinite_pending, 1u);
+    grad[abs_i] += s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// table-gradient scatter: thread per (probe, sample, level), probes fastest
+template <int F>
+__global__ __launch_bounds__(256) void k_scatter(DevCfg c, const nbvh_probe* __restrict__ probes, uint32_t n,
+                                                 const float* __restrict__ duT, uint64_t ldb, float* __restrict__ grad) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t total = (uint64_t)n * c.n_samples * c.n_levels;
+  if (t >= total) return;
+  const uint32_t sl = (uint32_t)(t / n);
+  const uint32_t p = (uint32_t)(t - (uint64_t)sl * n);
+  const int s = sl / c.n_levels, l = sl - s * c.n_levels;
+  float g[F];
+  bool any = false;
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    g[f] = duT[(size_t)(sl * F + f) * ldb + p];
+    any = any || g[f] != 0.0f;
+  }
+  if (!any) return;
+  const float4* pp = (const float4*)(probes + p);
+  const float4 a = pp[0], b = pp[1];
+  const float o[3] = {a.x, a.y, a.z}, d[3] = {b.x, b.y, b.z};
+  float x[3];
+  sample_position(c, o, d, a.w, b.w, s, x);
+  uint32_t idx[8];
+  float w[8];
+  corners_level(c, l, x, idx, w);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+#pragma unroll
+    for (int f = 0; f < F; ++f) unsafeAtomicAdd(grad + idx[k] + f, w[k] * g[f]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_loss_finalize(const float* __restrict__ part, uint32_t n_tiles, uint32_t n,
+                                                       float w_hit, float w_t, float w_normal, float* __restrict__ out,
+                                                       DevState* __restrict__ state) {
+  __shared__ float sh[3][256];
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  for (uint32_t i = threadIdx.x; i < n_tiles; i += blockDim.x) {
+    s0 += part[i * 4 + 0];
+    s1 += part[i * 4 + 1];
+    s2 += part[i * 4 + 2];
+  }
+  sh[0][threadIdx.x] = s0;
+  sh[1][threadIdx.x] = s1;
+  sh[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int j = 0; j < 3; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float inv = 1.0f / (float)n;
+    const float b = sh[0][0] * inv, t = sh[1][0] * inv, nn = sh[2][0] * inv;
+    const float tot = w_hit * b + w_t * t + w_normal * nn;
+    if (!isfinite(tot)) atomicOr(&state->nonfinite_pending, 1u);
+    state->last_loss[0] = tot;
+    state->last_loss[1] = b;
+    state->last_loss[2] = t;
+    state->last_loss[3] = nn;
+    if (out) {
+      out[0] = tot;
+      out[1] = b;
+      out[2] = t;
+      out[3] = nn;
+    }
+  }
+}
+
+// plain loss / dz kernel (nbvh_loss): thread per probe, partial sums per block
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ z, const nbvh_label* __restrict__ labels,
+                                              uint32_t n, int n_out, float w_hit, float w_t, float w_normal,
+                                              float* __restrict__ dz, float* __restrict__ part) {
+  __shared__ float sh[3][256];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  float lb_ = 0.f, lt = 0.f, ln = 0.f;
+  if (i < n) {
+    const float* zr = z + (size_t)i * n_out;
+    const nbvh_label lb = labels[i];
+    const float h = lb.hit, tau = lb.tau, st = sigmoidf_(zr[1]);
+    lb_ = bce_logits(zr[0], h);
+    lt = h * fabsf(st - tau);
+    float s = 0.f;
+    for (int a = 0; a < 3; ++a) s += fabsf(zr[2 + a] - lb.n[a]);
+    ln = h * s * (1.0f / 3.0f);
+    if (dz) {
+      const float invB = 1.0f / (float)n;
+      float* g = dz + (size_t)i * n_out;
+      for (int o = 0; o < n_out; ++o) g[o] = 0.f;
+      g[0] = w_hit * (sigmoidf_(zr[0]) - h) * invB;
+      g[1] = h * w_t * sgnf(st - tau) * st * (1.0f - st) * invB;
+      for (int a = 0; a < 3; ++a) g[2 + a] = h * w_normal * sgnf(zr[2 + a] - lb.n[a]) * (1.0f / 3.0f) * invB;
+    }
+  }
+  sh[0][threadIdx.x] = lb_;
+  sh[1][threadIdx.x] = lt;
+  sh[2][threadIdx.x] = ln;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int j = 0; j < 3; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 4 + 0] = sh[0][0];
+    part[blockIdx.x * 4 + 1] = sh[1][0];
+    part[blockIdx.x * 4 + 2] = sh[2][0];
+    part[blockIdx.x * 4 + 3] = 0.f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ g, uint64_t n,
+                                                      DevState* __restrict__ state) {
+  bool bad = false;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    bad = bad || !isfinite(g[i]);
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&state->nonfinite_pending, 1u);
+}
+
+// transposed copies of the MLP weights: W_k^T [fan_in][fan_out_pad]
+__device__ inline void write_transposed(const DevCfg& c, uint64_t i, float v, float* aux32, uint16_t* aux16) {
+  if (i < c.w_off[0]) return;
+  for (int k = 0; k <= c.hidden; ++k) {
+    const uint64_t sz = (uint64_t)c.fan_in[k] * c.fan_out[k];
+    if (i >= c.w_off[k] && i < c.w_off[k] + sz) {
+      const uint64_t j = i - c.w_off[k];
+      const uint32_t o = (uint32_t)(j / c.fan_in[k]), ii = (uint32_t)(j - (uint64_t)o * c.fan_in[k]);
+      const uint64_t dst = c.wt_off[k] + (uint64_t)ii * fan_out_pad(c, k) + o;
+      aux32[dst] = v;
+      aux16[dst] = f32_to_bf16_bits(v);
+      return;
+    }
+  }
+}
+
+// mode 0: Adam step; mode 1: shadow + transposed copies only
+__global__ __launch_bounds__(256) void k_adam(DevCfg c, float* __restrict__ params, uint16_t* __restrict__ lp,
+                                              float* __restrict__ m, float* __restrict__ v, float* __restrict__ grad,
+                                              float* __restrict__ aux32, uint16_t* __restrict__ aux16,
+                                              const DevState* __restrict__ state, float lr, float beta1, float beta2,
+                                              float eps, int mode) {
+  const bool skip = mode == 1 || state->nonfinite_pending != 0;
+  const float step = (float)(state->step + 1);
+  const float inv_scale = 1.0f / state->loss_scale;
+  const float c1 = 1.0f - powf(beta1, step), c2 = 1.0f - powf(beta2, step);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.n_params;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    float p = params[i];
+    if (mode == 0) {
+      const float g = grad[i];
+      grad[i] = 0.0f;
+      if (!skip) {
+        const float gs = g * inv_scale;
+        const float mi = beta1 * m[i] + (1.0f - beta1) * gs;
+        const float vi = beta2 * v[i] + (1.0f - beta2) * gs * gs;
+        m[i] = mi;
+        v[i] = vi;
+        const float mh = mi / c1, vh = vi / c2;
+        p -= lr * mh / (sqrtf(vh) + eps);
+        params[i] = p;
+      }
+    }
+    if (lp) lp[i] = f32_to_bf16_bits(p);
+    write_transposed(c, i, p, aux32, aux16);
+  }
+}
+
+__global__ void k_adam_finalize(DevState* state, int mode) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (mode == 0) {
+      if (state->nonfinite_pending) {
+        state->skipped += 1;
+        state->loss_scale *= 0.5f;
+        state->flags |= NBVH_FLAG_NONFINITE;
+      } else {
+        state->step += 1;
+      }
+    }
+    state->nonfinite_pending = 0u;
+  }
+}
+
+__global__ void k_reset_state(DevState* state, float loss_scale) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    state->step = 0;
+    state->skipped = 0;
+    state->loss_scale = loss_scale;
+    state->flags = 0u;
+    for (int i = 0; i < 4; ++i) state->last_loss[i] = 0.f;
+    state->last_n_segments = 0;
+    state->nonfinite_pending = 0u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename K>
+static void set_lds(K kernel, size_t bytes) {
+  hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+static WTiles make_tiles(const DevCfg& c) {
+  WTiles T;
+  T.n = 0;
+  for (int k = 0; k <= c.hidden; ++k)
+    for (int o0 = 0; o0 < fan_out_pad(c, k); o0 += 64)
+      for (int i0 = 0; i0 < c.fan_in[k]; i0 += 64) T.t[T.n++] = WTile{(int16_t)k, (int16_t)o0, (int16_t)i0, 0};
+  return T;
+}
+
+template <typename AT, int F, bool LP>
+static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const nbvh_label* labels, const float* dz_in,
+                           uint32_t n, float* loss_dev, void* ws, size_t ws_bytes) {
+  const DevCfg& c = L.cfg;
+  const TrainLayout T = train_layout(c, L.precision, n, L.n_cu);
+  if (ws_bytes < T.total) {
+    set_error("workspace too small for a batch of %u: need %zu bytes, got %zu", n, T.total, ws_bytes);
+    return NBVH_ERR_CAPACITY;
+  }
+  char* w = (char*)ws;
+  TrainPtrs P;
+  for (int k = 0; k <= c.hidden; ++k) {
+    P.hT[k] = w + T.hT[k];
+    P.gT[k] = w + T.gT[k];
+  }
+  P.duT = (float*)(w + T.duT);
+  P.loss_part = (float*)(w + T.loss_part);
+  const uint32_t kb = T.n_tiles * kTM;  // padded batch
+  P.ldb = kb;
+  const AT* W = (sizeof(AT) == 2) ? (const AT*)L.params_lp : (const AT*)L.params;
+  const AT* WT = (sizeof(AT) == 2) ? (const AT*)((char*)L.aux + c.n_wt * 4) : (const AT*)L.aux;
+  const void* table = LP ? (const void*)L.params_lp : (const void*)L.params;
+  const size_t lds = train_lds_bytes<AT>(c);
+  if (labels) {
+    auto kern = k_train_tile<AT, F, LP, true>;
+    set_lds(kern, lds);
+    kern<<<T.n_tiles, 256, lds, L.stream>>>(c, table, W, WT, probes, labels, nullptr, n, P, L.state, L.w_hit, L.w_t,
+                                             L.w_normal);
+    k_loss_finalize<<<1, 256, 0, L.stream>>>(P.loss_part, T.n_tiles, n, L.w_hit, L.w_t, L.w_normal, loss_dev, L.state);
+  } else {
+    auto kern = k_train_tile<AT, F, LP, false>;
+    set_lds(kern, lds);
+    kern<<<T.n_tiles, 256, lds, L.stream>>>(c, table, W, WT, probes, nullptr, dz_in, n, P, L.state, L.w_hit, L.w_t,
+                                             L.w_normal);
+  }
+  const WTiles tiles = make_tiles(c);
+  float* wpart = (float*)(w + T.wpart);
+  k_wgrad<AT><<<dim3(tiles.n, T.nsplit), 256, 0, L.stream>>>(c, tiles, P, kb, T.nsplit, wpart);
+  const uint64_t span = c.n_params - c.w_off[0];
+  k_wgrad_reduce<<<(uint32_t)((span + 255) / 256), 256, 0, L.stream>>>(c, wpart, T.nsplit, L.grad, L.state);
+  const uint64_t tasks = (uint64_t)n * c.n_samples * c.n_levels;
+  k_scatter<F><<<(uint32_t)((tasks + 255) / 256), 256, 0, L.stream>>>(c, probes, n, P.duT, kb, L.grad);
+  return check_launch("train");
+}
+
+nbvh_status launch_train_fwd_bwd(const LaunchCtx& L, const nbvh_probe* probes, const nbvh_label* labels,
+                                 const float* dz_in, uint32_t n, float* loss_dev, void* ws, size_t ws_bytes,
+                                 bool apply_grad) {
+  (void)apply_grad;
+  if (n == 0) return NBVH_OK;
+  const int F = L.cfg.n_features;
+  if (L.precision == NBVH_FP32)
+    return F == 2 ? train_t<float, 2, false>(L, probes, labels, dz_in, n, loss_dev, ws, ws_bytes)
+                  : train_t<float, 4, false>(L, probes, labels, dz_in, n, loss_dev, ws, ws_bytes);
+  return F == 2 ? train_t<bf16, 2, true>(L, probes, labels, dz_in, n, loss_dev, ws, ws_bytes)
+                : train_t<bf16, 4, true>(L, probes, labels, dz_in, n, loss_dev, ws, ws_bytes);
+}
+
+nbvh_status launch_loss(const LaunchCtx& L, const float* z, const nbvh_label* labels, uint32_t n, float* loss_dev,
+                        float* dz, void* ws, size_t ws_bytes) {
+  const uint32_t nb = (n + 255) / 256;
+  if (ws_bytes < (size_t)nb * 16) {
+    set_error("workspace too small for nbvh_loss");
+    return NBVH_ERR_CAPACITY;
+  }
+  if (n == 0) return NBVH_OK;
+  float* part = (float*)ws;
+  k_loss<<<nb, 256, 0, L.stream>>>(z, labels, n, L.cfg.n_out, L.w_hit, L.w_t, L.w_normal, dz, part);
+  k_loss_finalize<<<1, 256, 0, L.stream>>>(part, nb, n, L.w_hit, L.w_t, L.w_normal, loss_dev, L.state);
+  return check_launch("loss");
+}
+
+nbvh_status launch_optimizer(const LaunchCtx& L, bool reset, bool shadow_only) {
+  const DevCfg& c = L.cfg;
+  float* aux32 = (float*)L.aux;
+  uint16_t* aux16 = (uint16_t*)((char*)L.aux + c.n_wt * 4);
+  const uint32_t grid = (uint32_t)((c.n_params + 255) / 256 < 4096 ? (c.n_params + 255) / 256 : 4096);
+  if (reset) {
+    k_reset_state<<<1, 64, 0, L.stream>>>(L.state, L.loss_scale);
+  }
+  if (!shadow_only) {
+    k_check_finite<<<grid, 256, 0, L.stream>>>(L.grad, c.n_params, L.state);
+  }
+  k_adam<<<grid, 256, 0, L.stream>>>(c, L.params, (uint16_t*)L.params_lp, L.adam_m, L.adam_v, L.grad, aux32, aux16,
+                                     L.state, L.lr, L.beta1, L.beta2, L.eps, shadow_only ? 1 : 0);
+  k_adam_finalize<<<1, 64, 0, L.stream>>>(L.state, shadow_only ? 1 : 0);
+  return check_launch("optimizer");
+}
+
+}  // namespace nbvh

@@ -1,0 +1,271 @@
+// N-BVH traversal (Sec. 5): per-lane stack, two child slab tests per visit,
+// count -> exclusive scan -> fill into a compacted segment queue, each ray's
+// run sorted front to back by (t0, leaf id).
+//
+// The slab test is binary32 with one rounding per operation (this file is
+// built with FP contraction off) and correctly rounded reciprocals; because
+// every inner box is the exact union of its children and each operation is
+// monotone in the box bounds, the tree visits exactly the leaves an
+// every-leaf test reports, with bit-identical intervals.
+#include "launch.h"
+
+namespace nbvh {
+
+struct RayPre {
+  float o[3], d[3], inv[3];
+  float tmin, tmax;
+};
+
+__device__ inline RayPre load_ray(const nbvh_ray* rays, uint32_t r) {
+  const float4* p = (const float4*)(rays + r);
+  float4 a = p[0], b = p[1];
+  RayPre R;
+  R.o[0] = a.x;
+  R.o[1] = a.y;
+  R.o[2] = a.z;
+  R.tmin = a.w;
+  R.d[0] = b.x;
+  R.d[1] = b.y;
+  R.d[2] = b.z;
+  R.tmax = b.w;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) R.inv[k] = (R.d[k] == 0.0f) ? 0.0f : 1.0f / R.d[k];
+  return R;
+}
+
+// hit iff tn <= tf; axis with zero direction: origin must lie in the slab
+__device__ inline bool slab(const RayPre& R, const float lo[3], const float hi[3], float& t0, float& t1) {
+  float tn = R.tmin, tf = R.tmax;
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (R.d[a] == 0.0f) {
+      ok = ok && !(R.o[a] < lo[a] || R.o[a] > hi[a]);
+    } else {
+      float ta = (lo[a] - R.o[a]) * R.inv[a];
+      float tb = (hi[a] - R.o[a]) * R.inv[a];
+      if (R.inv[a] < 0.0f) {
+        float s = ta;
+        ta = tb;
+        tb = s;
+      }
+      tn = fmaxf(tn, ta);
+      tf = fminf(tf, tb);
+    }
+  }
+  t0 = tn;
+  t1 = tf;
+  return ok && (tn <= tf);
+}
+
+// Walk the tree; Emit(leaf, t0, t1) is called for every leaf crossed.
+template <typename Emit>
+__device__ inline void walk(const Node* __restrict__ nodes, const RayPre& R, Emit emit) {
+  int32_t stack[kMaxDepth];
+  int sp = 0;
+  int32_t node = 0;
+  while (true) {
+    const float4* p = (const float4*)(nodes + node);
+    float4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+    const float lo0[3] = {q0.x, q0.y, q0.z}, hi0[3] = {q0.w, q1.x, q1.y};
+    const float lo1[3] = {q1.z, q1.w, q2.x}, hi1[3] = {q2.y, q2.z, q2.w};
+    const int32_t c0 = __float_as_int(q3.x), c1 = __float_as_int(q3.y);
+    float a0, a1, b0, b1;
+    bool h0 = slab(R, lo0, hi0, a0, a1);
+    bool h1 = (c1 != kEmptyChild) && slab(R, lo1, hi1, b0, b1);
+    int32_t next = -1;
+    if (h0) {
+      if (c0 < 0) emit(~c0, a0, a1);
+      else next = c0;
+    }
+    if (h1) {
+      if (c1 < 0) {
+        emit(~c1, b0, b1);
+      } else if (next < 0) {
+        next = c1;
+      } else {
+        // both inner children: go to the nearer one first
+        if (b0 < a0) {
+          stack[sp++] = next;
+          next = c1;
+        } else {
+          stack[sp++] = c1;
+        }
+      }
+    }
+    if (next >= 0) {
+      node = next;
+    } else {
+      if (sp == 0) break;
+      node = stack[--sp];
+    }
+  }
+}
+
+// counts[r] = leaves crossed. If `hits` is given (full query), rays with no
+// segment get their miss record here and rays with segments are appended to
+// `active` (wave-aggregated atomic).
+__global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
+                                                        uint32_t n_rays, uint32_t* __restrict__ counts,
+                                                        nbvh_hit* __restrict__ hits, uint32_t* __restrict__ active,
+                                                        uint32_t* __restrict__ n_active) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t cnt = 0;
+  if (r < n_rays) {
+    RayPre R = load_ray(rays, r);
+    walk(nodes, R, [&](int32_t, float, float) { ++cnt; });
+    counts[r] = cnt;
+    if (hits && cnt == 0) {
+      float4* h = (float4*)(hits + r);
+      h[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+      h[1] = make_float4(0.f, 0.f, 0.f, __uint_as_float(NBVH_MISS));
+    }
+  }
+  if (active) {
+    const bool want = (r < n_rays) && cnt > 0;
+    const uint64_t mask = __ballot(want);
+    if (mask) {
+      const int lane = threadIdx.x & 63;
+      const int leader = __ffsll((unsigned long long)mask) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(n_active, (uint32_t)__popcll(mask));
+      base = __shfl(base, leader);
+      if (want) {
+        const uint32_t rank = __popcll(mask & ((1ull << lane) - 1ull));
+        active[base + rank] = r;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_traverse_fill(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
+                                                       uint32_t n_rays, const uint32_t* __restrict__ offsets,
+                                                       nbvh_segment* __restrict__ segs, uint64_t capacity) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rays) return;
+  if ((uint64_t)offsets[n_rays] > capacity) return;  // overflow flagged by the scan
+  const uint32_t beg = offsets[r], end = offsets[r + 1];
+  if (beg == end) return;
+  RayPre R = load_ray(rays, r);
+  uint32_t k = beg;
+  walk(nodes, R, [&](int32_t leaf, float t0, float t1) {
+    // insertion into the sorted run [beg, k)
+    uint32_t j = k;
+    while (j > beg) {
+      nbvh_segment prev = segs[j - 1];
+      if (prev.t0 > t0 || (prev.t0 == t0 && prev.leaf > (uint32_t)leaf)) {
+        segs[j] = prev;
+        --j;
+      } else {
+        break;
+      }
+    }
+    segs[j] = nbvh_segment{r, (uint32_t)leaf, t0, t1};
+    ++k;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of uint32 counts (3 kernels: tile scan, scan of tile sums,
+// add). Tile = 256 threads x 4 items.
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 4;
+constexpr int kScanTile = 256 * kScanItems;
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // inclusive scan within the wave
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  uint32_t wsum = 0, tot = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < wave) wsum += sh[w];
+    tot += sh[w];
+  }
+  __syncthreads();
+  total = tot;
+  return wsum + x - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tiles(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ out,
+                                                    uint32_t* __restrict__ tile_sums) {
+  __shared__ uint32_t sh[8];
+  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems], s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0u;
+    s += v[i];
+  }
+  uint32_t total;
+  uint32_t ex = block_exclusive_scan(s, sh, total);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = ex;
+    ex += v[i];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// one block: exclusive scan of the tile sums in place; total -> *total_out
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t* __restrict__ sums, uint32_t n_tiles,
+                                                    uint32_t* __restrict__ total_out) {
+  __shared__ uint32_t sh[16];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < n_tiles; base += blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t v = (i < n_tiles) ? sums[i] : 0u;
+    uint32_t total;
+    uint32_t ex = block_exclusive_scan(v, sh, total);
+    const uint32_t c0 = carry;
+    if (i < n_tiles) sums[i] = ex + c0;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c0 + total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(uint32_t* __restrict__ out, uint32_t n, const uint32_t* __restrict__ sums,
+                                                  const uint32_t* __restrict__ total, uint64_t capacity,
+                                                  DevState* __restrict__ state) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += sums[i / kScanTile];
+  if (i == 0) {
+    const uint32_t t = *total;
+    out[n] = t;
+    state->last_n_segments = t;
+    if ((uint64_t)t > capacity) atomicOr(&state->flags, NBVH_FLAG_CAPACITY);
+  }
+}
+
+// ---------------------------------------------------------------------------
+nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n_rays, uint32_t* offsets,
+                            nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
+                            uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
+                            uint32_t* scratch_total) {
+  const int grid = (int)((n_rays + 255) / 256);
+  if (n_active) {
+    k_zero_u32<<<1, 64, 0, L.stream>>>(n_active, 1);
+  }
+  if (n_rays > 0)
+    k_traverse_count<<<grid, 256, 0, L.stream>>>(L.nodes, rays, n_rays, scratch_counts, hits, active, n_active);
+  const uint32_t n_tiles = (n_rays + kScanTile - 1) / kScanTile;
+  if (n_rays > 0) k_scan_tiles<<<n_tiles, 256, 0, L.stream>>>(scratch_counts, n_rays, offsets, scratch_sums);
+  k_scan_sums<<<1, 1024, 0, L.stream>>>(scratch_sums, n_tiles, scratch_total);
+  k_scan_add<<<grid > 0 ? grid : 1, 256, 0, L.stream>>>(offsets, n_rays, scratch_sums, scratch_total, capacity,
+                                                        L.state);
+  if (segs && n_rays > 0)
+    k_traverse_fill<<<grid, 256, 0, L.stream>>>(L.nodes, rays, n_rays, offsets, segs, capacity);
+  return check_launch("traverse");
+}
+
+}  // namespace nbvh

@@ -1,0 +1,65 @@
+// Host-side launch plumbing shared by the kernel translation units.
+#pragma once
+#include "nbvh_internal.h"
+
+namespace nbvh {
+
+// Device state block (nbvh_state_bytes() bytes, caller-owned).
+struct DevState {
+  int64_t step;
+  int64_t skipped;
+  float loss_scale;
+  uint32_t flags;
+  float last_loss[4];
+  uint64_t last_n_segments;
+  uint32_t nonfinite_pending;  // set by producers of this step's gradient
+  uint32_t pad[7];
+};
+
+struct LaunchCtx {
+  hipStream_t stream;
+  const Node* nodes;
+  DevState* state;
+  DevCfg cfg;
+  int precision;
+  float* params;
+  void* params_lp;
+  float* adam_m;
+  float* adam_v;
+  float* grad;
+  void* aux;  // transposed weight copies: fp32 [n_mlp] then bf16 [n_mlp]
+  int n_cu;
+  // training hyper-parameters
+  float w_hit, w_t, w_normal, w_albedo;
+  float lr, beta1, beta2, eps, loss_scale;
+};
+
+nbvh_status check_launch(const char* what);
+void set_error(const char* fmt, ...);
+
+__global__ void k_zero_u32(uint32_t* p, uint32_t n);
+__global__ void k_zero_f32(float* p, uint64_t n);
+
+nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n_rays, uint32_t* offsets,
+                            nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
+                            uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
+                            uint32_t* scratch_total);
+
+nbvh_status launch_query_eval(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
+                              const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
+                              uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity);
+
+nbvh_status launch_encode(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, float* u);
+
+nbvh_status launch_forward(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, float* z);
+
+// training
+size_t train_ws_bytes(const DevCfg& c, int precision, uint64_t max_batch, int n_cu);
+nbvh_status launch_train_fwd_bwd(const LaunchCtx& L, const nbvh_probe* probes, const nbvh_label* labels,
+                                 const float* dz_in, uint32_t n, float* loss_dev, void* ws, size_t ws_bytes,
+                                 bool apply_grad);
+nbvh_status launch_loss(const LaunchCtx& L, const float* z, const nbvh_label* labels, uint32_t n, float* loss_dev,
+                        float* dz, void* ws, size_t ws_bytes);
+nbvh_status launch_optimizer(const LaunchCtx& L, bool reset, bool shadow_only);
+
+}  // namespace nbvh

@@ -1,0 +1,214 @@
+"""Thin Python layer over libnbvh.so: torch tensors for device memory, the
+current torch stream for ordering, ctypes for the calls. No compute here."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import check
+
+PRECISIONS = {"fp32": _abi.NBVH_FP32, "bf16": _abi.NBVH_BF16, "fp8": _abi.NBVH_FP8}
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_config(net, scene_lo, scene_side, precision="bf16", loss_weights=(2.0, 2.0, 1.0, 1.0), lr=1e-2,
+                beta1=0.9, beta2=0.99, eps=1e-8, loss_scale=1024.0) -> _abi.NbvhConfig:
+    """net: object with n_levels, n_features, log2_T, n_samples, level_res,
+    mlp_width, mlp_hidden, n_out."""
+    c = _abi.NbvhConfig()
+    c.n_levels, c.n_features, c.log2_T, c.n_samples = net.n_levels, net.n_features, net.log2_T, net.n_samples
+    for i, r in enumerate(net.level_res):
+        c.level_res[i] = int(r)
+    c.mlp_width, c.mlp_hidden, c.n_out = net.mlp_width, net.mlp_hidden, net.n_out
+    c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    for a in range(3):
+        c.scene_lo[a] = float(np.float32(scene_lo[a]))
+    c.scene_side = float(np.float32(scene_side))
+    c.w_hit, c.w_t, c.w_normal, c.w_albedo = loss_weights
+    c.lr, c.beta1, c.beta2, c.eps, c.loss_scale = lr, beta1, beta2, eps, loss_scale
+    return c
+
+
+class NBVH:
+    """An N-BVH with its network state on one GPU.
+
+    leaf_boxes: [n][6] float32 (lo.xyz, hi.xyz) on the host.
+    """
+
+    def __init__(self, net, leaf_boxes, scene_lo, scene_side, precision="bf16", device="cuda", **kw):
+        self.lib = _abi.load()
+        self.net = net
+        self.device = torch.device(device)
+        self.cfg = make_config(net, scene_lo, scene_side, precision, **kw)
+        self.precision = self.cfg.precision
+        lb = np.ascontiguousarray(leaf_boxes, dtype=np.float32)
+        self.n_leaves = lb.shape[0]
+        nb = self.lib.nbvh_nodes_bytes(self.n_leaves)
+        self.nodes = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        check(self.lib.nbvh_build(ctypes.byref(self.cfg), lb.ctypes.data_as(ctypes.c_void_p), self.n_leaves,
+                                  _ptr(self.nodes), nb, _stream(), ctypes.byref(ctx)))
+        self.ctx = ctx
+        nt, nm = ctypes.c_uint64(), ctypes.c_uint64()
+        check(self.lib.nbvh_param_count(ctypes.byref(self.cfg), ctypes.byref(nt), ctypes.byref(nm)))
+        self.n_table, self.n_mlp = nt.value, nm.value
+        offs = (ctypes.c_uint64 * (net.mlp_hidden + 3))()
+        check(self.lib.nbvh_param_layout(ctypes.byref(self.cfg), offs))
+        self.offsets = [int(o) for o in offs]
+        self.n_params = self.offsets[-1]
+        dev = self.device
+        self.params = torch.zeros(self.n_params, dtype=torch.float32, device=dev)
+        self.params_lp = torch.zeros(self.n_params, dtype=torch.bfloat16, device=dev)
+        self.adam_m = torch.zeros_like(self.params)
+        self.adam_v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.state = torch.zeros(self.lib.nbvh_state_bytes(), dtype=torch.uint8, device=dev)
+        self.aux = torch.zeros((self.lib.nbvh_aux_bytes(ctypes.byref(self.cfg)) + 255) // 256 * 256,
+                               dtype=torch.uint8, device=dev)
+        p = _abi.NbvhParams(_ptr(self.params).value, _ptr(self.params_lp).value, _ptr(self.adam_m).value,
+                            _ptr(self.adam_v).value, _ptr(self.grad).value, _ptr(self.state).value,
+                            _ptr(self.aux).value)
+        check(self.lib.nbvh_bind_params(self.ctx, ctypes.byref(p)))
+        check(self.lib.nbvh_reset_optimizer(self.ctx, _stream()))
+        self._ws = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.nbvh_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # -- parameters ---------------------------------------------------------------
+    def layer_dims(self):
+        n_in = self.net.n_samples * self.net.n_levels * self.net.n_features
+        w = self.net.mlp_width
+        return [(n_in, w)] + [(w, w)] * (self.net.mlp_hidden - 1) + [(w, self.net.n_out)]
+
+    def set_params(self, flat):
+        """flat: unpadded [table | W_0 | ... | W_H] (float32), as nbvh_synth.init_params."""
+        flat = torch.as_tensor(np.asarray(flat, dtype=np.float32))
+        dev = torch.zeros(self.n_params, dtype=torch.float32)
+        dev[: self.n_table] = flat[: self.n_table]
+        src = self.n_table
+        for k, (fi, fo) in enumerate(self.layer_dims()):
+            dst = self.offsets[1 + k]
+            dev[dst:dst + fi * fo] = flat[src:src + fi * fo]
+            src += fi * fo
+        assert src == flat.numel(), (src, flat.numel())
+        self.params.copy_(dev.to(self.device))
+        check(self.lib.nbvh_reset_optimizer(self.ctx, _stream()))
+
+    def get_params(self) -> np.ndarray:
+        """Unpadded float32 copy of the master parameters."""
+        return self.unpad(self.params)
+
+    def unpad(self, t: torch.Tensor) -> np.ndarray:
+        h = t.detach().float().cpu().numpy()
+        parts = [h[: self.n_table]]
+        for k, (fi, fo) in enumerate(self.layer_dims()):
+            o = self.offsets[1 + k]
+            parts.append(h[o:o + fi * fo])
+        return np.concatenate(parts)
+
+    def sync_shadow(self):
+        check(self.lib.nbvh_sync_shadow(self.ctx, _stream()))
+
+    def reset_optimizer(self):
+        check(self.lib.nbvh_reset_optimizer(self.ctx, _stream()))
+
+    # -- workspace ------------------------------------------------------------------
+    def workspace(self, max_rays=0, max_segments=0, max_batch=0) -> torch.Tensor:
+        need = self.lib.nbvh_workspace_bytes(self.ctx, max_rays, max_segments, max_batch)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    # -- calls --------------------------------------------------------------------
+    def traverse(self, rays: torch.Tensor, seg_capacity: int):
+        n = rays.shape[0]
+        offsets = torch.empty(n + 1, dtype=torch.int32, device=self.device)
+        segs = torch.empty((max(seg_capacity, 1), 4), dtype=torch.int32, device=self.device)
+        ws = self.workspace(n, 0, 0)
+        check(self.lib.nbvh_traverse(self.ctx, _ptr(rays), n, _ptr(offsets), _ptr(segs), seg_capacity, _ptr(ws),
+                                     ws.numel(), _stream()))
+        return offsets, segs
+
+    def query(self, rays: torch.Tensor, seg_capacity: int | None = None, hits: torch.Tensor | None = None):
+        """rays [n][8] float32 (device). Returns hits [n][8] float32 view:
+        t, n.xyz, albedo.rgb, leaf (bits; 0xFFFFFFFF = miss)."""
+        n = rays.shape[0]
+        if seg_capacity is None:
+            seg_capacity = 8 * n + 1024
+        if hits is None:
+            hits = torch.empty((n, 8), dtype=torch.float32, device=self.device)
+        ws = self.workspace(n, seg_capacity, 0)
+        check(self.lib.nbvh_query(self.ctx, _ptr(rays), n, _ptr(hits), seg_capacity, _ptr(ws), ws.numel(),
+                                  _stream()))
+        return hits
+
+    def encode(self, probes: torch.Tensor):
+        n = probes.shape[0]
+        u = torch.empty((n, self.net.n_samples * self.net.n_levels * self.net.n_features), dtype=torch.float32,
+                        device=self.device)
+        check(self.lib.nbvh_encode(self.ctx, _ptr(probes), n, _ptr(u), _stream()))
+        return u
+
+    def forward(self, probes: torch.Tensor):
+        n = probes.shape[0]
+        z = torch.empty((n, self.net.n_out), dtype=torch.float32, device=self.device)
+        check(self.lib.nbvh_forward(self.ctx, _ptr(probes), n, _ptr(z), None, 0, _stream()))
+        return z
+
+    def backward(self, probes: torch.Tensor, dz: torch.Tensor):
+        n = probes.shape[0]
+        ws = self.workspace(0, 0, n)
+        check(self.lib.nbvh_backward(self.ctx, _ptr(probes), n, _ptr(dz.contiguous()), _ptr(ws), ws.numel(),
+                                     _stream()))
+
+    def optimizer_step(self):
+        check(self.lib.nbvh_optimizer_step(self.ctx, _stream()))
+
+    def train_step(self, probes: torch.Tensor, labels: torch.Tensor, loss: torch.Tensor | None = None):
+        n = probes.shape[0]
+        ws = self.workspace(0, 0, n)
+        if loss is None:
+            loss = torch.empty(4, dtype=torch.float32, device=self.device)
+        check(self.lib.nbvh_train_step(self.ctx, _ptr(probes), _ptr(labels), n, _ptr(loss), _ptr(ws), ws.numel(),
+                                       _stream()))
+        return loss
+
+    def loss(self, z: torch.Tensor, labels: torch.Tensor, with_grad=True):
+        n = z.shape[0]
+        ws = self.workspace(0, 0, n)
+        loss = torch.empty(4, dtype=torch.float32, device=self.device)
+        dz = torch.empty_like(z) if with_grad else None
+        check(self.lib.nbvh_loss(self.ctx, _ptr(z.contiguous()), _ptr(labels), n, _ptr(loss), _ptr(dz), _ptr(ws),
+                                 ws.numel(), _stream()))
+        return loss, dz
+
+    def read_state(self) -> dict:
+        s = _abi.NbvhStateHost()
+        check(self.lib.nbvh_read_state(self.ctx, ctypes.byref(s), _stream()))
+        return dict(step=s.step, skipped=s.skipped, loss_scale=s.loss_scale, flags=s.flags,
+                    last_loss=list(s.last_loss), last_n_segments=s.last_n_segments)
+
+    def clear_flags(self):
+        check(self.lib.nbvh_clear_flags(self.ctx, _stream()))
+
+
+def hits_leaf(hits: torch.Tensor) -> torch.Tensor:
+    """Leaf ids of hit records (int64; -1 for a miss)."""
+    leaf = hits[:, 7].contiguous().view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    return torch.where(leaf == _abi.NBVH_MISS, torch.full_like(leaf, -1), leaf)
