@@ -162,6 +162,7 @@ typedef struct {
   uint32_t flags;      /* NBVH_FLAG_* bits, sticky until nbvh_clear_flags */
   float last_loss[4];  /* last train step: total, BCE, distance L1, normal L1 (unweighted) */
   uint64_t last_n_segments; /* segments produced by the last traversal */
+  uint64_t n_evaluated;     /* segments evaluated by queries since the last nbvh_reset_optimizer */
 } nbvh_state_host;
 
 typedef struct nbvh_ctx nbvh_ctx; /* opaque host handle */
@@ -276,6 +277,30 @@ nbvh_status nbvh_train_step(nbvh_ctx* ctx, const nbvh_probe* probes_dev, const n
 /* Loss and dL/dz only (no back-propagation): dz_dev may be NULL. */
 nbvh_status nbvh_loss(nbvh_ctx* ctx, const float* z_dev, const nbvh_label* labels_dev, uint64_t n,
                       float* loss_dev, float* dz_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Kernel groups reported by the profiler. */
+typedef enum {
+  NBVH_K_TRAVERSE = 0,   /* count + scan + fill */
+  NBVH_K_QUERY_EVAL = 1, /* fused encode + MLP + resolve */
+  NBVH_K_FORWARD = 2,    /* forward tile kernel */
+  NBVH_K_TRAIN_TILE = 3, /* fused encode + forward + loss + dgrad */
+  NBVH_K_WGRAD = 4,      /* weight-gradient GEMMs + reduction */
+  NBVH_K_SCATTER = 5,    /* table-gradient scatter */
+  NBVH_K_OPTIMIZER = 6,  /* finite check + Adam */
+  NBVH_K_COUNT = 7
+} nbvh_kernel_id;
+
+typedef struct {
+  double ms[NBVH_K_COUNT];     /* summed device time between the group's start and end events */
+  int64_t calls[NBVH_K_COUNT]; /* launches of the group */
+} nbvh_profile;
+
+/* Start recording a HIP event pair around every kernel group launched
+ * through this context (on the caller's stream) until nbvh_profile_end,
+ * which synchronises on the events and returns the sums. At most 16384
+ * groups are recorded per window; later ones are not timed. */
+nbvh_status nbvh_profile_begin(nbvh_ctx* ctx);
+nbvh_status nbvh_profile_end(nbvh_ctx* ctx, nbvh_profile* out);
 
 /* Copy the device state block to the host (synchronises `stream`). */
 nbvh_status nbvh_read_state(nbvh_ctx* ctx, nbvh_state_host* out, void* stream);

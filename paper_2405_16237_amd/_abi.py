@@ -39,9 +39,18 @@ class NbvhParams(ctypes.Structure):
                 ("aux_dev", ctypes.c_void_p)]
 
 
+NBVH_K_COUNT = 7
+KERNEL_GROUPS = ["traverse", "query_eval", "forward", "train_tile", "wgrad", "scatter", "optimizer"]
+
+
+class NbvhProfile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * NBVH_K_COUNT), ("calls", ctypes.c_int64 * NBVH_K_COUNT)]
+
+
 class NbvhStateHost(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("skipped", ctypes.c_int64), ("loss_scale", ctypes.c_float),
-                ("flags", ctypes.c_uint32), ("last_loss", ctypes.c_float * 4), ("last_n_segments", ctypes.c_uint64)]
+                ("flags", ctypes.c_uint32), ("last_loss", ctypes.c_float * 4), ("last_n_segments", ctypes.c_uint64),
+                ("n_evaluated", ctypes.c_uint64)]
 
 
 # every entry point declared in include/nbvh.h
@@ -49,7 +58,7 @@ EXPORTS = [
     "nbvh_param_count", "nbvh_param_layout", "nbvh_aux_bytes", "nbvh_nodes_bytes", "nbvh_state_bytes", "nbvh_build",
     "nbvh_bind_params", "nbvh_reset_optimizer", "nbvh_sync_shadow", "nbvh_workspace_bytes", "nbvh_traverse",
     "nbvh_query", "nbvh_query_segments", "nbvh_encode", "nbvh_forward", "nbvh_backward", "nbvh_optimizer_step",
-    "nbvh_train_step", "nbvh_loss", "nbvh_read_state", "nbvh_clear_flags", "nbvh_last_error", "nbvh_version",
+    "nbvh_train_step", "nbvh_loss", "nbvh_profile_begin", "nbvh_profile_end", "nbvh_read_state", "nbvh_clear_flags", "nbvh_last_error", "nbvh_version",
     "nbvh_destroy",
 ]
 
@@ -92,6 +101,8 @@ def load(path: str = LIB_PATH):
         "nbvh_optimizer_step": (st, [P, P]),
         "nbvh_train_step": (st, [P, P, P, U64, P, P, SZ, P]),
         "nbvh_loss": (st, [P, P, P, U64, P, P, P, SZ, P]),
+        "nbvh_profile_begin": (st, [P]),
+        "nbvh_profile_end": (st, [P, P]),
         "nbvh_read_state": (st, [P, P, P]),
         "nbvh_clear_flags": (st, [P, P]),
         "nbvh_last_error": (ctypes.c_char_p, []),

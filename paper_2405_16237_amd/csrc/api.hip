@@ -19,6 +19,7 @@ struct nbvh_ctx {
   nbvh_params p;
   bool bound;
   int n_cu;
+  nbvh::Profiler* prof;
 };
 
 namespace nbvh {
@@ -218,6 +219,7 @@ static LaunchCtx make_launch(const nbvh_ctx* ctx, void* stream) {
   L.beta2 = ctx->cfg.beta2;
   L.eps = ctx->cfg.eps;
   L.loss_scale = ctx->cfg.loss_scale;
+  L.prof = (ctx->prof && ctx->prof->on) ? ctx->prof : nullptr;
   return L;
 }
 
@@ -429,17 +431,21 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbv
 
 nbvh_status nbvh_query_segments(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, const uint32_t* seg_offsets,
                                 const nbvh_segment* segs, nbvh_hit* hits, void* ws, size_t ws_bytes, void* stream) {
-  (void)ctx;
-  (void)rays;
-  (void)n_rays;
-  (void)seg_offsets;
-  (void)segs;
-  (void)hits;
-  (void)ws;
-  (void)ws_bytes;
-  (void)stream;
-  set_error("nbvh_query_segments is not implemented in this version");
-  return NBVH_ERR_UNSUPPORTED;
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
+  if ((n_rays && (!rays || !hits || !seg_offsets || !segs)) || !ws) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  const QueryLayout Q = query_layout(n_rays, 0);
+  if (ws_bytes < Q.segs) return set_error("workspace too small: need %zu", Q.segs), NBVH_ERR_CAPACITY;
+  if (n_rays == 0) return NBVH_OK;
+  LaunchCtx L = make_launch(ctx, stream);
+  char* w = (char*)ws;
+  uint32_t* misc = (uint32_t*)(w + Q.misc);
+  uint32_t* active = (uint32_t*)(w + Q.active);
+  s = launch_active_rays(L, seg_offsets, (uint32_t)n_rays, hits, active, misc);
+  if (s != NBVH_OK) return s;
+  return launch_query_eval(L, rays, seg_offsets, segs, active, misc + 0, misc + 1, hits, (uint32_t)n_rays,
+                           0xffffffffull);
 }
 
 nbvh_status nbvh_encode(nbvh_ctx* ctx, const nbvh_probe* probes, uint64_t n, float* u, void* stream) {
@@ -517,6 +523,7 @@ nbvh_status nbvh_read_state(nbvh_ctx* ctx, nbvh_state_host* out, void* stream) {
   out->flags = st.flags;
   for (int i = 0; i < 4; ++i) out->last_loss[i] = st.last_loss[i];
   out->last_n_segments = st.last_n_segments;
+  out->n_evaluated = st.n_evaluated;
   return NBVH_OK;
 }
 
@@ -530,6 +537,48 @@ nbvh_status nbvh_clear_flags(nbvh_ctx* ctx, void* stream) {
   return check_launch("clear_flags");
 }
 
-void nbvh_destroy(nbvh_ctx* ctx) { delete ctx; }
+nbvh_status nbvh_profile_begin(nbvh_ctx* ctx) {
+  if (!ctx) return set_error("ctx is NULL"), NBVH_ERR_INVALID_ARG;
+  if (!ctx->prof) {
+    ctx->prof = new Profiler;
+    ctx->prof->ev.resize(2 * Profiler::kMax);
+    ctx->prof->kid.resize(Profiler::kMax);
+    for (auto& e : ctx->prof->ev)
+      if (hipEventCreate(&e) != hipSuccess) return set_error("hipEventCreate failed"), NBVH_ERR_HIP;
+  }
+  ctx->prof->used = 0;
+  ctx->prof->on = true;
+  return NBVH_OK;
+}
+
+nbvh_status nbvh_profile_end(nbvh_ctx* ctx, nbvh_profile* out) {
+  if (!ctx || !out) return set_error("NULL argument"), NBVH_ERR_INVALID_ARG;
+  memset(out, 0, sizeof(*out));
+  if (!ctx->prof || !ctx->prof->on) return set_error("no profiling window open"), NBVH_ERR_INVALID_ARG;
+  Profiler* p = ctx->prof;
+  p->on = false;
+  for (size_t i = 0; i < p->used; ++i) {
+    if (hipEventSynchronize(p->ev[2 * i + 1]) != hipSuccess) return set_error("hipEventSynchronize failed"), NBVH_ERR_HIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]) != hipSuccess)
+      return set_error("hipEventElapsedTime failed"), NBVH_ERR_HIP;
+    const int k = p->kid[i];
+    if (k >= 0 && k < NBVH_K_COUNT) {
+      out->ms[k] += ms;
+      out->calls[k] += 1;
+    }
+  }
+  p->used = 0;
+  return NBVH_OK;
+}
+
+void nbvh_destroy(nbvh_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->prof) {
+    for (auto& e : ctx->prof->ev) hipEventDestroy(e);
+    delete ctx->prof;
+  }
+  delete ctx;
+}
 
 }  // extern "C"

@@ -34,7 +34,8 @@ __global__ __launch_bounds__(256) void k_query_eval(DevCfg c, const void* __rest
                                                     const uint32_t* __restrict__ active,
                                                     const uint32_t* __restrict__ n_active_p,
                                                     uint32_t* __restrict__ counter, nbvh_hit* __restrict__ hits,
-                                                    const uint32_t* __restrict__ total_segs, uint64_t capacity) {
+                                                    const uint32_t* __restrict__ total_segs, uint64_t capacity,
+                                                    DevState* __restrict__ state) {
   if ((uint64_t)*total_segs > capacity) return;  // segment queue overflowed: flagged, nothing to read
   extern __shared__ __align__(16) unsigned char smem[];
   const int ld0 = (c.n_in > c.width ? c.n_in : c.width) + Pad<AT>::v;
@@ -55,6 +56,7 @@ __global__ __launch_bounds__(256) void k_query_eval(DevCfg c, const void* __rest
   float t0 = 0.f, t1 = 0.f, best_t = INFINITY;
   float bn[3] = {0.f, 0.f, 0.f}, ba[3] = {0.f, 0.f, 0.f};
   bool exhausted = false;
+  uint32_t evaluated = 0;
 
   while (true) {
     if (wave == 0) {
@@ -100,6 +102,7 @@ __global__ __launch_bounds__(256) void k_query_eval(DevCfg c, const void* __rest
     mlp_forward_tile<kQM, 4, AT>(c, W, act0, ld0, act1, ld1, z, kOutPad);
 
     if (wave == 0 && ray != NBVH_MISS) {
+      ++evaluated;
       const float* zr = z + lane * kOutPad;
       if (zr[0] > 0.0f) {
         const float t = t0 + sigmoidf_(zr[1]) * (t1 - t0);
@@ -145,6 +148,43 @@ __global__ __launch_bounds__(256) void k_query_eval(DevCfg c, const void* __rest
     }
     __syncthreads();
   }
+  if (wave == 0) {
+    uint32_t e = evaluated;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+    if (lane == 0 && e) atomicAdd(&state->n_evaluated, (unsigned long long)e);
+  }
+}
+
+// Rays with at least one segment, appended in wave order (query over a
+// caller-given segment queue). Also clears the ray counter of the eval kernel.
+__global__ __launch_bounds__(256) void k_active_rays(const uint32_t* __restrict__ offsets, uint32_t n_rays,
+                                                     nbvh_hit* __restrict__ hits, uint32_t* __restrict__ active,
+                                                     uint32_t* __restrict__ n_active) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = r < n_rays;
+  const bool want = valid && offsets[r + 1] > offsets[r];
+  if (valid && !want) {
+    float4* h = (float4*)(hits + r);
+    h[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    h[1] = make_float4(0.f, 0.f, 0.f, __uint_as_float(NBVH_MISS));
+  }
+  const uint64_t mask = __ballot(want);
+  if (mask) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(n_active, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    if (want) active[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = r;
+  }
+}
+
+nbvh_status launch_active_rays(const LaunchCtx& L, const uint32_t* offsets, uint32_t n_rays, nbvh_hit* hits,
+                               uint32_t* active, uint32_t* misc) {
+  k_zero_u32<<<1, 64, 0, L.stream>>>(misc, 2);
+  if (n_rays) k_active_rays<<<(n_rays + 255) / 256, 256, 0, L.stream>>>(offsets, n_rays, hits, active, misc);
+  return check_launch("active_rays");
 }
 
 // Forward of probe segments: tile of 64 probes per workgroup, z -> global.
@@ -221,11 +261,11 @@ static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const 
   uint32_t grid = (uint32_t)L.n_cu * per_cu;
   const uint32_t need = (n_rays_bound + kQM - 1) / kQM;
   if (need < grid) grid = need > 0 ? need : 1;
-  k_zero_u32<<<1, 64, 0, L.stream>>>(counter, 1);
   const AT* W = (sizeof(AT) == 2) ? (const AT*)L.params_lp : (const AT*)L.params;
   const void* table = LP ? (const void*)L.params_lp : (const void*)L.params;
+  ProfScope ps(L.prof, NBVH_K_QUERY_EVAL, L.stream);
   kern<<<grid, 256, lds, L.stream>>>(c, table, W, rays, offsets, segs, active, n_active, counter, hits,
-                                     offsets + n_rays_bound, capacity);
+                                     offsets + n_rays_bound, capacity, L.state);
   return check_launch("query_eval");
 }
 
@@ -250,6 +290,7 @@ static nbvh_status forward_t(const LaunchCtx& L, const nbvh_probe* probes, uint3
   const AT* W = (sizeof(AT) == 2) ? (const AT*)L.params_lp : (const AT*)L.params;
   const void* table = LP ? (const void*)L.params_lp : (const void*)L.params;
   if (n == 0) return NBVH_OK;
+  ProfScope ps(L.prof, NBVH_K_FORWARD, L.stream);
   kern<<<(n + kQM - 1) / kQM, 256, lds, L.stream>>>(c, table, W, probes, n, z);
   return check_launch("forward");
 }

@@ -539,6 +539,7 @@ __global__ void k_reset_state(DevState* state, float loss_scale) {
     for (int i = 0; i < 4; ++i) state->last_loss[i] = 0.f;
     state->last_n_segments = 0;
     state->nonfinite_pending = 0u;
+    state->n_evaluated = 0ull;
   }
 }
 
@@ -580,25 +581,40 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
   const AT* WT = (sizeof(AT) == 2) ? (const AT*)((char*)L.aux + c.n_wt * 4) : (const AT*)L.aux;
   const void* table = LP ? (const void*)L.params_lp : (const void*)L.params;
   const size_t lds = train_lds_bytes<AT>(c);
-  if (labels) {
-    auto kern = k_train_tile<AT, F, LP, true>;
-    set_lds(kern, lds);
-    kern<<<T.n_tiles, 256, lds, L.stream>>>(c, table, W, WT, probes, labels, nullptr, n, P, L.state, L.w_hit, L.w_t,
-                                             L.w_normal);
-    k_loss_finalize<<<1, 256, 0, L.stream>>>(P.loss_part, T.n_tiles, n, L.w_hit, L.w_t, L.w_normal, loss_dev, L.state);
-  } else {
-    auto kern = k_train_tile<AT, F, LP, false>;
-    set_lds(kern, lds);
-    kern<<<T.n_tiles, 256, lds, L.stream>>>(c, table, W, WT, probes, nullptr, dz_in, n, P, L.state, L.w_hit, L.w_t,
-                                             L.w_normal);
+  if (lds > 160 * 1024) {
+    set_error("training tile needs %zu bytes of LDS (> 160 KiB) for this network", lds);
+    return NBVH_ERR_UNSUPPORTED;
   }
-  const WTiles tiles = make_tiles(c);
-  float* wpart = (float*)(w + T.wpart);
-  k_wgrad<AT><<<dim3(tiles.n, T.nsplit), 256, 0, L.stream>>>(c, tiles, P, kb, T.nsplit, wpart);
-  const uint64_t span = c.n_params - c.w_off[0];
-  k_wgrad_reduce<<<(uint32_t)((span + 255) / 256), 256, 0, L.stream>>>(c, wpart, T.nsplit, L.grad, L.state);
-  const uint64_t tasks = (uint64_t)n * c.n_samples * c.n_levels;
-  k_scatter<F><<<(uint32_t)((tasks + 255) / 256), 256, 0, L.stream>>>(c, probes, n, P.duT, kb, L.grad);
+  {
+    ProfScope ps(L.prof, NBVH_K_TRAIN_TILE, L.stream);
+    if (labels) {
+      auto kern = k_train_tile<AT, F, LP, true>;
+      set_lds(kern, lds);
+      kern<<<T.n_tiles, 256, lds, L.stream>>>(c, table, W, WT, probes, labels, nullptr, n, P, L.state, L.w_hit,
+                                               L.w_t, L.w_normal);
+    } else {
+      auto kern = k_train_tile<AT, F, LP, false>;
+      set_lds(kern, lds);
+      kern<<<T.n_tiles, 256, lds, L.stream>>>(c, table, W, WT, probes, nullptr, dz_in, n, P, L.state, L.w_hit,
+                                               L.w_t, L.w_normal);
+    }
+  }
+  {
+    ProfScope ps(L.prof, NBVH_K_WGRAD, L.stream);
+    if (labels)
+      k_loss_finalize<<<1, 256, 0, L.stream>>>(P.loss_part, T.n_tiles, n, L.w_hit, L.w_t, L.w_normal, loss_dev,
+                                               L.state);
+    const WTiles tiles = make_tiles(c);
+    float* wpart = (float*)(w + T.wpart);
+    k_wgrad<AT><<<dim3(tiles.n, T.nsplit), 256, 0, L.stream>>>(c, tiles, P, kb, T.nsplit, wpart);
+    const uint64_t span = c.n_params - c.w_off[0];
+    k_wgrad_reduce<<<(uint32_t)((span + 255) / 256), 256, 0, L.stream>>>(c, wpart, T.nsplit, L.grad, L.state);
+  }
+  {
+    ProfScope ps(L.prof, NBVH_K_SCATTER, L.stream);
+    const uint64_t tasks = (uint64_t)n * c.n_samples * c.n_levels;
+    k_scatter<F><<<(uint32_t)((tasks + 255) / 256), 256, 0, L.stream>>>(c, probes, n, P.duT, kb, L.grad);
+  }
   return check_launch("train");
 }
 
@@ -634,6 +650,7 @@ nbvh_status launch_optimizer(const LaunchCtx& L, bool reset, bool shadow_only) {
   float* aux32 = (float*)L.aux;
   uint16_t* aux16 = (uint16_t*)((char*)L.aux + c.n_wt * 4);
   const uint32_t grid = (uint32_t)((c.n_params + 255) / 256 < 4096 ? (c.n_params + 255) / 256 : 4096);
+  ProfScope ps(L.prof, NBVH_K_OPTIMIZER, L.stream);
   if (reset) {
     k_reset_state<<<1, 64, 0, L.stream>>>(L.state, L.loss_scale);
   }

@@ -1,8 +1,39 @@
 // Host-side launch plumbing shared by the kernel translation units.
 #pragma once
+#include <vector>
+
 #include "nbvh_internal.h"
 
 namespace nbvh {
+
+// HIP event pairs around kernel groups, recorded on the launch stream while a
+// profiling window is open (nbvh_profile_begin / nbvh_profile_end).
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // 2 per record
+  std::vector<int> kid;
+  size_t used = 0;
+  static constexpr size_t kMax = 16384;
+};
+
+class ProfScope {
+ public:
+  ProfScope(Profiler* p, int kid, hipStream_t s) : p_(p), idx_((size_t)-1), s_(s) {
+    if (p_ && p_->on && p_->used < p_->kid.size()) {
+      idx_ = p_->used++;
+      p_->kid[idx_] = kid;
+      hipEventRecord(p_->ev[2 * idx_], s_);
+    }
+  }
+  ~ProfScope() {
+    if (idx_ != (size_t)-1) hipEventRecord(p_->ev[2 * idx_ + 1], s_);
+  }
+
+ private:
+  Profiler* p_;
+  size_t idx_;
+  hipStream_t s_;
+};
 
 // Device state block (nbvh_state_bytes() bytes, caller-owned).
 struct DevState {
@@ -13,7 +44,9 @@ struct DevState {
   float last_loss[4];
   uint64_t last_n_segments;
   uint32_t nonfinite_pending;  // set by producers of this step's gradient
-  uint32_t pad[7];
+  uint32_t pad0;
+  unsigned long long n_evaluated;  // segments evaluated by queries
+  uint32_t pad[4];
 };
 
 struct LaunchCtx {
@@ -32,6 +65,7 @@ struct LaunchCtx {
   // training hyper-parameters
   float w_hit, w_t, w_normal, w_albedo;
   float lr, beta1, beta2, eps, loss_scale;
+  Profiler* prof;
 };
 
 nbvh_status check_launch(const char* what);
@@ -48,6 +82,9 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
 nbvh_status launch_query_eval(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
                               const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
                               uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity);
+
+nbvh_status launch_active_rays(const LaunchCtx& L, const uint32_t* offsets, uint32_t n_rays, nbvh_hit* hits,
+                               uint32_t* active, uint32_t* misc);
 
 nbvh_status launch_encode(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, float* u);
 

@@ -198,11 +198,31 @@ class NBVH:
                                  ws.numel(), _stream()))
         return loss, dz
 
+    def query_segments(self, rays: torch.Tensor, offsets: torch.Tensor, segs: torch.Tensor,
+                       hits: torch.Tensor | None = None):
+        """Evaluation + resolve over a segment queue from traverse()."""
+        n = rays.shape[0]
+        if hits is None:
+            hits = torch.empty((n, 8), dtype=torch.float32, device=self.device)
+        ws = self.workspace(n, 0, 0)
+        check(self.lib.nbvh_query_segments(self.ctx, _ptr(rays), n, _ptr(offsets), _ptr(segs), _ptr(hits), _ptr(ws),
+                                           ws.numel(), _stream()))
+        return hits
+
+    def profile_begin(self):
+        check(self.lib.nbvh_profile_begin(self.ctx))
+
+    def profile_end(self) -> dict:
+        """{group: (total ms, launches)} over the window."""
+        p = _abi.NbvhProfile()
+        check(self.lib.nbvh_profile_end(self.ctx, ctypes.byref(p)))
+        return {name: (p.ms[i], p.calls[i]) for i, name in enumerate(_abi.KERNEL_GROUPS)}
+
     def read_state(self) -> dict:
         s = _abi.NbvhStateHost()
         check(self.lib.nbvh_read_state(self.ctx, ctypes.byref(s), _stream()))
         return dict(step=s.step, skipped=s.skipped, loss_scale=s.loss_scale, flags=s.flags,
-                    last_loss=list(s.last_loss), last_n_segments=s.last_n_segments)
+                    last_loss=list(s.last_loss), last_n_segments=s.last_n_segments, n_evaluated=s.n_evaluated)
 
     def clear_flags(self):
         check(self.lib.nbvh_clear_flags(self.ctx, _stream()))
