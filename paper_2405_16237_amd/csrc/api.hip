@@ -100,7 +100,7 @@ static nbvh_status make_devcfg(const nbvh_config* c, DevCfg* d) {
   d->n_table = off;
   for (int a = 0; a < 3; ++a) d->scene_lo[a] = c->scene_lo[a];
   d->inv_side = 1.0f / c->scene_side;
-  d->inv_S = 1.0f / (float)S;
+  for (int s = 0; s < S; ++s) d->frac[s] = ((float)s + 0.5f) / (float)S;
   uint64_t p = round_up(off, kAlign), wt = 0, nm = 0;
   for (int k = 0; k <= d->hidden; ++k) {
     d->fan_in[k] = (k == 0) ? n_in : W;
@@ -404,7 +404,7 @@ nbvh_status nbvh_traverse(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, 
   char* w = (char*)ws;
   uint32_t* misc = (uint32_t*)(w + Q.misc);
   return launch_traverse(L, rays, (uint32_t)n_rays, seg_offsets, segs, seg_capacity, nullptr, nullptr, nullptr,
-                         (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 2);
+                         (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12);
 }
 
 nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbvh_hit* hits, uint64_t seg_capacity,
@@ -423,7 +423,7 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbv
   uint32_t* misc = (uint32_t*)(w + Q.misc);
   nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
   s = launch_traverse(L, rays, (uint32_t)n_rays, offsets, segs, seg_capacity, hits, (uint32_t*)(w + Q.active), misc + 0,
-                      (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 2);
+                      (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12);
   if (s != NBVH_OK) return s;
   return launch_query_eval(L, rays, offsets, segs, (const uint32_t*)(w + Q.active), misc + 0, misc + 1, hits,
                            (uint32_t)n_rays, seg_capacity);

@@ -27,28 +27,125 @@ __device__ inline void store_features(AT* dst, const float v[F]) {
   }
 }
 
+// Raw table entry (F features) as loaded: packed bf16 or fp32 words.
+template <int F, bool LP>
+struct RawEntry;
+template <>
+struct RawEntry<2, true> {
+  typedef uint32_t T;
+};
+template <>
+struct RawEntry<4, true> {
+  typedef uint2 T;
+};
+template <>
+struct RawEntry<2, false> {
+  typedef float2 T;
+};
+template <>
+struct RawEntry<4, false> {
+  typedef float4 T;
+};
+
+template <int F, bool LP>
+__device__ inline typename RawEntry<F, LP>::T load_raw(const void* table, uint32_t param_index) {
+  typedef typename RawEntry<F, LP>::T T;
+  // 32-bit byte offset from a uniform base: one VGPR per address (tables
+  // are far below 4 GiB)
+  const uint32_t byte_off = param_index * (LP ? 2u : 4u);
+  return *(const T*)((const char*)table + byte_off);
+}
+
+template <int F, bool LP>
+__device__ inline void unpack_raw(const typename RawEntry<F, LP>::T& r, float v[F]) {
+  if constexpr (LP) {
+    if constexpr (F == 2) {
+      v[0] = bf16_bits_to_f32(r & 0xffffu);
+      v[1] = bf16_bits_to_f32(r >> 16);
+    } else {
+      v[0] = bf16_bits_to_f32(r.x & 0xffffu);
+      v[1] = bf16_bits_to_f32(r.x >> 16);
+      v[2] = bf16_bits_to_f32(r.y & 0xffffu);
+      v[3] = bf16_bits_to_f32(r.y >> 16);
+    }
+  } else {
+    if constexpr (F == 2) {
+      v[0] = r.x;
+      v[1] = r.y;
+    } else {
+      v[0] = r.x;
+      v[1] = r.y;
+      v[2] = r.z;
+      v[3] = r.w;
+    }
+  }
+}
+
 // Encode the M segments whose (o, t0) / (d, t1) sit in sA / sB into act0.
+// Each wave walks its (sample, level) pairs U at a time: all 8U gathers are
+// issued before any is consumed (U = 4 for 4-byte entries).
 template <typename AT, int F, bool LP, int NWAVES>
 __device__ inline void encode_tile(const DevCfg& c, const void* table, const float4* sA, const float4* sB,
                                    const int* s_valid, AT* act0, int ld0, int M) {
+  typedef typename RawEntry<F, LP>::T Raw;
+  constexpr int U = sizeof(Raw) >= 16 ? 1 : 16 / (int)sizeof(Raw);  // 32..64 bytes of loads in flight per lane
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int SL = c.n_samples * c.n_levels;
+  const uint32_t hmask = (1u << c.log2_T) - 1u;
   for (int m = lane; m < M; m += 64) {
     const bool valid = s_valid[m] != 0;
     const float4 a = sA[m], b = sB[m];
     const float o[3] = {a.x, a.y, a.z}, d[3] = {b.x, b.y, b.z};
-    for (int sl = wave; sl < SL; sl += NWAVES) {
-      const int s = sl / c.n_levels, l = sl - s * c.n_levels;
-      float v[F];
-      if (valid) {
+    for (int sl0 = wave; sl0 < SL; sl0 += NWAVES * U) {
+      Raw raw[U][8];
+      float wx[U], wy[U], wz[U];
+      int col[U];
+      bool act[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int sl = sl0 + u * NWAVES;
+        act[u] = sl < SL;
+        const int s = act[u] ? sl / c.n_levels : 0;
+        const int l = act[u] ? sl - s * c.n_levels : 0;
+        col[u] = s * c.n_levels * F + l * F;
         float x[3];
         sample_position(c, o, d, a.w, b.w, s, x);
-        interp_level<F, LP>(c, table, l, x, v);
-      } else {
+        const int N = c.level_res[l];
+        const bool dense = (c.dense_mask >> l) & 1u;
+        int cx, cy, cz;
+        cell_weight(x[0], N, cx, wx[u]);
+        cell_weight(x[1], N, cy, wy[u]);
+        cell_weight(x[2], N, cz, wz[u]);
+        const uint32_t base = c.level_off[l];
+        const bool ld = act[u] && valid;
 #pragma unroll
-        for (int f = 0; f < F; ++f) v[f] = 0.0f;
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t idx = base + corner_index(dense, N, hmask, cx + (k & 1), cy + ((k >> 1) & 1),
+                                                   cz + ((k >> 2) & 1)) * F;
+          raw[u][k] = load_raw<F, LP>(table, ld ? idx : 0u);  // unconditional: no branch per gather
+        }
       }
-      store_features<AT, F>(act0 + (size_t)m * ld0 + s * c.n_levels * F + l * F, v);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!act[u]) continue;
+        float out[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) out[f] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float w = ((k & 1) ? wx[u] : 1.0f - wx[u]) * (((k >> 1) & 1) ? wy[u] : 1.0f - wy[u]) *
+                          (((k >> 2) & 1) ? wz[u] : 1.0f - wz[u]);
+          float v[F];
+          unpack_raw<F, LP>(raw[u][k], v);
+#pragma unroll
+          for (int f = 0; f < F; ++f) out[f] = __builtin_fmaf(w, v[f], out[f]);
+        }
+        if (!valid) {
+#pragma unroll
+          for (int f = 0; f < F; ++f) out[f] = 0.0f;
+        }
+        store_features<AT, F>(act0 + (size_t)m * ld0 + col[u], out);
+      }
     }
   }
 }

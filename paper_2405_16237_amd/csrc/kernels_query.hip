@@ -17,17 +17,22 @@
 
 namespace nbvh {
 
-constexpr int kQM = 64;  // slots per workgroup
+constexpr int kQM = 64;      // slots per workgroup
+constexpr int kQWaves = 8;   // waves per workgroup
+constexpr uint32_t kXcds = 8;  // accelerator complex dies of an MI355X; ray-queue partitions
+
+__device__ inline uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u; }
 
 template <typename AT>
 __host__ __device__ inline size_t query_lds_bytes(int n_in, int width) {
   const int ld0 = (n_in > width ? n_in : width) + Pad<AT>::v;
   const int ld1 = width + Pad<AT>::v;
-  return (size_t)kQM * (ld0 + ld1) * sizeof(AT) + (size_t)kQM * kOutPad * 4 + (size_t)kQM * 32 + kQM * 4 + 16;
+  return (size_t)kQM * (ld0 + ld1) * sizeof(AT) + (size_t)kQM * kOutPad * 4 + (size_t)kQM * 32 + kQM * 4 + 16 +
+         (size_t)kQM * 4 * 12;
 }
 
 template <typename AT, int F, bool LP>
-__global__ __launch_bounds__(256) void k_query_eval(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_query_eval(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
                                                     const nbvh_ray* __restrict__ rays,
                                                     const uint32_t* __restrict__ offsets,
                                                     const nbvh_segment* __restrict__ segs,
@@ -47,48 +52,65 @@ __global__ __launch_bounds__(256) void k_query_eval(DevCfg c, const void* __rest
   float4* sB = sA + kQM;
   int* s_valid = (int*)(sB + kQM);
   int* s_any = s_valid + kQM;
+  // slot state (owned by wave 0, lane = slot), kept in LDS to spare VGPRs
+  uint32_t* s_ray = (uint32_t*)(s_any + 4);
+  uint32_t* s_cur = s_ray + kQM;
+  uint32_t* s_end = s_cur + kQM;
+  uint32_t* s_leaf = s_end + kQM;
+  uint32_t* s_bleaf = s_leaf + kQM;
+  float* s_bt = (float*)(s_bleaf + kQM);
+  float* s_bn = s_bt + kQM;       // [3][kQM]
+  float* s_ba = s_bn + 3 * kQM;   // [3][kQM]
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t n_active = *n_active_p;
-
-  // slot state of wave 0 (lane = slot)
-  uint32_t ray = NBVH_MISS, cur = 0, end = 0, leaf = 0, best_leaf = NBVH_MISS;
-  float t0 = 0.f, t1 = 0.f, best_t = INFINITY;
-  float bn[3] = {0.f, 0.f, 0.f}, ba[3] = {0.f, 0.f, 0.f};
   bool exhausted = false;
+  const uint32_t first_part = xcc_id() % kXcds;
+  uint32_t part = first_part;
   uint32_t evaluated = 0;
+  if (wave == 0) s_ray[lane] = NBVH_MISS;
 
   while (true) {
     if (wave == 0) {
+      uint32_t ray = s_ray[lane];
       const bool is_free = (ray == NBVH_MISS);
-      if (!exhausted) {
-        const uint64_t mask = __ballot(is_free);
+      // free slots take the next rays of this XCD's eighth of the queue
+      // (neighbouring rays read the same table lines, which then stay in
+      // one L2); an exhausted eighth moves on to the next one
+      uint64_t mask = exhausted ? 0ull : __ballot(is_free);
+      while (mask) {
         const uint32_t nfree = (uint32_t)__popcll(mask);
-        if (nfree) {
-          const int leader = __ffsll((unsigned long long)mask) - 1;
-          uint32_t base = 0;
-          if (lane == leader) base = atomicAdd(counter, nfree);
-          base = __shfl(base, leader);
-          if (is_free) {
-            const uint32_t idx = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-            if (idx < n_active) {
-              ray = active[idx];
-              cur = offsets[ray];
-              end = offsets[ray + 1];
-              best_t = INFINITY;
-              best_leaf = NBVH_MISS;
-              const float4* rp = (const float4*)(rays + ray);
-              const float4 ra = rp[0], rb = rp[1];
-              const nbvh_segment sg = segs[cur];
-              t0 = sg.t0;
-              t1 = sg.t1;
-              leaf = sg.leaf;
-              sA[lane] = make_float4(ra.x, ra.y, ra.z, t0);
-              sB[lane] = make_float4(rb.x, rb.y, rb.z, t1);
-            }
+        const uint32_t r0 = (uint32_t)(((uint64_t)n_active * part) / kXcds);
+        const uint32_t r1 = (uint32_t)(((uint64_t)n_active * (part + 1)) / kXcds);
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(counter + part, nfree);
+        base = __shfl(base, leader);
+        if ((mask >> lane) & 1ull) {
+          const uint32_t idx = r0 + base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+          if (idx < r1) {
+            ray = active[idx];
+            const uint32_t cur = offsets[ray];
+            s_ray[lane] = ray;
+            s_cur[lane] = cur;
+            s_end[lane] = offsets[ray + 1];
+            s_bt[lane] = INFINITY;
+            s_bleaf[lane] = NBVH_MISS;
+            const float4* rp = (const float4*)(rays + ray);
+            const float4 ra = rp[0], rb = rp[1];
+            const nbvh_segment sg = segs[cur];
+            s_leaf[lane] = sg.leaf;
+            sA[lane] = make_float4(ra.x, ra.y, ra.z, sg.t0);
+            sB[lane] = make_float4(rb.x, rb.y, rb.z, sg.t1);
           }
-          if (base + nfree >= n_active) exhausted = true;
         }
+        if (r0 + base + nfree < r1) break;  // this eighth still has rays
+        part = (part + 1) % kXcds;
+        if (part == first_part) {
+          exhausted = true;
+          break;
+        }
+        mask = __ballot(ray == NBVH_MISS);
       }
       s_valid[lane] = (ray != NBVH_MISS) ? 1 : 0;
       const uint64_t live = __ballot(ray != NBVH_MISS);
@@ -97,53 +119,57 @@ __global__ __launch_bounds__(256) void k_query_eval(DevCfg c, const void* __rest
     __syncthreads();
     if (*s_any == 0) break;
 
-    encode_tile<AT, F, LP, 4>(c, table, sA, sB, s_valid, act0, ld0, kQM);
+    encode_tile<AT, F, LP, kQWaves>(c, table, sA, sB, s_valid, act0, ld0, kQM);
     __syncthreads();
-    mlp_forward_tile<kQM, 4, AT>(c, W, act0, ld0, act1, ld1, z, kOutPad);
+    mlp_forward_tile<kQM, kQWaves, AT>(c, W, act0, ld0, act1, ld1, z, kOutPad);
 
-    if (wave == 0 && ray != NBVH_MISS) {
+    if (wave == 0 && s_valid[lane]) {
       ++evaluated;
+      const uint32_t ray = s_ray[lane];
+      const float t0 = sA[lane].w, t1 = sB[lane].w;
+      float best_t = s_bt[lane];
       const float* zr = z + lane * kOutPad;
       if (zr[0] > 0.0f) {
         const float t = t0 + sigmoidf_(zr[1]) * (t1 - t0);
         if (t < best_t) {
           best_t = t;
-          best_leaf = leaf;
-          bn[0] = zr[2];
-          bn[1] = zr[3];
-          bn[2] = zr[4];
+          s_bt[lane] = t;
+          s_bleaf[lane] = s_leaf[lane];
+          s_bn[lane] = zr[2];
+          s_bn[kQM + lane] = zr[3];
+          s_bn[2 * kQM + lane] = zr[4];
           if (c.n_out >= 8) {
-            ba[0] = sigmoidf_(zr[5]);
-            ba[1] = sigmoidf_(zr[6]);
-            ba[2] = sigmoidf_(zr[7]);
+            s_ba[lane] = sigmoidf_(zr[5]);
+            s_ba[kQM + lane] = sigmoidf_(zr[6]);
+            s_ba[2 * kQM + lane] = sigmoidf_(zr[7]);
           }
         }
       }
-      ++cur;
+      const uint32_t cur = s_cur[lane] + 1;
+      s_cur[lane] = cur;
       bool more = false;
-      if (cur < end) {
+      if (cur < s_end[lane]) {
         const nbvh_segment sg = segs[cur];
         if (sg.t0 < best_t) {
           more = true;
-          t0 = sg.t0;
-          t1 = sg.t1;
-          leaf = sg.leaf;
-          sA[lane].w = t0;
-          sB[lane].w = t1;
+          s_leaf[lane] = sg.leaf;
+          sA[lane].w = sg.t0;
+          sB[lane].w = sg.t1;
         }
       }
       if (!more) {
         float4* h = (float4*)(hits + ray);
-        if (best_leaf == NBVH_MISS) {
+        const uint32_t bl = s_bleaf[lane];
+        if (bl == NBVH_MISS) {
           h[0] = make_float4(0.f, 0.f, 0.f, 0.f);
           h[1] = make_float4(0.f, 0.f, 0.f, __uint_as_float(NBVH_MISS));
         } else {
-          h[0] = make_float4(best_t, bn[0], bn[1], bn[2]);
-          h[1] = make_float4(ba[0], ba[1], ba[2], __uint_as_float(best_leaf));
+          const bool alb = c.n_out >= 8;
+          h[0] = make_float4(best_t, s_bn[lane], s_bn[kQM + lane], s_bn[2 * kQM + lane]);
+          h[1] = make_float4(alb ? s_ba[lane] : 0.f, alb ? s_ba[kQM + lane] : 0.f, alb ? s_ba[2 * kQM + lane] : 0.f,
+                             __uint_as_float(bl));
         }
-        ray = NBVH_MISS;
-        bn[0] = bn[1] = bn[2] = 0.f;
-        ba[0] = ba[1] = ba[2] = 0.f;
+        s_ray[lane] = NBVH_MISS;
       }
     }
     __syncthreads();
@@ -182,14 +208,14 @@ __global__ __launch_bounds__(256) void k_active_rays(const uint32_t* __restrict_
 
 nbvh_status launch_active_rays(const LaunchCtx& L, const uint32_t* offsets, uint32_t n_rays, nbvh_hit* hits,
                                uint32_t* active, uint32_t* misc) {
-  k_zero_u32<<<1, 64, 0, L.stream>>>(misc, 2);
+  k_zero_u32<<<1, 64, 0, L.stream>>>(misc, 1 + kXcds);
   if (n_rays) k_active_rays<<<(n_rays + 255) / 256, 256, 0, L.stream>>>(offsets, n_rays, hits, active, misc);
   return check_launch("active_rays");
 }
 
 // Forward of probe segments: tile of 64 probes per workgroup, z -> global.
 template <typename AT, int F, bool LP>
-__global__ __launch_bounds__(256) void k_forward(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_forward(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
                                                  const nbvh_probe* __restrict__ probes, uint32_t n,
                                                  float* __restrict__ zout) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -211,9 +237,9 @@ __global__ __launch_bounds__(256) void k_forward(DevCfg c, const void* __restric
     s_valid[threadIdx.x] = v ? 1 : 0;
   }
   __syncthreads();
-  encode_tile<AT, F, LP, 4>(c, table, sA, sB, s_valid, act0, ld0, kQM);
+  encode_tile<AT, F, LP, kQWaves>(c, table, sA, sB, s_valid, act0, ld0, kQM);
   __syncthreads();
-  mlp_forward_tile<kQM, 4, AT>(c, W, act0, ld0, act1, ld1, z, kOutPad);
+  mlp_forward_tile<kQM, kQWaves, AT>(c, W, act0, ld0, act1, ld1, z, kOutPad);
   for (int e = threadIdx.x; e < kQM * c.n_out; e += blockDim.x) {
     const int m = e / c.n_out, o = e - m * c.n_out;
     if (base + m < n) zout[(size_t)(base + m) * c.n_out + o] = z[m * kOutPad + o];
@@ -264,7 +290,7 @@ static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const 
   const AT* W = (sizeof(AT) == 2) ? (const AT*)L.params_lp : (const AT*)L.params;
   const void* table = LP ? (const void*)L.params_lp : (const void*)L.params;
   ProfScope ps(L.prof, NBVH_K_QUERY_EVAL, L.stream);
-  kern<<<grid, 256, lds, L.stream>>>(c, table, W, rays, offsets, segs, active, n_active, counter, hits,
+  kern<<<grid, 64 * kQWaves, lds, L.stream>>>(c, table, W, rays, offsets, segs, active, n_active, counter, hits,
                                      offsets + n_rays_bound, capacity, L.state);
   return check_launch("query_eval");
 }
@@ -291,7 +317,7 @@ static nbvh_status forward_t(const LaunchCtx& L, const nbvh_probe* probes, uint3
   const void* table = LP ? (const void*)L.params_lp : (const void*)L.params;
   if (n == 0) return NBVH_OK;
   ProfScope ps(L.prof, NBVH_K_FORWARD, L.stream);
-  kern<<<(n + kQM - 1) / kQM, 256, lds, L.stream>>>(c, table, W, probes, n, z);
+  kern<<<(n + kQM - 1) / kQM, 64 * kQWaves, lds, L.stream>>>(c, table, W, probes, n, z);
   return check_launch("forward");
 }
 

@@ -10,9 +10,10 @@
 //  k_wgrad        dL/dW_k = sum_b g_k[b] h_k[b]^T as split-K MFMA GEMMs into
 //                 per-split partials; k_wgrad_reduce adds them into grad in
 //                 a fixed order.
-//  k_scatter      recomputes every sample's cell corners and weights (no
-//                 stored encodings) and adds w * dL/du into the table
-//                 gradient with hardware FP32 atomics.
+//  k_scatter_*    recompute every sample's cell corners and weights (no
+//                 stored encodings) and add w * dL/du into the table
+//                 gradient (LDS for the coarsest levels, coalesced FP32
+//                 atomics for the rest).
 //  k_check_finite / k_adam / k_adam_finalize   dense Adam with loss-scale
 //                 removal and non-finite skip; writes the BF16 shadow and the
 //                 transposed weight copies the dgrad reads.
@@ -23,7 +24,7 @@
 namespace nbvh {
 
 constexpr int kTM = 64;
-constexpr int kTWaves = 4;
+constexpr int kTWaves = 8;
 constexpr int kGPad = 32;  // gradient rows of the output layer padded to 32
 
 __host__ __device__ inline int fan_out_pad(const DevCfg& c, int k) {
@@ -100,7 +101,7 @@ __device__ inline float bce_logits(float z, float h) {
 __device__ inline float sgnf(float v) { return (float)((v > 0.0f) - (v < 0.0f)); }
 
 template <typename AT, int F, bool LP, bool WITH_LABELS>
-__global__ __launch_bounds__(256) void k_train_tile(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_train_tile(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
                                                     const AT* __restrict__ WT, const nbvh_probe* __restrict__ probes,
                                                     const nbvh_label* __restrict__ labels,
                                                     const float* __restrict__ dz_in, uint32_t n, TrainPtrs P,
@@ -345,36 +346,157 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(DevCfg c, const float* __r
 }
 
 // ---------------------------------------------------------------------------
-// table-gradient scatter: thread per (probe, sample, level), probes fastest
-template <int F>
-__global__ __launch_bounds__(256) void k_scatter(DevCfg c, const nbvh_probe* __restrict__ probes, uint32_t n,
-                                                 const float* __restrict__ duT, uint64_t ldb, float* __restrict__ grad) {
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t total = (uint64_t)n * c.n_samples * c.n_levels;
-  if (t >= total) return;
-  const uint32_t sl = (uint32_t)(t / n);
-  const uint32_t p = (uint32_t)(t - (uint64_t)sl * n);
-  const int s = sl / c.n_levels, l = sl - s * c.n_levels;
-  float g[F];
-  bool any = false;
-#pragma unroll
-  for (int f = 0; f < F; ++f) {
-    g[f] = duT[(size_t)(sl * F + f) * ldb + p];
-    any = any || g[f] != 0.0f;
+// Table-gradient scatter. Global FP32 atomics cost one request per distinct
+// cache line a wave instruction touches, so the scatter is organised to put
+// many updates into few lines:
+//  - coarse dense levels small enough for LDS are accumulated per workgroup
+//    with LDS atomics and flushed once with fully coalesced global atomics;
+//  - every other level uses 2F lanes per (probe, level): lane (dx, f) owns one
+//    feature of one x-neighbour, so the 2F lanes of an x-pair update one
+//    contiguous run (always on dense levels; when the cell's x is even on
+//    hashed ones, since the spatial hash keeps x's low bit);
+//  - consecutive samples of a ray that fall into the same cell are summed in
+//    registers before the atomics are issued.
+// Corner indices and weights are recomputed from the probes (nothing from the
+// forward pass is stored).
+
+// levels [0, n_lds) go through LDS; returns n_lds and their float count
+static int coarse_lds_levels(const DevCfg& c, size_t budget_bytes, uint32_t* n_floats) {
+  uint64_t acc = 0;
+  int nl = 0;
+  for (int l = 0; l < c.n_levels; ++l) {
+    if (!((c.dense_mask >> l) & 1u)) break;
+    const uint64_t r1 = (uint64_t)c.level_res[l] + 1;
+    const uint64_t fl = r1 * r1 * r1 * c.n_features;
+    if ((acc + fl) * 4 > budget_bytes) break;
+    acc += fl;
+    ++nl;
   }
-  if (!any) return;
+  *n_floats = (uint32_t)acc;
+  return nl;
+}
+
+template <int F>
+__global__ __launch_bounds__(1024) void k_scatter_lds(DevCfg c, int n_lds, uint32_t n_floats,
+                                                      const nbvh_probe* __restrict__ probes, uint32_t n,
+                                                      const float* __restrict__ duT, uint64_t ldb,
+                                                      float* __restrict__ grad) {
+  extern __shared__ __align__(16) float acc[];
+  for (uint32_t i = threadIdx.x; i < n_floats; i += blockDim.x) acc[i] = 0.0f;
+  __syncthreads();
+  const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const uint32_t p0 = blockIdx.x * chunk;
+  const uint32_t p1 = min(n, p0 + chunk);
+  const uint32_t np = p1 > p0 ? p1 - p0 : 0;
+  const uint32_t tasks = np * c.n_samples * n_lds;
+  for (uint32_t t = threadIdx.x; t < tasks; t += blockDim.x) {
+    const uint32_t p = p0 + t % np;
+    const uint32_t sl = t / np;
+    const int s = sl / n_lds, l = sl - s * n_lds;
+    float g[F];
+    bool any = false;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      g[f] = duT[(size_t)((s * c.n_levels + l) * F + f) * ldb + p];
+      any = any || g[f] != 0.0f;
+    }
+    if (!any) continue;
+    const float4* pp = (const float4*)(probes + p);
+    const float4 a = pp[0], b = pp[1];
+    const float o[3] = {a.x, a.y, a.z}, d[3] = {b.x, b.y, b.z};
+    float x[3];
+    sample_position(c, o, d, a.w, b.w, s, x);
+    uint32_t idx[8];
+    float w[8];
+    corners_level(c, l, x, idx, w);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int f = 0; f < F; ++f) atomicAdd(&acc[idx[k] + f], w[k] * g[f]);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n_floats; i += blockDim.x) {
+    const float v = acc[i];
+    if (v != 0.0f) unsafeAtomicAdd(grad + i, v);  // levels [0, n_lds) start at parameter 0
+  }
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void k_scatter_pairs(DevCfg c, int l_begin, const nbvh_probe* __restrict__ probes,
+                                                       uint32_t n, const float* __restrict__ duT, uint64_t ldb,
+                                                       float* __restrict__ grad) {
+  constexpr int LPT = 2 * F;  // lanes per (probe, level)
+  const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t task = gt / LPT;
+  const int q = (int)(gt % LPT);
+  const int dx = q / F, f = q - dx * F;
+  const uint32_t nl = (uint32_t)(c.n_levels - l_begin);
+  if (task >= (uint64_t)n * nl) return;
+  const uint32_t li = (uint32_t)(task / n);
+  const uint32_t p = (uint32_t)(task - (uint64_t)li * n);
+  const int l = l_begin + (int)li;
+  const int N = c.level_res[l];
+  const bool dense = (c.dense_mask >> l) & 1u;
+  const uint32_t mask = (1u << c.log2_T) - 1u;
+  const uint32_t base = c.level_off[l];
   const float4* pp = (const float4*)(probes + p);
   const float4 a = pp[0], b = pp[1];
   const float o[3] = {a.x, a.y, a.z}, d[3] = {b.x, b.y, b.z};
-  float x[3];
-  sample_position(c, o, d, a.w, b.w, s, x);
-  uint32_t idx[8];
-  float w[8];
-  corners_level(c, l, x, idx, w);
+  int ccx = -1, ccy = -1, ccz = -1;
+  uint32_t idx[4] = {0u, 0u, 0u, 0u};
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int s = 0; s < c.n_samples; ++s) {
+    const float g = duT[(size_t)((s * c.n_levels + l) * F + f) * ldb + p];
+    float x[3];
+    sample_position(c, o, d, a.w, b.w, s, x);
+    int cx, cy, cz;
+    float wx, wy, wz;
+    cell_weight(x[0], N, cx, wx);
+    cell_weight(x[1], N, cy, wy);
+    cell_weight(x[2], N, cz, wz);
+    if (cx != ccx || cy != ccy || cz != ccz) {
+      if (ccx >= 0) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+        for (int j = 0; j < 4; ++j)
+          if (acc[j] != 0.0f) unsafeAtomicAdd(grad + idx[j] + f, acc[j]);
+      }
+      ccx = cx;
+      ccy = cy;
+      ccz = cz;
 #pragma unroll
-    for (int f = 0; f < F; ++f) unsafeAtomicAdd(grad + idx[k] + f, w[k] * g[f]);
+      for (int j = 0; j < 4; ++j) {
+        idx[j] = base + corner_index(dense, N, mask, (uint32_t)(cx + dx), (uint32_t)(cy + (j & 1)),
+                                     (uint32_t)(cz + (j >> 1))) * F;
+        acc[j] = 0.0f;
+      }
+    }
+    const float wxs = dx ? wx : 1.0f - wx;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float w = (wxs * ((j & 1) ? wy : 1.0f - wy)) * ((j >> 1) ? wz : 1.0f - wz);
+      acc[j] = __builtin_fmaf(w, g, acc[j]);
+    }
+  }
+  if (ccx >= 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (acc[j] != 0.0f) unsafeAtomicAdd(grad + idx[j] + f, acc[j]);
+  }
+}
+
+template <int F>
+static void launch_scatter(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, const float* duT, uint64_t ldb) {
+  const DevCfg& c = L.cfg;
+  uint32_t n_floats = 0;
+  const int n_lds = coarse_lds_levels(c, 144 * 1024, &n_floats);
+  if (n_lds > 0) {
+    const size_t lds = (size_t)n_floats * 4;
+    hipFuncSetAttribute((const void*)k_scatter_lds<F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_scatter_lds<F><<<L.n_cu, 1024, lds, L.stream>>>(c, n_lds, n_floats, probes, n, duT, ldb, L.grad);
+  }
+  if (n_lds < c.n_levels) {
+    const uint64_t threads = (uint64_t)n * (c.n_levels - n_lds) * 2 * F;
+    k_scatter_pairs<F><<<(uint32_t)((threads + 255) / 256), 256, 0, L.stream>>>(c, n_lds, probes, n, duT, ldb, L.grad);
   }
 }
 
@@ -590,12 +712,12 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
     if (labels) {
       auto kern = k_train_tile<AT, F, LP, true>;
       set_lds(kern, lds);
-      kern<<<T.n_tiles, 256, lds, L.stream>>>(c, table, W, WT, probes, labels, nullptr, n, P, L.state, L.w_hit,
+      kern<<<T.n_tiles, 64 * kTWaves, lds, L.stream>>>(c, table, W, WT, probes, labels, nullptr, n, P, L.state, L.w_hit,
                                                L.w_t, L.w_normal);
     } else {
       auto kern = k_train_tile<AT, F, LP, false>;
       set_lds(kern, lds);
-      kern<<<T.n_tiles, 256, lds, L.stream>>>(c, table, W, WT, probes, nullptr, dz_in, n, P, L.state, L.w_hit,
+      kern<<<T.n_tiles, 64 * kTWaves, lds, L.stream>>>(c, table, W, WT, probes, nullptr, dz_in, n, P, L.state, L.w_hit,
                                                L.w_t, L.w_normal);
     }
   }
@@ -612,8 +734,7 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
   }
   {
     ProfScope ps(L.prof, NBVH_K_SCATTER, L.stream);
-    const uint64_t tasks = (uint64_t)n * c.n_samples * c.n_levels;
-    k_scatter<F><<<(uint32_t)((tasks + 255) / 256), 256, 0, L.stream>>>(c, probes, n, P.duT, kb, L.grad);
+    launch_scatter<F>(L, probes, n, P.duT, kb);
   }
   return check_launch("train");
 }

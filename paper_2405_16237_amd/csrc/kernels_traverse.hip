@@ -255,7 +255,7 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
   ProfScope ps(L.prof, NBVH_K_TRAVERSE, L.stream);
   const int grid = (int)((n_rays + 255) / 256);
   if (n_active) {
-    k_zero_u32<<<1, 64, 0, L.stream>>>(n_active, 2);  // n_active and the query's ray counter
+    k_zero_u32<<<1, 64, 0, L.stream>>>(n_active, 9);  // n_active and the query's 8 ray-queue counters
   }
   if (n_rays > 0)
     k_traverse_count<<<grid, 256, 0, L.stream>>>(L.nodes, rays, n_rays, scratch_counts, hits, active, n_active);

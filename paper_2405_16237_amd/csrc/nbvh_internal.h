@@ -42,7 +42,7 @@ struct DevCfg {
   uint32_t level_off[NBVH_MAX_LEVELS];  // first parameter (not entry) of level l
   float scene_lo[3];
   float inv_side;             // correctly rounded 1/scene_side
-  float inv_S;                // unused by the sampling arithmetic; kept for kernels that need 1/S
+  float frac[16];             // (s + 1/2) / S, correctly rounded on the host
   // parameter layout (elements): W_k starts at w_off[k] inside params
   uint64_t n_table, n_mlp, n_params;
   uint64_t n_wt;                 // elements of the transposed weight copies
@@ -79,7 +79,7 @@ __device__ __host__ inline uint16_t f32_to_bf16_bits(float f) {
 // ---------------------------------------------------------------------------
 __device__ inline void sample_position(const DevCfg& c, const float o[3], const float d[3], float t0,
                                        float t1, int s, float x[3]) {
-  float frac = ((float)s + 0.5f) / (float)c.n_samples;
+  float frac = c.frac[s];
   float span = t1 - t0;
   float step = frac * span;
   float ts = t0 + step;
@@ -175,6 +175,26 @@ __device__ inline void interp_level(const DevCfg& c, const void* table, int l, c
     load_entry<F, LP>(table, base + idx * F, v);
 #pragma unroll
     for (int f = 0; f < F; ++f) out[f] = __builtin_fmaf(w, v[f], out[f]);
+  }
+}
+
+// Corner entry indices (parameter index of feature 0) and weights of level
+// l, split from the loads so that callers can issue many gathers at once.
+__device__ inline void corner_params(const DevCfg& c, int l, const float x[3], uint32_t idx[8], float wts[8]) {
+  const int N = c.level_res[l];
+  const bool dense = (c.dense_mask >> l) & 1u;
+  const uint32_t mask = (1u << c.log2_T) - 1u;
+  int cx, cy, cz;
+  float wx, wy, wz;
+  cell_weight(x[0], N, cx, wx);
+  cell_weight(x[1], N, cy, wy);
+  cell_weight(x[2], N, cz, wz);
+  const uint32_t base = c.level_off[l];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+    wts[k] = (dx ? wx : 1.0f - wx) * (dy ? wy : 1.0f - wy) * (dz ? wz : 1.0f - wz);
+    idx[k] = base + corner_index(dense, N, mask, cx + dx, cy + dy, cz + dz) * c.n_features;
   }
 }
 
