@@ -167,6 +167,22 @@ typedef struct {
 
 typedef struct nbvh_ctx nbvh_ctx; /* opaque host handle */
 
+/* Launch-shape knobs (defaults shown). Results do not depend on them beyond
+ * floating-point summation order; an autotuner may search them. Changing
+ * wgrad_splits changes nbvh_workspace_bytes. */
+typedef struct {
+  int32_t query_waves;      /* waves per query workgroup: 4 or 8 (8) */
+  int32_t query_unroll;     /* (sample, level) pairs gathered together: 1, 2, 4; 0 = by entry size (0) */
+  int32_t query_wgs_per_cu; /* persistent query workgroups per compute unit; 0 = as many as LDS allows (0) */
+  int32_t train_waves;      /* waves per training-tile workgroup: 4 or 8 (8) */
+  int32_t wgrad_splits;     /* batch splits of the weight-gradient GEMMs: 1..256 (32) */
+  int32_t scatter_lds_kb;   /* LDS budget for coarse levels in the table-gradient scatter: 0..144 (144) */
+} nbvh_tuning;
+
+/* Read / replace the context's launch knobs (validated). */
+nbvh_status nbvh_get_tuning(const nbvh_ctx* ctx, nbvh_tuning* out);
+nbvh_status nbvh_set_tuning(nbvh_ctx* ctx, const nbvh_tuning* t);
+
 /* Parameter counts for a configuration (no context needed). Returns
  * NBVH_ERR_INVALID_ARG for unsupported configurations. */
 nbvh_status nbvh_param_count(const nbvh_config* cfg, uint64_t* n_table, uint64_t* n_mlp);
@@ -277,6 +293,37 @@ nbvh_status nbvh_train_step(nbvh_ctx* ctx, const nbvh_probe* probes_dev, const n
 /* Loss and dL/dz only (no back-propagation): dz_dev may be NULL. */
 nbvh_status nbvh_loss(nbvh_ctx* ctx, const float* z_dev, const nbvh_label* labels_dev, uint64_t n,
                       float* loss_dev, float* dz_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* ---- Several N-BVH objects in one scene --------------------------------
+ * Objects that share the network shape (levels, features, samples, level
+ * resolutions, MLP, precision; table sizes may differ) are grouped so that a
+ * ray batch is answered in one evaluation launch: each object is traversed,
+ * one persistent kernel drains every object's ray queue (a workgroup's tile
+ * always holds segments of a single object, so the MLP runs on that object's
+ * weights), and a merge keeps each ray's closest predicted hit across
+ * objects (ties: lower object index). In batch hit records
+ * leaf = (object << 24) | leaf id. At most 16 objects of fewer than 2^24
+ * leaves each. The contexts must stay alive while the batch is used. */
+typedef struct nbvh_batch nbvh_batch;
+
+/* Device bytes of the per-object descriptor table. */
+size_t nbvh_batch_desc_bytes(uint32_t n_objects);
+
+/* Validate and group the objects; uploads their descriptors into
+ * descs_dev (caller-owned) and synchronises `stream` once. */
+nbvh_status nbvh_batch_create(nbvh_ctx* const* ctxs, uint32_t n_objects, void* descs_dev, size_t descs_bytes,
+                              void* stream, nbvh_batch** out);
+
+/* Workspace bytes for batch queries of up to max_rays rays with up to
+ * seg_capacity segments per object. */
+size_t nbvh_batch_workspace_bytes(const nbvh_batch* b, uint64_t max_rays, uint64_t seg_capacity);
+
+/* Neural ray query against all objects of the batch (see nbvh_query for the
+ * per-object semantics). */
+nbvh_status nbvh_batch_query(nbvh_batch* b, const nbvh_ray* rays_dev, uint64_t n_rays, nbvh_hit* hits_dev,
+                             uint64_t seg_capacity, void* ws_dev, size_t ws_bytes, void* stream);
+
+void nbvh_batch_destroy(nbvh_batch* b);
 
 /* Kernel groups reported by the profiler. */
 typedef enum {

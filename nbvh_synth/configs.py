@@ -135,3 +135,33 @@ C2 = dict(n_tris=1_003_520, n_leaves=1024, width=1920, height=1080, net=C2_NET,
 C3 = dict(C2, batch=1 << 18)
 C5 = dict(n_tris=3_996_180, n_leaves=16384, n_rays=1 << 24, net=C5_NET,
           feature_init="normal", feature_scale=1e-2)
+
+
+def c4_objects():
+    """The batched scene: 8 displaced icospheres on a 4 x 2 grid (spacing 3),
+    triangle counts log-spaced over 50,000..1,997,120, 256 * 2^floor(5k/7)
+    leaves and T = 2^(16 + floor(4k/7)) hash entries for object k, seeds
+    100 + k; network otherwise as in the 1920x1080 workload."""
+    objs = []
+    for k in range(8):
+        n_tris = int(round(50_000 * (1_997_120 / 50_000) ** (k / 7)))
+        leaves = 256 * 2 ** ((5 * k) // 7)
+        log2_T = 16 + (4 * k) // 7
+        offset = ((k % 4 - 1.5) * 3.0, (k // 4 - 0.5) * 3.0, 0.0)
+        net = NetConfig(16, 2, log2_T, 8, 16, 1.38, 128, 4, 5)
+        objs.append(dict(n_tris=n_tris, n_leaves=leaves, seed=100 + k, offset=offset, net=net))
+    return objs
+
+
+def c4_rays(boxes_all: np.ndarray, n_rays: int, seed: int = 107, lo: int = 1, hi: int = 32):
+    """Rays from the scene's bounding sphere towards random points of the
+    scene box, subsampled so the number of leaf boxes crossed follows a
+    log-uniform mix over [lo, hi]."""
+    blo = boxes_all[:, :3].min(0).astype(np.float64)
+    bhi = boxes_all[:, 3:].max(0).astype(np.float64)
+    c = 0.5 * (blo + bhi)
+    r = 0.5 * float(np.linalg.norm(bhi - blo)) * 1.05
+    cand = scene.sphere_rays(c, r, blo, bhi, 4 * n_rays, seed)
+    counts = scene.box_crossings(boxes_all, cand)
+    idx = scene.log_uniform_subsample(counts, lo, hi, n_rays, seed + 1)
+    return cand[idx], counts[idx]

@@ -259,3 +259,99 @@ void tb_closest_brute(const double* verts, const int32_t* tris, int64_t nt, cons
     v_out[r] = bv;
   }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Number of boxes each ray crosses (double precision, inclusive), used only */
+/* to shape the segment-count mix of generated ray sets. A median-split BVH  */
+/* over the boxes prunes the search.                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double lo[3], hi[3];
+  int64_t a, b; /* inner: children; leaf: a = box index, b = -1 */
+} bx_node;
+
+static const double* g_bx;
+static int64_t bx_build_rec(bx_node* nodes, int64_t* n_nodes, int64_t* idx, int64_t first, int64_t count,
+                            double* cen) {
+  int64_t id = (*n_nodes)++;
+  bx_node* n = &nodes[id];
+  for (int a = 0; a < 3; ++a) {
+    n->lo[a] = INFINITY;
+    n->hi[a] = -INFINITY;
+  }
+  double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = 0; i < count; ++i) {
+    const double* bb = g_bx + 6 * idx[first + i];
+    for (int a = 0; a < 3; ++a) {
+      if (bb[a] < n->lo[a]) n->lo[a] = bb[a];
+      if (bb[3 + a] > n->hi[a]) n->hi[a] = bb[3 + a];
+      double c = cen[3 * idx[first + i] + a];
+      if (c < clo[a]) clo[a] = c;
+      if (c > chi[a]) chi[a] = c;
+    }
+  }
+  if (count == 1) {
+    n->a = idx[first];
+    n->b = -1;
+    return id;
+  }
+  int axis = 0;
+  for (int a = 1; a < 3; ++a)
+    if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+  int64_t half = count / 2;
+  select_kth(idx + first, count, half, cen, axis);
+  int64_t l = bx_build_rec(nodes, n_nodes, idx, first, half, cen);
+  int64_t r = bx_build_rec(nodes, n_nodes, idx, first + half, count - half, cen);
+  nodes[id].a = l;
+  nodes[id].b = r;
+  return id;
+}
+
+static int bx_hit(const double lo[3], const double hi[3], const double* o, const double* d) {
+  double tn = 0.0, tf = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] == 0.0) {
+      if (o[a] < lo[a] || o[a] > hi[a]) return 0;
+      continue;
+    }
+    double ta = (lo[a] - o[a]) / d[a], tb = (hi[a] - o[a]) / d[a];
+    if (ta > tb) { double s = ta; ta = tb; tb = s; }
+    if (ta > tn) tn = ta;
+    if (tb < tf) tf = tb;
+  }
+  return tn <= tf;
+}
+
+void bx_count(const double* boxes, int64_t n_boxes, const double* o, const double* d, int64_t n_rays,
+              int32_t* counts) {
+  int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)n_boxes);
+  double* cen = (double*)malloc(sizeof(double) * 3 * (size_t)n_boxes);
+  bx_node* nodes = (bx_node*)malloc(sizeof(bx_node) * (size_t)(2 * n_boxes));
+  for (int64_t i = 0; i < n_boxes; ++i) {
+    idx[i] = i;
+    for (int a = 0; a < 3; ++a) cen[3 * i + a] = 0.5 * (boxes[6 * i + a] + boxes[6 * i + 3 + a]);
+  }
+  int64_t nn = 0;
+  g_bx = boxes;
+  bx_build_rec(nodes, &nn, idx, 0, n_boxes, cen);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t r = 0; r < n_rays; ++r) {
+    int64_t stack[128];
+    int sp = 0, c = 0;
+    stack[sp++] = 0;
+    while (sp) {
+      const bx_node* nd = &nodes[stack[--sp]];
+      if (!bx_hit(nd->lo, nd->hi, o + 3 * r, d + 3 * r)) continue;
+      if (nd->b < 0) {
+        ++c;
+      } else {
+        stack[sp++] = nd->a;
+        stack[sp++] = nd->b;
+      }
+    }
+    counts[r] = c;
+  }
+  free(idx);
+  free(cen);
+  free(nodes);
+}

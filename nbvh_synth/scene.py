@@ -56,6 +56,7 @@ def _lib():
             lib.tb_free.argtypes = [P]
             lib.tb_closest.argtypes = [P, P, P, P, P, I, P, P, P, P]
             lib.tb_closest_brute.argtypes = [P, P, I, P, P, P, P, I, P, P, P, P]
+            lib.bx_count.argtypes = [P, I, P, P, I, P]
             _LIB = lib
     return _LIB
 
@@ -229,12 +230,13 @@ def scene_cube(boxes: np.ndarray):
 # --------------------------------------------------------------------------
 # rays
 # --------------------------------------------------------------------------
-def pinhole_rays(width: int, height: int, eye=(0.0, 0.0, 3.0), fov_deg: float = 45.0):
-    """Camera at `eye` looking at the origin, up +y, vertical field of view
+def pinhole_rays(width: int, height: int, eye=(0.0, 0.0, 3.0), fov_deg: float = 45.0, target=(0.0, 0.0, 0.0)):
+    """Camera at `eye` looking at `target`, up +y, vertical field of view
     fov_deg, one ray through each pixel centre. Returns [H*W][8] float32 rows
     (o.xyz, tmin, d.xyz, tmax) with tmin = 0 and tmax = +inf."""
     eye = np.asarray(eye, dtype=np.float64)
-    fwd = -eye / np.linalg.norm(eye)
+    fwd = np.asarray(target, dtype=np.float64) - eye
+    fwd /= np.linalg.norm(fwd)
     up0 = np.array([0.0, 1.0, 0.0])
     right = np.cross(fwd, up0)
     right /= np.linalg.norm(right)
@@ -426,3 +428,51 @@ def cosine_bounces(points: np.ndarray, normals: np.ndarray, count: int, seed: in
     rays[:, 4:7] = d
     rays[:, 7] = np.inf
     return rays
+
+
+def box_crossings(boxes: np.ndarray, rays: np.ndarray) -> np.ndarray:
+    """Number of boxes each ray crosses for t >= 0 (double precision; used to
+    shape ray sets, not by the neural query)."""
+    b = np.ascontiguousarray(boxes, dtype=np.float64)
+    o = np.ascontiguousarray(rays[:, 0:3], dtype=np.float64)
+    d = np.ascontiguousarray(rays[:, 4:7], dtype=np.float64)
+    out = np.zeros(rays.shape[0], dtype=np.int32)
+    _lib().bx_count(_ptr(b), b.shape[0], _ptr(o), _ptr(d), o.shape[0], _ptr(out))
+    return out
+
+
+def sphere_rays(center, radius, box_lo, box_hi, n, seed):
+    """Origins uniform on a sphere, each aimed at a uniform point of a box."""
+    rng = np.random.default_rng(seed)
+    o = np.asarray(center, np.float64)[None, :] + radius * _unit_vectors(rng, n)
+    tgt = rng.uniform(np.asarray(box_lo, np.float64), np.asarray(box_hi, np.float64), size=(n, 3))
+    d = tgt - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rays = np.zeros((n, 8), dtype=np.float32)
+    rays[:, 0:3] = o
+    rays[:, 4:7] = d
+    rays[:, 7] = np.inf
+    return rays
+
+
+def log_uniform_subsample(counts: np.ndarray, lo: int, hi: int, n_out: int, seed: int) -> np.ndarray:
+    """Indices of a subsample whose counts follow P(c) ~ log((c+1)/c) on
+    [lo, hi] (log-uniform over the integers), as close as the supply allows."""
+    rng = np.random.default_rng(seed)
+    cs = np.arange(lo, hi + 1)
+    p = np.log((cs + 1.0) / cs)
+    p /= p.sum()
+    want = np.floor(p * n_out).astype(np.int64)
+    want[0] += n_out - want.sum()
+    picked = []
+    short = 0
+    for c, w in zip(cs, want):
+        pool = np.nonzero(counts == c)[0]
+        take = min(w + short, pool.size)
+        short = w + short - take
+        picked.append(rng.choice(pool, size=take, replace=False) if take else pool[:0])
+    idx = np.concatenate(picked)
+    if idx.size < n_out:  # fill from the largest counts available
+        rest = np.setdiff1d(np.nonzero((counts >= lo) & (counts <= hi))[0], idx)
+        idx = np.concatenate([idx, rng.choice(rest, size=min(n_out - idx.size, rest.size), replace=False)])
+    return np.sort(idx)

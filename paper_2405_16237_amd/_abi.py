@@ -47,6 +47,11 @@ class NbvhProfile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * NBVH_K_COUNT), ("calls", ctypes.c_int64 * NBVH_K_COUNT)]
 
 
+class NbvhTuning(ctypes.Structure):
+    _fields_ = [("query_waves", ctypes.c_int32), ("query_unroll", ctypes.c_int32), ("query_wgs_per_cu", ctypes.c_int32),
+                ("train_waves", ctypes.c_int32), ("wgrad_splits", ctypes.c_int32), ("scatter_lds_kb", ctypes.c_int32)]
+
+
 class NbvhStateHost(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("skipped", ctypes.c_int64), ("loss_scale", ctypes.c_float),
                 ("flags", ctypes.c_uint32), ("last_loss", ctypes.c_float * 4), ("last_n_segments", ctypes.c_uint64),
@@ -58,7 +63,8 @@ EXPORTS = [
     "nbvh_param_count", "nbvh_param_layout", "nbvh_aux_bytes", "nbvh_nodes_bytes", "nbvh_state_bytes", "nbvh_build",
     "nbvh_bind_params", "nbvh_reset_optimizer", "nbvh_sync_shadow", "nbvh_workspace_bytes", "nbvh_traverse",
     "nbvh_query", "nbvh_query_segments", "nbvh_encode", "nbvh_forward", "nbvh_backward", "nbvh_optimizer_step",
-    "nbvh_train_step", "nbvh_loss", "nbvh_profile_begin", "nbvh_profile_end", "nbvh_read_state", "nbvh_clear_flags", "nbvh_last_error", "nbvh_version",
+    "nbvh_train_step", "nbvh_loss", "nbvh_batch_desc_bytes", "nbvh_batch_create", "nbvh_batch_workspace_bytes",
+    "nbvh_batch_query", "nbvh_batch_destroy", "nbvh_get_tuning", "nbvh_set_tuning", "nbvh_profile_begin", "nbvh_profile_end", "nbvh_read_state", "nbvh_clear_flags", "nbvh_last_error", "nbvh_version",
     "nbvh_destroy",
 ]
 
@@ -101,6 +107,13 @@ def load(path: str = LIB_PATH):
         "nbvh_optimizer_step": (st, [P, P]),
         "nbvh_train_step": (st, [P, P, P, U64, P, P, SZ, P]),
         "nbvh_loss": (st, [P, P, P, U64, P, P, P, SZ, P]),
+        "nbvh_batch_desc_bytes": (SZ, [ctypes.c_uint32]),
+        "nbvh_batch_create": (st, [P, ctypes.c_uint32, P, SZ, P, P]),
+        "nbvh_batch_workspace_bytes": (SZ, [P, U64, U64]),
+        "nbvh_batch_query": (st, [P, P, U64, P, U64, P, SZ, P]),
+        "nbvh_batch_destroy": (None, [P]),
+        "nbvh_get_tuning": (st, [P, P]),
+        "nbvh_set_tuning": (st, [P, P]),
         "nbvh_profile_begin": (st, [P]),
         "nbvh_profile_end": (st, [P, P]),
         "nbvh_read_state": (st, [P, P, P]),

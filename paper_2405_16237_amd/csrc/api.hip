@@ -20,6 +20,7 @@ struct nbvh_ctx {
   bool bound;
   int n_cu;
   nbvh::Profiler* prof;
+  nbvh_tuning tune;
 };
 
 namespace nbvh {
@@ -220,6 +221,7 @@ static LaunchCtx make_launch(const nbvh_ctx* ctx, void* stream) {
   L.eps = ctx->cfg.eps;
   L.loss_scale = ctx->cfg.loss_scale;
   L.prof = (ctx->prof && ctx->prof->on) ? ctx->prof : nullptr;
+  L.tune = ctx->tune;
   return L;
 }
 
@@ -345,6 +347,7 @@ nbvh_status nbvh_build(const nbvh_config* cfg, const float* leaf_boxes_host, uin
   hipDeviceProp_t prop;
   ctx->n_cu = (hipGetDeviceProperties(&prop, dev) == hipSuccess) ? prop.multiProcessorCount : 256;
   if (ctx->n_cu <= 0) ctx->n_cu = 256;
+  ctx->tune = nbvh_tuning{8, 0, 0, 8, 32, 144};
   *out = ctx;
   return NBVH_OK;
 }
@@ -386,7 +389,7 @@ size_t nbvh_workspace_bytes(const nbvh_ctx* ctx, uint64_t max_rays, uint64_t max
   if (!ctx) return 0;
   size_t q = query_layout(max_rays, max_segments).total;
   const int prec = ctx->cfg.precision == NBVH_FP8 ? NBVH_BF16 : ctx->cfg.precision;
-  size_t t = train_ws_bytes(ctx->dev, prec, max_batch, ctx->n_cu);
+  size_t t = train_ws_bytes(ctx->dev, prec, max_batch, ctx->tune.wgrad_splits);
   size_t l = a256((max_batch / 256 + 2) * 16);
   return std::max(q, std::max(t, l));
 }
@@ -536,6 +539,121 @@ nbvh_status nbvh_clear_flags(nbvh_ctx* ctx, void* stream) {
   k_clear_flags<<<1, 64, 0, (hipStream_t)stream>>>((DevState*)ctx->p.state_dev);
   return check_launch("clear_flags");
 }
+
+// ---------------------------------------------------------------------------
+// batches of objects
+}  // extern "C"
+
+struct nbvh_batch {
+  std::vector<nbvh_ctx*> ctxs;
+  DevCfg* cfgs_dev;
+};
+
+static bool same_shape(const nbvh_config& a, const nbvh_config& b) {
+  if (a.n_levels != b.n_levels || a.n_features != b.n_features || a.n_samples != b.n_samples ||
+      a.mlp_width != b.mlp_width || a.mlp_hidden != b.mlp_hidden || a.n_out != b.n_out || a.precision != b.precision)
+    return false;
+  for (int l = 0; l < a.n_levels; ++l)
+    if (a.level_res[l] != b.level_res[l]) return false;
+  return true;
+}
+
+extern "C" {
+
+nbvh_status nbvh_get_tuning(const nbvh_ctx* ctx, nbvh_tuning* out) {
+  if (!ctx || !out) return set_error("NULL argument"), NBVH_ERR_INVALID_ARG;
+  *out = ctx->tune;
+  return NBVH_OK;
+}
+
+nbvh_status nbvh_set_tuning(nbvh_ctx* ctx, const nbvh_tuning* t) {
+  if (!ctx || !t) return set_error("NULL argument"), NBVH_ERR_INVALID_ARG;
+  if (t->query_waves != 4 && t->query_waves != 8) return set_error("query_waves must be 4 or 8"), NBVH_ERR_INVALID_ARG;
+  if (t->query_unroll != 0 && t->query_unroll != 1 && t->query_unroll != 2 && t->query_unroll != 4)
+    return set_error("query_unroll must be 0, 1, 2 or 4"), NBVH_ERR_INVALID_ARG;
+  if (t->query_wgs_per_cu < 0 || t->query_wgs_per_cu > 4) return set_error("query_wgs_per_cu in 0..4"), NBVH_ERR_INVALID_ARG;
+  if (t->train_waves != 4 && t->train_waves != 8) return set_error("train_waves must be 4 or 8"), NBVH_ERR_INVALID_ARG;
+  if (t->wgrad_splits < 1 || t->wgrad_splits > 256) return set_error("wgrad_splits in 1..256"), NBVH_ERR_INVALID_ARG;
+  if (t->scatter_lds_kb < 0 || t->scatter_lds_kb > 144) return set_error("scatter_lds_kb in 0..144"), NBVH_ERR_INVALID_ARG;
+  ctx->tune = *t;
+  return NBVH_OK;
+}
+
+size_t nbvh_batch_desc_bytes(uint32_t n_objects) { return (size_t)n_objects * sizeof(DevCfg); }
+
+nbvh_status nbvh_batch_create(nbvh_ctx* const* ctxs, uint32_t n_objects, void* descs_dev, size_t descs_bytes,
+                              void* stream, nbvh_batch** out) {
+  if (!out) return set_error("out is NULL"), NBVH_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!ctxs || n_objects < 1 || n_objects > 16) return set_error("batch needs 1..16 objects"), NBVH_ERR_INVALID_ARG;
+  if (!descs_dev || descs_bytes < nbvh_batch_desc_bytes(n_objects))
+    return set_error("descriptor buffer too small"), NBVH_ERR_CAPACITY;
+  std::vector<DevCfg> h(n_objects);
+  for (uint32_t k = 0; k < n_objects; ++k) {
+    nbvh_status s = require_bound(ctxs[k]);
+    if (s != NBVH_OK) return s;
+    if (!same_shape(ctxs[0]->cfg, ctxs[k]->cfg)) return set_error("object %u has a different network shape", k), NBVH_ERR_INVALID_ARG;
+    if (ctxs[k]->n_leaves >= (1u << 24)) return set_error("object %u has too many leaves", k), NBVH_ERR_UNSUPPORTED;
+    h[k] = ctxs[k]->dev;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (hipMemcpyAsync(descs_dev, h.data(), h.size() * sizeof(DevCfg), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return set_error("uploading batch descriptors failed"), NBVH_ERR_HIP;
+  nbvh_batch* b = new nbvh_batch;
+  b->ctxs.assign(ctxs, ctxs + n_objects);
+  b->cfgs_dev = (DevCfg*)descs_dev;
+  *out = b;
+  return NBVH_OK;
+}
+
+// workspace: one query part per object, then the per-object hit records
+// [object][ray] that the merge reads
+static size_t batch_part_bytes(uint64_t n_rays, uint64_t cap) { return query_layout(n_rays, cap).total; }
+
+size_t nbvh_batch_workspace_bytes(const nbvh_batch* b, uint64_t max_rays, uint64_t seg_capacity) {
+  if (!b) return 0;
+  return b->ctxs.size() * (batch_part_bytes(max_rays, seg_capacity) + a256(max_rays * sizeof(nbvh_hit)));
+}
+
+nbvh_status nbvh_batch_query(nbvh_batch* b, const nbvh_ray* rays, uint64_t n_rays, nbvh_hit* hits, uint64_t seg_capacity,
+                             void* ws, size_t ws_bytes, void* stream) {
+  if (!b) return set_error("batch is NULL"), NBVH_ERR_INVALID_ARG;
+  if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
+  if ((n_rays && (!rays || !hits)) || !ws) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  if (seg_capacity > 0xffffffffull) seg_capacity = 0xffffffffull;
+  const int n = (int)b->ctxs.size();
+  const size_t part = batch_part_bytes(n_rays, seg_capacity);
+  const size_t need = n * (part + a256(n_rays * sizeof(nbvh_hit)));
+  if (ws_bytes < need) return set_error("workspace too small: need %zu, got %zu", need, ws_bytes), NBVH_ERR_CAPACITY;
+  if (n_rays == 0) return NBVH_OK;
+  std::vector<LaunchCtx> Ls(n);
+  std::vector<const uint32_t*> offs(n), act(n), nact(n);
+  std::vector<const nbvh_segment*> sg(n);
+  std::vector<uint32_t*> cnt(n);
+  const QueryLayout Q = query_layout(n_rays, seg_capacity);
+  nbvh_hit* per_obj = (nbvh_hit*)((char*)ws + n * part);
+  for (int k = 0; k < n; ++k) {
+    Ls[k] = make_launch(b->ctxs[k], stream);
+    char* w = (char*)ws + part * k;
+    uint32_t* offsets = (uint32_t*)(w + Q.offsets);
+    uint32_t* misc = (uint32_t*)(w + Q.misc);
+    nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
+    nbvh_status s = launch_traverse(Ls[k], rays, (uint32_t)n_rays, offsets, segs, seg_capacity,
+                                    per_obj + (size_t)k * n_rays, (uint32_t*)(w + Q.active), misc + 0,
+                                    (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12);
+    if (s != NBVH_OK) return s;
+    offs[k] = offsets;
+    sg[k] = segs;
+    act[k] = (const uint32_t*)(w + Q.active);
+    nact[k] = misc + 0;
+    cnt[k] = misc + 1;
+  }
+  return launch_query_eval_batch(Ls.data(), n, b->cfgs_dev, offs.data(), sg.data(), act.data(), nact.data(),
+                                 cnt.data(), per_obj, hits, rays, (uint32_t)n_rays, seg_capacity);
+}
+
+void nbvh_batch_destroy(nbvh_batch* b) { delete b; }
 
 nbvh_status nbvh_profile_begin(nbvh_ctx* ctx) {
   if (!ctx) return set_error("ctx is NULL"), NBVH_ERR_INVALID_ARG;

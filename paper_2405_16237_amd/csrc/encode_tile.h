@@ -84,11 +84,12 @@ __device__ inline void unpack_raw(const typename RawEntry<F, LP>::T& r, float v[
 // Encode the M segments whose (o, t0) / (d, t1) sit in sA / sB into act0.
 // Each wave walks its (sample, level) pairs U at a time: all 8U gathers are
 // issued before any is consumed (U = 4 for 4-byte entries).
-template <typename AT, int F, bool LP, int NWAVES>
+template <typename AT, int F, bool LP, int NWAVES, int UNROLL = 0>
 __device__ inline void encode_tile(const DevCfg& c, const void* table, const float4* sA, const float4* sB,
                                    const int* s_valid, AT* act0, int ld0, int M) {
   typedef typename RawEntry<F, LP>::T Raw;
-  constexpr int U = sizeof(Raw) >= 16 ? 1 : 16 / (int)sizeof(Raw);  // 32..64 bytes of loads in flight per lane
+  // by default 32..64 bytes of loads in flight per lane
+  constexpr int U = UNROLL > 0 ? UNROLL : (sizeof(Raw) >= 16 ? 1 : 16 / (int)sizeof(Raw));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int SL = c.n_samples * c.n_levels;
   const uint32_t hmask = (1u << c.log2_T) - 1u;

@@ -21,6 +21,31 @@ constexpr int kQM = 64;      // slots per workgroup
 constexpr int kQWaves = 8;   // waves per workgroup
 constexpr uint32_t kXcds = 8;  // accelerator complex dies of an MI355X; ray-queue partitions
 
+// Instantiation choice from the precision, feature count and the tuned
+// (waves, unroll) pair; unroll 0 means "by entry size".
+#define NBVH_DISPATCH_UNROLL(AT, F, LP, NW, UNR, M)   \
+  do {                                                 \
+    if ((UNR) == 1) M(AT, F, LP, NW, 1);                \
+    if ((UNR) == 2) M(AT, F, LP, NW, 2);                \
+    M(AT, F, LP, NW, 4);                               \
+  } while (0)
+#define NBVH_DISPATCH_WAVES(AT, F, LP, Lc, M)                                                           \
+  do {                                                                                                  \
+    const int unr_ = (Lc).tune.query_unroll > 0 ? (Lc).tune.query_unroll                               \
+                                                : (16 / (F * (int)sizeof(AT)) >= 4 ? 4 : 16 / (F * (int)sizeof(AT))); \
+    if ((Lc).tune.query_waves == 4) NBVH_DISPATCH_UNROLL(AT, F, LP, 4, unr_, M);                       \
+    NBVH_DISPATCH_UNROLL(AT, F, LP, 8, unr_, M);                                                        \
+  } while (0)
+#define NBVH_DISPATCH_QUERY(Lc, M)                                               \
+  do {                                                                           \
+    if ((Lc).precision == NBVH_FP32) {                                          \
+      if ((Lc).cfg.n_features == 2) NBVH_DISPATCH_WAVES(float, 2, false, Lc, M); \
+      NBVH_DISPATCH_WAVES(float, 4, false, Lc, M);                              \
+    }                                                                           \
+    if ((Lc).cfg.n_features == 2) NBVH_DISPATCH_WAVES(bf16, 2, true, Lc, M);     \
+    NBVH_DISPATCH_WAVES(bf16, 4, true, Lc, M);                                  \
+  } while (0)
+
 __device__ inline uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u; }
 
 template <typename AT>
@@ -31,18 +56,28 @@ __host__ __device__ inline size_t query_lds_bytes(int n_in, int width) {
          (size_t)kQM * 4 * 12;
 }
 
-template <typename AT, int F, bool LP>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_query_eval(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
-                                                    const nbvh_ray* __restrict__ rays,
-                                                    const uint32_t* __restrict__ offsets,
-                                                    const nbvh_segment* __restrict__ segs,
-                                                    const uint32_t* __restrict__ active,
-                                                    const uint32_t* __restrict__ n_active_p,
-                                                    uint32_t* __restrict__ counter, nbvh_hit* __restrict__ hits,
-                                                    const uint32_t* __restrict__ total_segs, uint64_t capacity,
-                                                    DevState* __restrict__ state) {
-  if ((uint64_t)*total_segs > capacity) return;  // segment queue overflowed: flagged, nothing to read
-  extern __shared__ __align__(16) unsigned char smem[];
+// One object's query inputs.
+struct QueryJob {
+  const void* table;
+  const void* W;
+  const nbvh_ray* rays;
+  const uint32_t* offsets;
+  const nbvh_segment* segs;
+  const uint32_t* active;
+  const uint32_t* n_active;
+  uint32_t* counters;  // kXcds ray-queue counters
+  nbvh_hit* hits;
+  const uint32_t* total_segs;
+  uint64_t capacity;
+  DevState* state;
+};
+
+// The persistent slot loop over one object's ray queue (see the file comment).
+// Returns with every slot drained, so a workgroup can move on to another
+// object afterwards.
+template <typename AT, int F, bool LP, int NW, int U>
+__device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsigned char* smem) {
+  if ((uint64_t)*J.total_segs > J.capacity) return;  // segment queue overflowed: flagged, nothing to read
   const int ld0 = (c.n_in > c.width ? c.n_in : c.width) + Pad<AT>::v;
   const int ld1 = c.width + Pad<AT>::v;
   AT* act0 = (AT*)smem;
@@ -63,7 +98,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   float* s_ba = s_bn + 3 * kQM;   // [3][kQM]
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t n_active = *n_active_p;
+  const uint32_t n_active = *J.n_active;
   bool exhausted = false;
   const uint32_t first_part = xcc_id() % kXcds;
   uint32_t part = first_part;
@@ -84,21 +119,21 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         const uint32_t r1 = (uint32_t)(((uint64_t)n_active * (part + 1)) / kXcds);
         const int leader = __ffsll((unsigned long long)mask) - 1;
         uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(counter + part, nfree);
+        if (lane == leader) base = atomicAdd(J.counters + part, nfree);
         base = __shfl(base, leader);
         if ((mask >> lane) & 1ull) {
           const uint32_t idx = r0 + base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
           if (idx < r1) {
-            ray = active[idx];
-            const uint32_t cur = offsets[ray];
+            ray = J.active[idx];
+            const uint32_t cur = J.offsets[ray];
             s_ray[lane] = ray;
             s_cur[lane] = cur;
-            s_end[lane] = offsets[ray + 1];
+            s_end[lane] = J.offsets[ray + 1];
             s_bt[lane] = INFINITY;
             s_bleaf[lane] = NBVH_MISS;
-            const float4* rp = (const float4*)(rays + ray);
+            const float4* rp = (const float4*)(J.rays + ray);
             const float4 ra = rp[0], rb = rp[1];
-            const nbvh_segment sg = segs[cur];
+            const nbvh_segment sg = J.segs[cur];
             s_leaf[lane] = sg.leaf;
             sA[lane] = make_float4(ra.x, ra.y, ra.z, sg.t0);
             sB[lane] = make_float4(rb.x, rb.y, rb.z, sg.t1);
@@ -119,9 +154,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     __syncthreads();
     if (*s_any == 0) break;
 
-    encode_tile<AT, F, LP, kQWaves>(c, table, sA, sB, s_valid, act0, ld0, kQM);
+    encode_tile<AT, F, LP, NW, U>(c, J.table, sA, sB, s_valid, act0, ld0, kQM);
     __syncthreads();
-    mlp_forward_tile<kQM, kQWaves, AT>(c, W, act0, ld0, act1, ld1, z, kOutPad);
+    mlp_forward_tile<kQM, NW, AT>(c, (const AT*)J.W, act0, ld0, act1, ld1, z, kOutPad);
 
     if (wave == 0 && s_valid[lane]) {
       ++evaluated;
@@ -149,7 +184,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       s_cur[lane] = cur;
       bool more = false;
       if (cur < s_end[lane]) {
-        const nbvh_segment sg = segs[cur];
+        const nbvh_segment sg = J.segs[cur];
         if (sg.t0 < best_t) {
           more = true;
           s_leaf[lane] = sg.leaf;
@@ -158,7 +193,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
       }
       if (!more) {
-        float4* h = (float4*)(hits + ray);
+        float4* h = (float4*)(J.hits + ray);
         const uint32_t bl = s_bleaf[lane];
         if (bl == NBVH_MISS) {
           h[0] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -178,7 +213,33 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     uint32_t e = evaluated;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
-    if (lane == 0 && e) atomicAdd(&state->n_evaluated, (unsigned long long)e);
+    if (lane == 0 && e) atomicAdd(&J.state->n_evaluated, (unsigned long long)e);
+  }
+}
+
+template <typename AT, int F, bool LP, int NW, int U>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_query_eval(DevCfg c, QueryJob J) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  query_eval_loop<AT, F, LP, NW, U>(c, J, smem);
+}
+
+// Several objects (same network shape, own tables and weights) in one
+// launch: each workgroup drains the objects' ray queues starting at a
+// different object.
+constexpr int kMaxBatch = 16;
+struct QueryJobs {
+  QueryJob j[kMaxBatch];
+  int n;
+};
+
+template <typename AT, int F, bool LP, int NW, int U>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_query_eval_batch(
+    const DevCfg* __restrict__ cfgs, QueryJobs jobs) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int i = 0; i < jobs.n; ++i) {
+    const int k = (int)((blockIdx.x + (uint32_t)i) % (uint32_t)jobs.n);
+    query_eval_loop<AT, F, LP, NW, U>(cfgs[k], jobs.j[k], smem);
+    __syncthreads();
   }
 }
 
@@ -270,41 +331,123 @@ __global__ __launch_bounds__(256) void k_encode(DevCfg c, const void* __restrict
 // ---------------------------------------------------------------------------
 template <typename K>
 static void set_lds(K kernel, size_t bytes) {
-  hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename AT, int F, bool LP>
+// persistent workgroups per CU: as many as LDS allows (at most 4) unless tuned
+static int query_per_cu(const LaunchCtx& L, size_t lds) {
+  int per_cu = (int)(160 * 1024 / lds);
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 4) per_cu = 4;
+  if (L.tune.query_wgs_per_cu > 0 && L.tune.query_wgs_per_cu < per_cu) per_cu = L.tune.query_wgs_per_cu;
+  return per_cu;
+}
+
+// merge per-object hit records: closest t, ties to the lower object index
+__global__ __launch_bounds__(256) void k_merge_hits(const nbvh_hit* __restrict__ per_obj, uint32_t n_obj, uint32_t n_rays,
+                                                    nbvh_hit* __restrict__ hits) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rays) return;
+  float4 best0 = make_float4(0.f, 0.f, 0.f, 0.f), best1 = make_float4(0.f, 0.f, 0.f, __uint_as_float(NBVH_MISS));
+  bool have = false;
+  for (uint32_t k = 0; k < n_obj; ++k) {
+    const float4* h = (const float4*)(per_obj + (size_t)k * n_rays + r);
+    const float4 a = h[0], b = h[1];
+    const uint32_t leaf = __float_as_uint(b.w);
+    if (leaf == NBVH_MISS) continue;
+    if (!have || a.x < best0.x) {
+      best0 = a;
+      best1 = make_float4(b.x, b.y, b.z, __uint_as_float((k << 24) | leaf));
+      have = true;
+    }
+  }
+  float4* o = (float4*)(hits + r);
+  o[0] = best0;
+  o[1] = best1;
+}
+
+template <typename AT, int F, bool LP, int NW, int U>
+static nbvh_status query_batch_t(const LaunchCtx* Ls, int n_obj, const DevCfg* cfgs_dev, const QueryJob* jobs,
+                                 nbvh_hit* per_obj, nbvh_hit* hits, uint32_t n_rays) {
+  const LaunchCtx& L = Ls[0];
+  const size_t lds = query_lds_bytes<AT>(L.cfg.n_in, L.cfg.width);
+  auto kern = k_query_eval_batch<AT, F, LP, NW, U>;
+  set_lds(kern, lds);
+  const int per_cu = query_per_cu(L, lds);
+  QueryJobs Q;
+  Q.n = n_obj;
+  for (int k = 0; k < n_obj; ++k) Q.j[k] = jobs[k];
+  {
+    ProfScope ps(L.prof, NBVH_K_QUERY_EVAL, L.stream);
+    kern<<<(uint32_t)L.n_cu * per_cu, 64 * NW, lds, L.stream>>>(cfgs_dev, Q);
+  }
+  k_merge_hits<<<(n_rays + 255) / 256, 256, 0, L.stream>>>(per_obj, (uint32_t)n_obj, n_rays, hits);
+  return check_launch("query_eval_batch");
+}
+
+nbvh_status launch_query_eval_batch(const LaunchCtx* Ls, int n_obj, const DevCfg* cfgs_dev, const uint32_t* const* offsets,
+                                    const nbvh_segment* const* segs, const uint32_t* const* active,
+                                    const uint32_t* const* n_active, uint32_t* const* counters, nbvh_hit* per_obj,
+                                    nbvh_hit* hits, const nbvh_ray* rays, uint32_t n_rays, uint64_t capacity) {
+  if (n_obj < 1 || n_obj > kMaxBatch) return set_error("batch of %d objects (1..%d)", n_obj, kMaxBatch), NBVH_ERR_INVALID_ARG;
+  QueryJob jobs[kMaxBatch];
+  for (int k = 0; k < n_obj; ++k) {
+    const LaunchCtx& Lk = Ls[k];
+    QueryJob& J = jobs[k];
+    J.W = (Lk.precision != NBVH_FP32) ? (const void*)Lk.params_lp : (const void*)Lk.params;
+    J.table = J.W;
+    J.rays = rays;
+    J.offsets = offsets[k];
+    J.segs = segs[k];
+    J.active = active[k];
+    J.n_active = n_active[k];
+    J.counters = counters[k];
+    J.hits = per_obj + (size_t)k * n_rays;
+    J.total_segs = offsets[k] + n_rays;
+    J.capacity = capacity;
+    J.state = Lk.state;
+  }
+#define NBVH_QB(AT, F, LP, NW, U) return query_batch_t<AT, F, LP, NW, U>(Ls, n_obj, cfgs_dev, jobs, per_obj, hits, n_rays)
+  NBVH_DISPATCH_QUERY(Ls[0], NBVH_QB);
+#undef NBVH_QB
+}
+
+template <typename AT, int F, bool LP, int NW, int U>
 static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
                                 const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
                                 uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity) {
   const DevCfg& c = L.cfg;
   const size_t lds = query_lds_bytes<AT>(c.n_in, c.width);
-  auto kern = k_query_eval<AT, F, LP>;
+  auto kern = k_query_eval<AT, F, LP, NW, U>;
   set_lds(kern, lds);
-  int per_cu = (int)(160 * 1024 / lds);
-  if (per_cu < 1) per_cu = 1;
-  if (per_cu > 4) per_cu = 4;
-  uint32_t grid = (uint32_t)L.n_cu * per_cu;
+  uint32_t grid = (uint32_t)L.n_cu * query_per_cu(L, lds);
   const uint32_t need = (n_rays_bound + kQM - 1) / kQM;
   if (need < grid) grid = need > 0 ? need : 1;
-  const AT* W = (sizeof(AT) == 2) ? (const AT*)L.params_lp : (const AT*)L.params;
-  const void* table = LP ? (const void*)L.params_lp : (const void*)L.params;
+  QueryJob J;
+  J.W = (sizeof(AT) == 2) ? (const void*)L.params_lp : (const void*)L.params;
+  J.table = LP ? (const void*)L.params_lp : (const void*)L.params;
+  J.rays = rays;
+  J.offsets = offsets;
+  J.segs = segs;
+  J.active = active;
+  J.n_active = n_active;
+  J.counters = counter;
+  J.hits = hits;
+  J.total_segs = offsets + n_rays_bound;
+  J.capacity = capacity;
+  J.state = L.state;
   ProfScope ps(L.prof, NBVH_K_QUERY_EVAL, L.stream);
-  kern<<<grid, 64 * kQWaves, lds, L.stream>>>(c, table, W, rays, offsets, segs, active, n_active, counter, hits,
-                                     offsets + n_rays_bound, capacity, L.state);
+  kern<<<grid, 64 * NW, lds, L.stream>>>(c, J);
   return check_launch("query_eval");
 }
 
 nbvh_status launch_query_eval(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
                               const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
                               uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity) {
-  const int F = L.cfg.n_features;
-  if (L.precision == NBVH_FP32) {
-    if (F == 2) return query_eval_t<float, 2, false>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity);
-    return query_eval_t<float, 4, false>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity);
-  }
-  if (F == 2) return query_eval_t<bf16, 2, true>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity);
-  return query_eval_t<bf16, 4, true>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity);
+#define NBVH_QE(AT, F, LP, NW, U) \
+  return query_eval_t<AT, F, LP, NW, U>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity)
+  NBVH_DISPATCH_QUERY(L, NBVH_QE);
+#undef NBVH_QE
 }
 
 template <typename AT, int F, bool LP>

@@ -24,7 +24,6 @@
 namespace nbvh {
 
 constexpr int kTM = 64;
-constexpr int kTWaves = 8;
 constexpr int kGPad = 32;  // gradient rows of the output layer padded to 32
 
 __host__ __device__ inline int fan_out_pad(const DevCfg& c, int k) {
@@ -41,7 +40,7 @@ struct TrainLayout {
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_batch, int n_cu) {
+static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_batch, int wgrad_splits) {
   TrainLayout T;
   const size_t es = precision == NBVH_FP32 ? 4 : 2;
   const uint64_t B = (max_batch + kTM - 1) / kTM * kTM;
@@ -56,8 +55,7 @@ static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_bat
   }
   T.duT = off;
   off = align256(off + (size_t)c.n_in * B * 4);
-  T.nsplit = 32;
-  (void)n_cu;
+  T.nsplit = wgrad_splits > 0 ? wgrad_splits : 32;
   T.wpart = off;
   off = align256(off + (size_t)T.nsplit * (c.n_params - c.w_off[0]) * 4);
   T.n_tiles = (uint32_t)(B / kTM);
@@ -67,9 +65,9 @@ static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_bat
   return T;
 }
 
-size_t train_ws_bytes(const DevCfg& c, int precision, uint64_t max_batch, int n_cu) {
+size_t train_ws_bytes(const DevCfg& c, int precision, uint64_t max_batch, int wgrad_splits) {
   if (max_batch == 0) return 0;
-  return train_layout(c, precision, max_batch, n_cu).total;
+  return train_layout(c, precision, max_batch, wgrad_splits).total;
 }
 
 template <typename AT>
@@ -100,8 +98,8 @@ __device__ inline float bce_logits(float z, float h) {
 }
 __device__ inline float sgnf(float v) { return (float)((v > 0.0f) - (v < 0.0f)); }
 
-template <typename AT, int F, bool LP, bool WITH_LABELS>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_train_tile(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
+template <typename AT, int F, bool LP, bool WITH_LABELS, int kTWaves>
+__global__ __launch_bounds__(64 * kTWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_train_tile(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
                                                     const AT* __restrict__ WT, const nbvh_probe* __restrict__ probes,
                                                     const nbvh_label* __restrict__ labels,
                                                     const float* __restrict__ dz_in, uint32_t n, TrainPtrs P,
@@ -488,10 +486,11 @@ template <int F>
 static void launch_scatter(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, const float* duT, uint64_t ldb) {
   const DevCfg& c = L.cfg;
   uint32_t n_floats = 0;
-  const int n_lds = coarse_lds_levels(c, 144 * 1024, &n_floats);
+  const int budget_kb = L.tune.scatter_lds_kb < 0 ? 0 : (L.tune.scatter_lds_kb > 144 ? 144 : L.tune.scatter_lds_kb);
+  const int n_lds = budget_kb > 0 ? coarse_lds_levels(c, (size_t)budget_kb * 1024, &n_floats) : 0;
   if (n_lds > 0) {
     const size_t lds = (size_t)n_floats * 4;
-    hipFuncSetAttribute((const void*)k_scatter_lds<F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_scatter_lds<F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_scatter_lds<F><<<L.n_cu, 1024, lds, L.stream>>>(c, n_lds, n_floats, probes, n, duT, ldb, L.grad);
   }
   if (n_lds < c.n_levels) {
@@ -668,7 +667,7 @@ __global__ void k_reset_state(DevState* state, float loss_scale) {
 // ---------------------------------------------------------------------------
 template <typename K>
 static void set_lds(K kernel, size_t bytes) {
-  hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 static WTiles make_tiles(const DevCfg& c) {
@@ -684,7 +683,7 @@ template <typename AT, int F, bool LP>
 static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const nbvh_label* labels, const float* dz_in,
                            uint32_t n, float* loss_dev, void* ws, size_t ws_bytes) {
   const DevCfg& c = L.cfg;
-  const TrainLayout T = train_layout(c, L.precision, n, L.n_cu);
+  const TrainLayout T = train_layout(c, L.precision, n, L.tune.wgrad_splits);
   if (ws_bytes < T.total) {
     set_error("workspace too small for a batch of %u: need %zu bytes, got %zu", n, T.total, ws_bytes);
     return NBVH_ERR_CAPACITY;
@@ -709,17 +708,22 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
   }
   {
     ProfScope ps(L.prof, NBVH_K_TRAIN_TILE, L.stream);
+    const int nw = L.tune.train_waves == 4 ? 4 : 8;
+#define NBVH_TT(LAB, NW)                                                                                  \
+  do {                                                                                                    \
+    auto kern = k_train_tile<AT, F, LP, LAB, NW>;                                                         \
+    set_lds(kern, lds);                                                                                   \
+    kern<<<T.n_tiles, 64 * NW, lds, L.stream>>>(c, table, W, WT, probes, labels, dz_in, n, P, L.state, L.w_hit, \
+                                               L.w_t, L.w_normal);                                       \
+  } while (0)
     if (labels) {
-      auto kern = k_train_tile<AT, F, LP, true>;
-      set_lds(kern, lds);
-      kern<<<T.n_tiles, 64 * kTWaves, lds, L.stream>>>(c, table, W, WT, probes, labels, nullptr, n, P, L.state, L.w_hit,
-                                               L.w_t, L.w_normal);
+      if (nw == 4) NBVH_TT(true, 4);
+      else NBVH_TT(true, 8);
     } else {
-      auto kern = k_train_tile<AT, F, LP, false>;
-      set_lds(kern, lds);
-      kern<<<T.n_tiles, 64 * kTWaves, lds, L.stream>>>(c, table, W, WT, probes, nullptr, dz_in, n, P, L.state, L.w_hit,
-                                               L.w_t, L.w_normal);
+      if (nw == 4) NBVH_TT(false, 4);
+      else NBVH_TT(false, 8);
     }
+#undef NBVH_TT
   }
   {
     ProfScope ps(L.prof, NBVH_K_WGRAD, L.stream);

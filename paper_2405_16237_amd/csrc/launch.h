@@ -22,11 +22,11 @@ class ProfScope {
     if (p_ && p_->on && p_->used < p_->kid.size()) {
       idx_ = p_->used++;
       p_->kid[idx_] = kid;
-      hipEventRecord(p_->ev[2 * idx_], s_);
+      (void)hipEventRecord(p_->ev[2 * idx_], s_);
     }
   }
   ~ProfScope() {
-    if (idx_ != (size_t)-1) hipEventRecord(p_->ev[2 * idx_ + 1], s_);
+    if (idx_ != (size_t)-1) (void)hipEventRecord(p_->ev[2 * idx_ + 1], s_);
   }
 
  private:
@@ -66,6 +66,7 @@ struct LaunchCtx {
   float w_hit, w_t, w_normal, w_albedo;
   float lr, beta1, beta2, eps, loss_scale;
   Profiler* prof;
+  nbvh_tuning tune;
 };
 
 nbvh_status check_launch(const char* what);
@@ -83,6 +84,11 @@ nbvh_status launch_query_eval(const LaunchCtx& L, const nbvh_ray* rays, const ui
                               const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
                               uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity);
 
+nbvh_status launch_query_eval_batch(const LaunchCtx* Ls, int n_obj, const DevCfg* cfgs_dev, const uint32_t* const* offsets,
+                                    const nbvh_segment* const* segs, const uint32_t* const* active,
+                                    const uint32_t* const* n_active, uint32_t* const* counters, nbvh_hit* per_obj,
+                                    nbvh_hit* hits, const nbvh_ray* rays, uint32_t n_rays, uint64_t capacity);
+
 nbvh_status launch_active_rays(const LaunchCtx& L, const uint32_t* offsets, uint32_t n_rays, nbvh_hit* hits,
                                uint32_t* active, uint32_t* misc);
 
@@ -91,7 +97,7 @@ nbvh_status launch_encode(const LaunchCtx& L, const nbvh_probe* probes, uint32_t
 nbvh_status launch_forward(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, float* z);
 
 // training
-size_t train_ws_bytes(const DevCfg& c, int precision, uint64_t max_batch, int n_cu);
+size_t train_ws_bytes(const DevCfg& c, int precision, uint64_t max_batch, int wgrad_splits);
 nbvh_status launch_train_fwd_bwd(const LaunchCtx& L, const nbvh_probe* probes, const nbvh_label* labels,
                                  const float* dz_in, uint32_t n, float* loss_dev, void* ws, size_t ws_bytes,
                                  bool apply_grad);

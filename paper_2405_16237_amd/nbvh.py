@@ -107,7 +107,8 @@ class NBVH:
             dev[dst:dst + fi * fo] = flat[src:src + fi * fo]
             src += fi * fo
         assert src == flat.numel(), (src, flat.numel())
-        self.params.copy_(dev.to(self.device))
+        with torch.no_grad():
+            self.params.copy_(dev.to(self.device))
         check(self.lib.nbvh_reset_optimizer(self.ctx, _stream()))
 
     def get_params(self) -> np.ndarray:
@@ -218,6 +219,18 @@ class NBVH:
         check(self.lib.nbvh_profile_end(self.ctx, ctypes.byref(p)))
         return {name: (p.ms[i], p.calls[i]) for i, name in enumerate(_abi.KERNEL_GROUPS)}
 
+    def get_tuning(self) -> dict:
+        t = _abi.NbvhTuning()
+        check(self.lib.nbvh_get_tuning(self.ctx, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in _abi.NbvhTuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = _abi.NbvhTuning(**cur)
+        check(self.lib.nbvh_set_tuning(self.ctx, ctypes.byref(t)))
+        self._ws = None  # the workspace size may depend on the knobs
+
     def read_state(self) -> dict:
         s = _abi.NbvhStateHost()
         check(self.lib.nbvh_read_state(self.ctx, ctypes.byref(s), _stream()))
@@ -226,6 +239,56 @@ class NBVH:
 
     def clear_flags(self):
         check(self.lib.nbvh_clear_flags(self.ctx, _stream()))
+
+
+class NBVHBatch:
+    """Several NBVH objects (same network shape) answered together."""
+
+    def __init__(self, models):
+        self.lib = _abi.load()
+        self.models = list(models)
+        n = len(self.models)
+        self.device = self.models[0].device
+        self.desc = torch.empty(self.lib.nbvh_batch_desc_bytes(n), dtype=torch.uint8, device=self.device)
+        arr = (ctypes.c_void_p * n)(*[m.ctx.value for m in self.models])
+        b = ctypes.c_void_p()
+        check(self.lib.nbvh_batch_create(arr, n, _ptr(self.desc), self.desc.numel(), _stream(), ctypes.byref(b)))
+        self.b = b
+        self._ws = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "b", None):
+                self.lib.nbvh_batch_destroy(self.b)
+                self.b = None
+        except Exception:
+            pass
+
+    def workspace(self, n_rays, seg_capacity):
+        need = self.lib.nbvh_batch_workspace_bytes(self.b, n_rays, seg_capacity)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def query(self, rays: torch.Tensor, seg_capacity: int | None = None, hits: torch.Tensor | None = None):
+        """Hits [n][8]; leaf word = (object << 24) | leaf (0xFFFFFFFF = miss)."""
+        n = rays.shape[0]
+        if seg_capacity is None:
+            seg_capacity = 8 * n + 1024
+        if hits is None:
+            hits = torch.empty((n, 8), dtype=torch.float32, device=self.device)
+        ws = self.workspace(n, seg_capacity)
+        check(self.lib.nbvh_batch_query(self.b, _ptr(rays), n, _ptr(hits), seg_capacity, _ptr(ws), ws.numel(),
+                                        _stream()))
+        return hits
+
+    def train_step(self, probes, labels, losses=None):
+        """One optimiser step per object (batches probes[k], labels[k])."""
+        if losses is None:
+            losses = torch.empty((len(self.models), 4), dtype=torch.float32, device=self.device)
+        for k, m in enumerate(self.models):
+            m.train_step(probes[k], labels[k], losses[k])
+        return losses
 
 
 def hits_leaf(hits: torch.Tensor) -> torch.Tensor:
