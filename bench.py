@@ -61,6 +61,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-fp8", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the query shards by rays and the "
@@ -175,6 +176,24 @@ def main():
         log("fp32: query %.3f ms, train %.3f ms, hit acc %.4f (bf16 %.4f)" %
             (fq_ms, ft_ms, acc_fp["hit_accuracy"], acc_bf["hit_accuracy"]))
 
+    # FP8 inference option with the same trained parameters: per-layer scales
+    # calibrated on 2^16 seeded probe segments
+    fp8 = None
+    if not args.no_fp8:
+        f8 = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp8")
+        f8.set_params(bf.get_params())
+        f8.calibrate_fp8(batches[0][0][: 1 << 16].contiguous())
+        f8.workspace(R, seg_cap, 0)
+        hits_f8 = torch.empty((R, 8), dtype=torch.float32, device="cuda")
+        f8.query(rays, seg_cap, hits_f8)
+        torch.cuda.synchronize()
+        acc_f8 = hit_error(hits_f8.cpu().numpy(), gt, sc.diagonal)
+        f8_ms = time_loop(lambda i: f8.query(rays, seg_cap, hits_f8), args.steps)
+        fp8 = dict(query_ms=f8_ms, rays_per_s=R / (f8_ms * 1e-3), accuracy=acc_f8,
+                   calibration="2^16 probe segments of the first training batch")
+        log("fp8: query %.3f ms, hit acc %.4f (bf16 %.4f)" % (f8_ms, acc_f8["hit_accuracy"], acc_bf["hit_accuracy"]))
+        del f8
+
     # dominant kernel group and its roofline
     per = {k: (v[0] / max(1, v[1]), v[1], v[0]) for k, v in prof.items() if v[1] > 0}
     dom = max(per, key=lambda k: per[k][2])
@@ -252,6 +271,7 @@ def main():
         "train_segs_per_s": B / (t_ms * 1e-3),
         "accuracy": acc_bf,
         "fp32": fp32,
+        "fp8": fp8,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -46,7 +46,10 @@ typedef enum {
 /* Arithmetic of the MLP and of the feature reads in queries and training.
  * FP32: FP32 table reads and FP32 matrix-core products.
  * BF16: BF16 table shadow, BF16 activations and weights, FP32 accumulation.
- * FP8 : (query only) E4M3 weights and activations with per-layer scales. */
+ * FP8 : inference only (queries and nbvh_forward): BF16 table shadow, OCP
+ *       E4M3 weights and activations (largest value 448) with one scale per
+ *       layer, FP32 accumulation; set up by nbvh_calibrate_fp8. Training
+ *       calls return NBVH_ERR_UNSUPPORTED. */
 typedef enum { NBVH_FP32 = 0, NBVH_BF16 = 1, NBVH_FP8 = 2 } nbvh_precision;
 
 /* Device-state flag bits (nbvh_state_host.flags). */
@@ -151,7 +154,8 @@ typedef struct {
   float* adam_v_dev;
   float* grad_dev;
   void* state_dev;
-  void* aux_dev; /* nbvh_aux_bytes(cfg) bytes: transposed weight copies read by back-propagation */
+  void* aux_dev; /* nbvh_aux_bytes(cfg) bytes: transposed weight copies read by back-propagation,
+                    then the FP8 weights and scales */
 } nbvh_params;
 
 /* Host copy of the device state block. */
@@ -169,14 +173,16 @@ typedef struct nbvh_ctx nbvh_ctx; /* opaque host handle */
 
 /* Launch-shape knobs (defaults shown). Results do not depend on them beyond
  * floating-point summation order; an autotuner may search them. Changing
- * wgrad_splits changes nbvh_workspace_bytes. */
+ * wgrad_splits, scatter_lds_kb or scatter_binned changes nbvh_workspace_bytes. */
 typedef struct {
   int32_t query_waves;      /* waves per query workgroup: 4 or 8 (8) */
-  int32_t query_unroll;     /* (sample, level) pairs gathered together: 1, 2, 4; 0 = by entry size (0) */
+  int32_t query_unroll;     /* (sample, level) pairs gathered together: 2, 3, 4; 0 = by entry size (0) */
   int32_t query_wgs_per_cu; /* persistent query workgroups per compute unit; 0 = as many as LDS allows (0) */
   int32_t train_waves;      /* waves per training-tile workgroup: 4 or 8 (8) */
   int32_t wgrad_splits;     /* batch splits of the weight-gradient GEMMs: 1..256 (32) */
   int32_t scatter_lds_kb;   /* LDS budget for coarse levels in the table-gradient scatter: 0..144 (144) */
+  int32_t scatter_binned;   /* other levels: 1 = counting sort by 64 KiB table chunk, then per-chunk LDS
+                               accumulation (no global atomics); 0 = coalesced global atomics (1) */
 } nbvh_tuning;
 
 /* Read / replace the context's launch knobs (validated). */
@@ -193,8 +199,9 @@ nbvh_status nbvh_param_count(const nbvh_config* cfg, uint64_t* n_table, uint64_t
  * mlp_hidden + 3 entries. */
 nbvh_status nbvh_param_layout(const nbvh_config* cfg, uint64_t* offsets);
 
-/* Bytes of the auxiliary buffer (transposed FP32 and BF16 weight copies,
- * rewritten by nbvh_sync_shadow and every optimiser step). */
+/* Bytes of the auxiliary buffer: transposed FP32 and BF16 weight copies
+ * (rewritten by nbvh_sync_shadow and every optimiser step), then E4M3
+ * weights and per-layer scales (written by nbvh_calibrate_fp8). */
 size_t nbvh_aux_bytes(const nbvh_config* cfg);
 
 /* Bytes of the node buffer nbvh_build writes for n_leaves leaves. */
@@ -224,6 +231,21 @@ nbvh_status nbvh_reset_optimizer(nbvh_ctx* ctx, void* stream);
 /* Rewrite the BF16 shadow from the FP32 params (after the caller edits
  * params directly). */
 nbvh_status nbvh_sync_shadow(nbvh_ctx* ctx, void* stream);
+
+/* FP8 inference set-up (precision FP8 only; the MLP of Sec. 4 run at 8 bits).
+ * Weight scale of layer k: sw_k = 448 / max|W_k| over the FP32 master
+ * weights. Activation scale of layer k's input: sa_k = 448 / max|h_k|, the
+ * maximum taken over an FP32 forward (BF16 table reads, FP32 weights) of the
+ * n calibration segments probes_dev (device, [n]); a zero maximum gives
+ * scale 1. Writes E4M3 weights fp8(W_k * sw_k) and the scales into aux.
+ * A query then stores fp8(h_k * sa_k) in LDS, multiplies on the FP8 matrix
+ * cores with FP32 accumulation and divides by sw_k * sa_k; values beyond the
+ * calibrated range saturate at +-448. Must be called again after any change
+ * of the parameters (nbvh_bind_params, nbvh_sync_shadow,
+ * nbvh_reset_optimizer and nbvh_optimizer_step invalidate it); until then
+ * FP8 queries and nbvh_forward return NBVH_ERR_NOT_BOUND. Asynchronous on
+ * `stream`; NBVH_ERR_INVALID_ARG for n = 0, a NULL buffer or a non-FP8 context. */
+nbvh_status nbvh_calibrate_fp8(nbvh_ctx* ctx, const nbvh_probe* probes_dev, uint64_t n, void* stream);
 
 /* Workspace bytes for queries of up to max_rays rays producing up to
  * max_segments segments, and for training/forward/backward batches of up to

@@ -64,6 +64,7 @@ def _lib():
             L.oc_backward.argtypes = [P, P, P, I, P, P]
             L.oc_adam.argtypes = [I, P, P, P, P, I, D, D, D, D, D]
             L.oc_min_abs_preact.argtypes = [P, P, P, I, P]
+            L.oc_layer_amax.argtypes = [P, P, P, I, P]
             L.oc_resolve.argtypes = [I, P, P, P, P, P, ctypes.c_int, P]
             L.oc_num_threads.restype = ctypes.c_int
             _LIB = L
@@ -186,6 +187,16 @@ def min_abs_preact(cfg, params, segs):
     segs = _c(segs, np.float32)
     out = np.zeros(segs.shape[0], dtype=np.float64)
     _lib().oc_min_abs_preact(ctypes.byref(cfg), _p(params), _p(segs), segs.shape[0], _p(out))
+    return out
+
+
+def layer_amax(cfg, params, segs):
+    """[H + 1]: max |u| over the encoded features, then the largest ReLU
+    output of each hidden layer, over the batch."""
+    params = _c(params, np.float64)
+    segs = _c(segs, np.float32)
+    out = np.zeros(cfg.mlp_hidden + 1, dtype=np.float64)
+    _lib().oc_layer_amax(ctypes.byref(cfg), _p(params), _p(segs), segs.shape[0], _p(out))
     return out
 
 

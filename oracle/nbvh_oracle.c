@@ -341,6 +341,43 @@ void oc_min_abs_preact(const oc_cfg* c, const double* params, const float* segs,
   }
 }
 
+/* Largest magnitude of each layer's input over a batch: amax[0] = max |u|
+ * over the encoded features, amax[k] = max h_k over the ReLU outputs of
+ * hidden layer k (k = 1..H). These fix the per-layer scales of 8-bit
+ * inference (value range of the format / amax). */
+void oc_layer_amax(const oc_cfg* c, const double* params, const float* segs, int64_t n, double* amax) {
+  int64_t n_tab = oc_table_params(c);
+  int n_in = oc_n_in(c), width = c->mlp_width, H = c->mlp_hidden;
+  int maxw = n_in > width ? n_in : width;
+  for (int k = 0; k <= H; ++k) amax[k] = 0.0;
+#pragma omp parallel
+  {
+    double* u = (double*)malloc(sizeof(double) * (size_t)n_in);
+    double* pre = (double*)malloc(sizeof(double) * (size_t)H * width);
+    double* buf = (double*)malloc(sizeof(double) * 2 * (size_t)maxw);
+    double* z = (double*)malloc(sizeof(double) * (size_t)c->n_out);
+    double* local = (double*)calloc((size_t)H + 1, sizeof(double));
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      oc_encode_one(c, params, segs + 8 * i, u);
+      oc_mlp_one(c, params + n_tab, u, z, pre, buf);
+      for (int j = 0; j < n_in; ++j) local[0] = fabs(u[j]) > local[0] ? fabs(u[j]) : local[0];
+      for (int k = 1; k <= H; ++k)
+        for (int j = 0; j < width; ++j) {
+          double h = pre[(size_t)(k - 1) * width + j] > 0.0 ? pre[(size_t)(k - 1) * width + j] : 0.0;
+          local[k] = h > local[k] ? h : local[k];
+        }
+    }
+#pragma omp critical
+    for (int k = 0; k <= H; ++k) amax[k] = local[k] > amax[k] ? local[k] : amax[k];
+    free(local);
+    free(u);
+    free(pre);
+    free(buf);
+    free(z);
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Losses (Sec. 5.2): visibility is a binary cross-entropy on a sigmoid;     */
 /* the local distance (distance along the segment relative to its length,    */

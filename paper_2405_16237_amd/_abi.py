@@ -49,7 +49,8 @@ class NbvhProfile(ctypes.Structure):
 
 class NbvhTuning(ctypes.Structure):
     _fields_ = [("query_waves", ctypes.c_int32), ("query_unroll", ctypes.c_int32), ("query_wgs_per_cu", ctypes.c_int32),
-                ("train_waves", ctypes.c_int32), ("wgrad_splits", ctypes.c_int32), ("scatter_lds_kb", ctypes.c_int32)]
+                ("train_waves", ctypes.c_int32), ("wgrad_splits", ctypes.c_int32), ("scatter_lds_kb", ctypes.c_int32),
+                ("scatter_binned", ctypes.c_int32)]
 
 
 class NbvhStateHost(ctypes.Structure):
@@ -61,7 +62,8 @@ class NbvhStateHost(ctypes.Structure):
 # every entry point declared in include/nbvh.h
 EXPORTS = [
     "nbvh_param_count", "nbvh_param_layout", "nbvh_aux_bytes", "nbvh_nodes_bytes", "nbvh_state_bytes", "nbvh_build",
-    "nbvh_bind_params", "nbvh_reset_optimizer", "nbvh_sync_shadow", "nbvh_workspace_bytes", "nbvh_traverse",
+    "nbvh_bind_params", "nbvh_reset_optimizer", "nbvh_sync_shadow", "nbvh_calibrate_fp8", "nbvh_workspace_bytes",
+    "nbvh_traverse",
     "nbvh_query", "nbvh_query_segments", "nbvh_encode", "nbvh_forward", "nbvh_backward", "nbvh_optimizer_step",
     "nbvh_train_step", "nbvh_loss", "nbvh_batch_desc_bytes", "nbvh_batch_create", "nbvh_batch_workspace_bytes",
     "nbvh_batch_query", "nbvh_batch_destroy", "nbvh_get_tuning", "nbvh_set_tuning", "nbvh_profile_begin", "nbvh_profile_end", "nbvh_read_state", "nbvh_clear_flags", "nbvh_last_error", "nbvh_version",
@@ -97,6 +99,7 @@ def load(path: str = LIB_PATH):
         "nbvh_bind_params": (st, [P, P]),
         "nbvh_reset_optimizer": (st, [P, P]),
         "nbvh_sync_shadow": (st, [P, P]),
+        "nbvh_calibrate_fp8": (st, [P, P, U64, P]),
         "nbvh_workspace_bytes": (SZ, [P, U64, U64, U64]),
         "nbvh_traverse": (st, [P, P, U64, P, P, U64, P, SZ, P]),
         "nbvh_query": (st, [P, P, U64, P, U64, P, SZ, P]),

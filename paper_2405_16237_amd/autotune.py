@@ -14,8 +14,8 @@ import os
 
 import torch
 
-QUERY_SPACE = dict(query_waves=(4, 8), query_unroll=(0, 1, 2, 4), query_wgs_per_cu=(0, 1, 2))
-TRAIN_SPACE = dict(train_waves=(4, 8), wgrad_splits=(16, 32, 64), scatter_lds_kb=(0, 64, 144))
+QUERY_SPACE = dict(query_waves=(4, 8), query_unroll=(2, 3, 4), query_wgs_per_cu=(0, 1, 2))
+TRAIN_SPACE = dict(train_waves=(4, 8), wgrad_splits=(16, 32, 64), scatter_lds_kb=(0, 144), scatter_binned=(0, 1))
 
 
 def _time(fn, reps):

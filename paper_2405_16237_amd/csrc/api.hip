@@ -21,6 +21,7 @@ struct nbvh_ctx {
   int n_cu;
   nbvh::Profiler* prof;
   nbvh_tuning tune;
+  bool fp8_ready;  // FP8 weights and scales in aux match the current parameters
 };
 
 namespace nbvh {
@@ -196,6 +197,13 @@ static nbvh_status require_bound(const nbvh_ctx* ctx) {
   return NBVH_OK;
 }
 
+static nbvh_status require_fp8_ready(const nbvh_ctx* ctx) {
+  if (ctx->cfg.precision == NBVH_FP8 && !ctx->fp8_ready)
+    return set_error("FP8 weights are stale or missing: call nbvh_calibrate_fp8 after setting parameters"),
+           NBVH_ERR_NOT_BOUND;
+  return NBVH_OK;
+}
+
 static LaunchCtx make_launch(const nbvh_ctx* ctx, void* stream) {
   LaunchCtx L;
   memset(&L, 0, sizeof(L));
@@ -210,6 +218,7 @@ static LaunchCtx make_launch(const nbvh_ctx* ctx, void* stream) {
   L.adam_v = ctx->p.adam_v_dev;
   L.grad = ctx->p.grad_dev;
   L.aux = ctx->p.aux_dev;
+  L.fp8 = ctx->cfg.precision == NBVH_FP8;
   L.n_cu = ctx->n_cu;
   L.w_hit = ctx->cfg.w_hit;
   L.w_t = ctx->cfg.w_t;
@@ -284,7 +293,7 @@ nbvh_status nbvh_param_layout(const nbvh_config* cfg, uint64_t* offsets) {
 size_t nbvh_aux_bytes(const nbvh_config* cfg) {
   DevCfg d;
   if (make_devcfg(cfg, &d) != NBVH_OK) return 0;
-  return (size_t)d.n_wt * 6;
+  return (size_t)aux_total_bytes(d);
 }
 
 size_t nbvh_nodes_bytes(uint32_t n_leaves) { return (size_t)(n_leaves > 1 ? n_leaves - 1 : 1) * sizeof(Node); }
@@ -347,7 +356,7 @@ nbvh_status nbvh_build(const nbvh_config* cfg, const float* leaf_boxes_host, uin
   hipDeviceProp_t prop;
   ctx->n_cu = (hipGetDeviceProperties(&prop, dev) == hipSuccess) ? prop.multiProcessorCount : 256;
   if (ctx->n_cu <= 0) ctx->n_cu = 256;
-  ctx->tune = nbvh_tuning{8, 0, 0, 8, 32, 144};
+  ctx->tune = nbvh_tuning{8, 0, 0, 8, 32, 144, 1};
   *out = ctx;
   return NBVH_OK;
 }
@@ -362,6 +371,7 @@ nbvh_status nbvh_bind_params(nbvh_ctx* ctx, const nbvh_params* p) {
     return set_error("parameter buffers must be 16-byte aligned"), NBVH_ERR_INVALID_ARG;
   ctx->p = *p;
   ctx->bound = true;
+  ctx->fp8_ready = false;
   return NBVH_OK;
 }
 
@@ -374,7 +384,8 @@ nbvh_status nbvh_reset_optimizer(nbvh_ctx* ctx, void* stream) {
   k_zero_f32<<<grid, 256, 0, L.stream>>>(L.adam_m, n);
   k_zero_f32<<<grid, 256, 0, L.stream>>>(L.adam_v, n);
   k_zero_f32<<<grid, 256, 0, L.stream>>>(L.grad, n);
-  k_zero_f32<<<grid, 256, 0, L.stream>>>((float*)L.aux, (ctx->dev.n_wt * 6 + 3) / 4);
+  k_zero_f32<<<grid, 256, 0, L.stream>>>((float*)L.aux, aux_total_bytes(ctx->dev) / 4);
+  ctx->fp8_ready = false;
   return launch_optimizer(L, true, true);
 }
 
@@ -382,14 +393,26 @@ nbvh_status nbvh_sync_shadow(nbvh_ctx* ctx, void* stream) {
   nbvh_status s = require_bound(ctx);
   if (s != NBVH_OK) return s;
   LaunchCtx L = make_launch(ctx, stream);
+  ctx->fp8_ready = false;
   return launch_optimizer(L, false, true);
+}
+
+nbvh_status nbvh_calibrate_fp8(nbvh_ctx* ctx, const nbvh_probe* probes, uint64_t n, void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  if (ctx->cfg.precision != NBVH_FP8) return set_error("context precision is not FP8"), NBVH_ERR_INVALID_ARG;
+  if (n == 0 || !probes) return set_error("calibration needs at least one segment"), NBVH_ERR_INVALID_ARG;
+  if (n > 0x7fffffffull) return set_error("batch too large"), NBVH_ERR_UNSUPPORTED;
+  s = launch_calibrate_fp8(make_launch(ctx, stream), probes, (uint32_t)n);
+  if (s == NBVH_OK) ctx->fp8_ready = true;
+  return s;
 }
 
 size_t nbvh_workspace_bytes(const nbvh_ctx* ctx, uint64_t max_rays, uint64_t max_segments, uint64_t max_batch) {
   if (!ctx) return 0;
   size_t q = query_layout(max_rays, max_segments).total;
   const int prec = ctx->cfg.precision == NBVH_FP8 ? NBVH_BF16 : ctx->cfg.precision;
-  size_t t = train_ws_bytes(ctx->dev, prec, max_batch, ctx->tune.wgrad_splits);
+  size_t t = train_ws_bytes(ctx->dev, prec, max_batch, ctx->tune);
   size_t l = a256((max_batch / 256 + 2) * 16);
   return std::max(q, std::max(t, l));
 }
@@ -414,6 +437,8 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbv
                        void* ws, size_t ws_bytes, void* stream) {
   nbvh_status s = require_bound(ctx);
   if (s != NBVH_OK) return s;
+  s = require_fp8_ready(ctx);
+  if (s != NBVH_OK) return s;
   if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
   if ((n_rays && (!rays || !hits)) || !ws) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
   if (seg_capacity > 0xffffffffull) seg_capacity = 0xffffffffull;
@@ -435,6 +460,8 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbv
 nbvh_status nbvh_query_segments(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, const uint32_t* seg_offsets,
                                 const nbvh_segment* segs, nbvh_hit* hits, void* ws, size_t ws_bytes, void* stream) {
   nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  s = require_fp8_ready(ctx);
   if (s != NBVH_OK) return s;
   if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
   if ((n_rays && (!rays || !hits || !seg_offsets || !segs)) || !ws) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
@@ -465,6 +492,8 @@ nbvh_status nbvh_forward(nbvh_ctx* ctx, const nbvh_probe* probes, uint64_t n, fl
   (void)ws_bytes;
   nbvh_status s = require_bound(ctx);
   if (s != NBVH_OK) return s;
+  s = require_fp8_ready(ctx);
+  if (s != NBVH_OK) return s;
   if (n && (!probes || !z)) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
   if (n > 0x7fffffffull) return set_error("batch too large"), NBVH_ERR_UNSUPPORTED;
   return launch_forward(make_launch(ctx, stream), probes, (uint32_t)n, z);
@@ -483,6 +512,7 @@ nbvh_status nbvh_backward(nbvh_ctx* ctx, const nbvh_probe* probes, uint64_t n, c
 nbvh_status nbvh_optimizer_step(nbvh_ctx* ctx, void* stream) {
   nbvh_status s = require_bound(ctx);
   if (s != NBVH_OK) return s;
+  ctx->fp8_ready = false;
   return launch_optimizer(make_launch(ctx, stream), false, false);
 }
 
@@ -569,12 +599,13 @@ nbvh_status nbvh_get_tuning(const nbvh_ctx* ctx, nbvh_tuning* out) {
 nbvh_status nbvh_set_tuning(nbvh_ctx* ctx, const nbvh_tuning* t) {
   if (!ctx || !t) return set_error("NULL argument"), NBVH_ERR_INVALID_ARG;
   if (t->query_waves != 4 && t->query_waves != 8) return set_error("query_waves must be 4 or 8"), NBVH_ERR_INVALID_ARG;
-  if (t->query_unroll != 0 && t->query_unroll != 1 && t->query_unroll != 2 && t->query_unroll != 4)
-    return set_error("query_unroll must be 0, 1, 2 or 4"), NBVH_ERR_INVALID_ARG;
+  if (t->query_unroll != 0 && (t->query_unroll < 2 || t->query_unroll > 4))
+    return set_error("query_unroll must be 0 (default), 2, 3 or 4"), NBVH_ERR_INVALID_ARG;
   if (t->query_wgs_per_cu < 0 || t->query_wgs_per_cu > 4) return set_error("query_wgs_per_cu in 0..4"), NBVH_ERR_INVALID_ARG;
   if (t->train_waves != 4 && t->train_waves != 8) return set_error("train_waves must be 4 or 8"), NBVH_ERR_INVALID_ARG;
   if (t->wgrad_splits < 1 || t->wgrad_splits > 256) return set_error("wgrad_splits in 1..256"), NBVH_ERR_INVALID_ARG;
   if (t->scatter_lds_kb < 0 || t->scatter_lds_kb > 144) return set_error("scatter_lds_kb in 0..144"), NBVH_ERR_INVALID_ARG;
+  if (t->scatter_binned != 0 && t->scatter_binned != 1) return set_error("scatter_binned must be 0 or 1"), NBVH_ERR_INVALID_ARG;
   ctx->tune = *t;
   return NBVH_OK;
 }
@@ -633,6 +664,10 @@ nbvh_status nbvh_batch_query(nbvh_batch* b, const nbvh_ray* rays, uint64_t n_ray
   std::vector<uint32_t*> cnt(n);
   const QueryLayout Q = query_layout(n_rays, seg_capacity);
   nbvh_hit* per_obj = (nbvh_hit*)((char*)ws + n * part);
+  for (int k = 0; k < n; ++k) {
+    nbvh_status s = require_fp8_ready(b->ctxs[k]);
+    if (s != NBVH_OK) return s;
+  }
   for (int k = 0; k < n; ++k) {
     Ls[k] = make_launch(b->ctxs[k], stream);
     char* w = (char*)ws + part * k;

@@ -3,13 +3,21 @@
 // and neighbouring segments share cache lines; waves stride over the
 // (sample, level) pairs.
 #pragma once
+#include "mlp_tile.h"
 #include "nbvh_internal.h"
 
 namespace nbvh {
 
 template <typename AT, int F>
-__device__ inline void store_features(AT* dst, const float v[F]) {
-  if constexpr (sizeof(AT) == 2) {
+__device__ inline void store_features(AT* dst, const float v[F], float qscale = 1.0f) {
+  if constexpr (sizeof(AT) == 1) {
+    const uint32_t w = pack_fp8x4(v[0] * qscale, v[1] * qscale, F == 4 ? v[2 % F] * qscale : 0.0f,
+                                  F == 4 ? v[3 % F] * qscale : 0.0f);
+    if constexpr (F == 2)
+      *(uint16_t*)dst = (uint16_t)w;
+    else
+      *(uint32_t*)dst = w;
+  } else if constexpr (sizeof(AT) == 2) {
     if constexpr (F == 2) {
       uint32_t w = (uint32_t)f32_to_bf16_bits(v[0]) | ((uint32_t)f32_to_bf16_bits(v[1]) << 16);
       *(uint32_t*)dst = w;
@@ -81,13 +89,48 @@ __device__ inline void unpack_raw(const typename RawEntry<F, LP>::T& r, float v[
   }
 }
 
+// Two adjacent table entries (an x-neighbour pair) as loaded.
+template <int F, bool LP>
+struct RawPair;
+template <>
+struct RawPair<2, true> {
+  typedef uint2 T;  // 2 entries x 2 bf16
+};
+template <>
+struct RawPair<4, true> {
+  typedef uint4 T;  // 2 entries x 4 bf16
+};
+template <>
+struct RawPair<2, false> {
+  typedef float4 T;  // 2 entries x 2 fp32
+};
+
+template <int F, bool LP>
+__device__ inline typename RawPair<F, LP>::T load_pair(const void* table, uint32_t param_index) {
+  typedef typename RawPair<F, LP>::T T;
+  const uint32_t byte_off = param_index * (LP ? 2u : 4u);
+  return *(const T*)((const char*)table + byte_off);
+}
+
+// entry 0 / 1 of a pair, as a raw entry
+template <int F, bool LP>
+__device__ inline typename RawEntry<F, LP>::T pair_half(const typename RawPair<F, LP>::T& p, bool second) {
+  if constexpr (LP && F == 2) return second ? p.y : p.x;
+  else if constexpr (LP && F == 4) return second ? uint2{p.z, p.w} : uint2{p.x, p.y};
+  else return second ? float2{p.z, p.w} : float2{p.x, p.y};
+}
+
 // Encode the M segments whose (o, t0) / (d, t1) sit in sA / sB into act0.
-// Each wave walks its (sample, level) pairs U at a time: all 8U gathers are
-// issued before any is consumed (U = 4 for 4-byte entries).
+// Each wave walks its (sample, level) pairs U at a time and issues all their
+// gathers before consuming any. Corners are fetched as x-neighbour pairs: on
+// dense levels (x, x+1) are adjacent entries; on hashed levels they are the
+// two halves of an aligned pair whenever x is even (the hash keeps x's low
+// bit), so one load serves both and lanes with odd x add one masked load.
 template <typename AT, int F, bool LP, int NWAVES, int UNROLL = 0>
 __device__ inline void encode_tile(const DevCfg& c, const void* table, const float4* sA, const float4* sB,
-                                   const int* s_valid, AT* act0, int ld0, int M) {
+                                   const int* s_valid, AT* act0, int ld0, int M, float qscale = 1.0f) {
   typedef typename RawEntry<F, LP>::T Raw;
+  constexpr bool kPairs = !(F == 4 && !LP);  // a 32-byte fp32 pair has no single load
   // by default 32..64 bytes of loads in flight per lane
   constexpr int U = UNROLL > 0 ? UNROLL : (sizeof(Raw) >= 16 ? 1 : 16 / (int)sizeof(Raw));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -119,11 +162,36 @@ __device__ inline void encode_tile(const DevCfg& c, const void* table, const flo
         cell_weight(x[2], N, cz, wz[u]);
         const uint32_t base = c.level_off[l];
         const bool ld = act[u] && valid;
+        if constexpr (kPairs) {
+          if (dense) {
+            const uint32_t r1 = (uint32_t)N + 1u;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const uint32_t idx = base + corner_index(dense, N, hmask, cx + (k & 1), cy + ((k >> 1) & 1),
-                                                   cz + ((k >> 2) & 1)) * F;
-          raw[u][k] = load_raw<F, LP>(table, ld ? idx : 0u);  // unconditional: no branch per gather
+            for (int j = 0; j < 4; ++j) {
+              const uint32_t i0 = base + ((uint32_t)cx + r1 * ((uint32_t)(cy + (j & 1)) + r1 * (uint32_t)(cz + (j >> 1)))) * F;
+              const auto p = load_pair<F, LP>(table, ld ? i0 : 0u);
+              raw[u][2 * j] = pair_half<F, LP>(p, false);
+              raw[u][2 * j + 1] = pair_half<F, LP>(p, true);
+            }
+          } else {
+            const bool even = (cx & 1) == 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const uint32_t hyz = ((uint32_t)(cy + (j & 1)) * 2654435761u) ^ ((uint32_t)(cz + (j >> 1)) * 805459861u);
+              const uint32_t h0 = ((uint32_t)cx ^ hyz) & hmask;
+              const uint32_t h1 = ((uint32_t)(cx + 1) ^ hyz) & hmask;
+              const auto p = load_pair<F, LP>(table, ld ? base + (h0 & ~1u) * F : 0u);
+              raw[u][2 * j] = pair_half<F, LP>(p, (h0 & 1u) != 0u);
+              raw[u][2 * j + 1] = even ? pair_half<F, LP>(p, (h1 & 1u) != 0u)
+                                       : load_raw<F, LP>(table, ld ? base + h1 * F : 0u);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const uint32_t idx = base + corner_index(dense, N, hmask, cx + (k & 1), cy + ((k >> 1) & 1),
+                                                     cz + ((k >> 2) & 1)) * F;
+            raw[u][k] = load_raw<F, LP>(table, ld ? idx : 0u);  // unconditional: no branch per gather
+          }
         }
       }
 #pragma unroll
@@ -145,7 +213,7 @@ __device__ inline void encode_tile(const DevCfg& c, const void* table, const flo
 #pragma unroll
           for (int f = 0; f < F; ++f) out[f] = 0.0f;
         }
-        store_features<AT, F>(act0 + (size_t)m * ld0 + col[u], out);
+        store_features<AT, F>(act0 + (size_t)m * ld0 + col[u], out, qscale);
       }
     }
   }

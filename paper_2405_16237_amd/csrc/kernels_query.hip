@@ -25,22 +25,27 @@ constexpr uint32_t kXcds = 8;  // accelerator complex dies of an MI355X; ray-que
 // (waves, unroll) pair; unroll 0 means "by entry size".
 #define NBVH_DISPATCH_UNROLL(AT, F, LP, NW, UNR, M)   \
   do {                                                 \
-    if ((UNR) == 1) M(AT, F, LP, NW, 1);                \
     if ((UNR) == 2) M(AT, F, LP, NW, 2);                \
+    if ((UNR) == 3) M(AT, F, LP, NW, 3);                \
     M(AT, F, LP, NW, 4);                               \
   } while (0)
-#define NBVH_DISPATCH_WAVES(AT, F, LP, Lc, M)                                                           \
-  do {                                                                                                  \
-    const int unr_ = (Lc).tune.query_unroll > 0 ? (Lc).tune.query_unroll                               \
-                                                : (16 / (F * (int)sizeof(AT)) >= 4 ? 4 : 16 / (F * (int)sizeof(AT))); \
-    if ((Lc).tune.query_waves == 4) NBVH_DISPATCH_UNROLL(AT, F, LP, 4, unr_, M);                       \
-    NBVH_DISPATCH_UNROLL(AT, F, LP, 8, unr_, M);                                                        \
+// default unroll: 3 for 4-byte table entries (bf16 pairs), else 2
+#define NBVH_DISPATCH_WAVES(AT, F, LP, Lc, M)                                                     \
+  do {                                                                                            \
+    const int unr_ = (Lc).tune.query_unroll > 0 ? (Lc).tune.query_unroll                         \
+                                                : ((F) * ((LP) ? 2 : 4) == 4 ? 3 : 2);            \
+    if ((Lc).tune.query_waves == 4) NBVH_DISPATCH_UNROLL(AT, F, LP, 4, unr_, M);                 \
+    NBVH_DISPATCH_UNROLL(AT, F, LP, 8, unr_, M);                                                  \
   } while (0)
 #define NBVH_DISPATCH_QUERY(Lc, M)                                               \
   do {                                                                           \
     if ((Lc).precision == NBVH_FP32) {                                          \
       if ((Lc).cfg.n_features == 2) NBVH_DISPATCH_WAVES(float, 2, false, Lc, M); \
       NBVH_DISPATCH_WAVES(float, 4, false, Lc, M);                              \
+    }                                                                           \
+    if ((Lc).fp8) {                                                              \
+      if ((Lc).cfg.n_features == 2) NBVH_DISPATCH_WAVES(fp8e4, 2, true, Lc, M); \
+      NBVH_DISPATCH_WAVES(fp8e4, 4, true, Lc, M);                               \
     }                                                                           \
     if ((Lc).cfg.n_features == 2) NBVH_DISPATCH_WAVES(bf16, 2, true, Lc, M);     \
     NBVH_DISPATCH_WAVES(bf16, 4, true, Lc, M);                                  \
@@ -60,6 +65,7 @@ __host__ __device__ inline size_t query_lds_bytes(int n_in, int width) {
 struct QueryJob {
   const void* table;
   const void* W;
+  const float* scales;  // FP8: weight scales [kMaxLayers], then activation scales
   const nbvh_ray* rays;
   const uint32_t* offsets;
   const nbvh_segment* segs;
@@ -154,9 +160,16 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
     __syncthreads();
     if (*s_any == 0) break;
 
-    encode_tile<AT, F, LP, NW, U>(c, J.table, sA, sB, s_valid, act0, ld0, kQM);
-    __syncthreads();
-    mlp_forward_tile<kQM, NW, AT>(c, (const AT*)J.W, act0, ld0, act1, ld1, z, kOutPad);
+    if constexpr (sizeof(AT) == 1) {
+      encode_tile<AT, F, LP, NW, U>(c, J.table, sA, sB, s_valid, act0, ld0, kQM, J.scales[kMaxLayers]);
+      __syncthreads();
+      mlp_forward_tile_fp8<kQM, NW>(c, (const uint8_t*)J.W, J.scales, (uint8_t*)act0, ld0, (uint8_t*)act1, ld1, z,
+                                    kOutPad);
+    } else {
+      encode_tile<AT, F, LP, NW, U>(c, J.table, sA, sB, s_valid, act0, ld0, kQM);
+      __syncthreads();
+      mlp_forward_tile<kQM, NW, AT>(c, (const AT*)J.W, act0, ld0, act1, ld1, z, kOutPad);
+    }
 
     if (wave == 0 && s_valid[lane]) {
       ++evaluated;
@@ -276,9 +289,9 @@ nbvh_status launch_active_rays(const LaunchCtx& L, const uint32_t* offsets, uint
 
 // Forward of probe segments: tile of 64 probes per workgroup, z -> global.
 template <typename AT, int F, bool LP>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_forward(DevCfg c, const void* __restrict__ table, const AT* __restrict__ W,
-                                                 const nbvh_probe* __restrict__ probes, uint32_t n,
-                                                 float* __restrict__ zout) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_forward(
+    DevCfg c, const void* __restrict__ table, const void* __restrict__ W, const float* __restrict__ scales,
+    const nbvh_probe* __restrict__ probes, uint32_t n, float* __restrict__ zout) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int ld0 = (c.n_in > c.width ? c.n_in : c.width) + Pad<AT>::v;
   const int ld1 = c.width + Pad<AT>::v;
@@ -298,9 +311,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     s_valid[threadIdx.x] = v ? 1 : 0;
   }
   __syncthreads();
-  encode_tile<AT, F, LP, kQWaves>(c, table, sA, sB, s_valid, act0, ld0, kQM);
-  __syncthreads();
-  mlp_forward_tile<kQM, kQWaves, AT>(c, W, act0, ld0, act1, ld1, z, kOutPad);
+  if constexpr (sizeof(AT) == 1) {
+    encode_tile<AT, F, LP, kQWaves>(c, table, sA, sB, s_valid, act0, ld0, kQM, scales[kMaxLayers]);
+    __syncthreads();
+    mlp_forward_tile_fp8<kQM, kQWaves>(c, (const uint8_t*)W, scales, (uint8_t*)act0, ld0, (uint8_t*)act1, ld1, z,
+                                       kOutPad);
+  } else {
+    encode_tile<AT, F, LP, kQWaves>(c, table, sA, sB, s_valid, act0, ld0, kQM);
+    __syncthreads();
+    mlp_forward_tile<kQM, kQWaves, AT>(c, (const AT*)W, act0, ld0, act1, ld1, z, kOutPad);
+  }
   for (int e = threadIdx.x; e < kQM * c.n_out; e += blockDim.x) {
     const int m = e / c.n_out, o = e - m * c.n_out;
     if (base + m < n) zout[(size_t)(base + m) * c.n_out + o] = z[m * kOutPad + o];
@@ -394,8 +414,10 @@ nbvh_status launch_query_eval_batch(const LaunchCtx* Ls, int n_obj, const DevCfg
   for (int k = 0; k < n_obj; ++k) {
     const LaunchCtx& Lk = Ls[k];
     QueryJob& J = jobs[k];
-    J.W = (Lk.precision != NBVH_FP32) ? (const void*)Lk.params_lp : (const void*)Lk.params;
-    J.table = J.W;
+    J.W = Lk.fp8 ? (const void*)((const char*)Lk.aux + fp8_weights_off(Lk.cfg))
+                 : (Lk.precision != NBVH_FP32) ? (const void*)Lk.params_lp : (const void*)Lk.params;
+    J.scales = (const float*)((const char*)Lk.aux + fp8_scales_off(Lk.cfg));
+    J.table = (Lk.precision != NBVH_FP32) ? (const void*)Lk.params_lp : (const void*)Lk.params;
     J.rays = rays;
     J.offsets = offsets[k];
     J.segs = segs[k];
@@ -424,7 +446,10 @@ static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const 
   const uint32_t need = (n_rays_bound + kQM - 1) / kQM;
   if (need < grid) grid = need > 0 ? need : 1;
   QueryJob J;
-  J.W = (sizeof(AT) == 2) ? (const void*)L.params_lp : (const void*)L.params;
+  J.W = (sizeof(AT) == 1)   ? (const void*)((const char*)L.aux + fp8_weights_off(c))
+        : (sizeof(AT) == 2) ? (const void*)L.params_lp
+                            : (const void*)L.params;
+  J.scales = (const float*)((const char*)L.aux + fp8_scales_off(c));
   J.table = LP ? (const void*)L.params_lp : (const void*)L.params;
   J.rays = rays;
   J.offsets = offsets;
@@ -456,17 +481,21 @@ static nbvh_status forward_t(const LaunchCtx& L, const nbvh_probe* probes, uint3
   const size_t lds = query_lds_bytes<AT>(c.n_in, c.width);
   auto kern = k_forward<AT, F, LP>;
   set_lds(kern, lds);
-  const AT* W = (sizeof(AT) == 2) ? (const AT*)L.params_lp : (const AT*)L.params;
+  const void* W = (sizeof(AT) == 1)   ? (const void*)((const char*)L.aux + fp8_weights_off(c))
+                  : (sizeof(AT) == 2) ? (const void*)L.params_lp
+                                      : (const void*)L.params;
+  const float* scales = (const float*)((const char*)L.aux + fp8_scales_off(c));
   const void* table = LP ? (const void*)L.params_lp : (const void*)L.params;
   if (n == 0) return NBVH_OK;
   ProfScope ps(L.prof, NBVH_K_FORWARD, L.stream);
-  kern<<<(n + kQM - 1) / kQM, 64 * kQWaves, lds, L.stream>>>(c, table, W, probes, n, z);
+  kern<<<(n + kQM - 1) / kQM, 64 * kQWaves, lds, L.stream>>>(c, table, W, scales, probes, n, z);
   return check_launch("forward");
 }
 
 nbvh_status launch_forward(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, float* z) {
   const int F = L.cfg.n_features;
   if (L.precision == NBVH_FP32) return F == 2 ? forward_t<float, 2, false>(L, probes, n, z) : forward_t<float, 4, false>(L, probes, n, z);
+  if (L.fp8) return F == 2 ? forward_t<fp8e4, 2, true>(L, probes, n, z) : forward_t<fp8e4, 4, true>(L, probes, n, z);
   return F == 2 ? forward_t<bf16, 2, true>(L, probes, n, z) : forward_t<bf16, 4, true>(L, probes, n, z);
 }
 
@@ -485,6 +514,123 @@ nbvh_status launch_encode(const LaunchCtx& L, const nbvh_probe* probes, uint32_t
     else k_encode<4, false><<<grid, 256, 0, L.stream>>>(c, table, probes, n, u);
   }
   return check_launch("encode");
+}
+
+
+// ---------------------------------------------------------------------------
+// FP8 calibration. Every amax is a maximum of non-negative floats, whose bit
+// patterns order like unsigned integers, so it is kept with integer atomicMax.
+__device__ inline void amax_lds(float* dst, float v) { atomicMax((unsigned int*)dst, __float_as_uint(v)); }
+
+__device__ inline float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+
+// amax |W_k| per layer: blockIdx.y = layer
+__global__ __launch_bounds__(256) void k_weight_amax(DevCfg c, const float* __restrict__ params,
+                                                     float* __restrict__ amax_w) {
+  const int k = blockIdx.y;
+  const float* W = params + c.w_off[k];
+  const uint64_t cnt = (uint64_t)c.fan_in[k] * c.fan_out[k];
+  float m = 0.0f;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (uint64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(W[i]));
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) amax_lds(amax_w + k, m);
+}
+
+// amax of each layer's input over a tile of calibration segments: the
+// encoded features (layer 0) and the ReLU outputs (layers 1..H), from the
+// BF16 table the FP8 query reads and the FP32 master weights.
+template <int F>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_calib_act(
+    DevCfg c, const void* __restrict__ table, const float* __restrict__ W, const nbvh_probe* __restrict__ probes,
+    uint32_t n, float* __restrict__ amax_act) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ld0 = (c.n_in > c.width ? c.n_in : c.width) + Pad<float>::v;
+  const int ld1 = c.width + Pad<float>::v;
+  float* act0 = (float*)smem;
+  float* act1 = act0 + (size_t)kQM * ld0;
+  float* z = act1 + (size_t)kQM * ld1;
+  float4* sA = (float4*)(z + kQM * kOutPad);
+  float4* sB = sA + kQM;
+  int* s_valid = (int*)(sB + kQM);
+  float* s_amax = (float*)(s_valid + kQM);  // [kMaxLayers], fits the 4 + 12 * kQM words after s_valid
+  const uint32_t base = blockIdx.x * kQM;
+  if (threadIdx.x < kQM) {
+    const uint32_t i = base + threadIdx.x;
+    const bool v = i < n;
+    const float4* p = (const float4*)(probes + (v ? i : 0));
+    sA[threadIdx.x] = p[0];
+    sB[threadIdx.x] = p[1];
+    s_valid[threadIdx.x] = v ? 1 : 0;
+  }
+  if (threadIdx.x < kMaxLayers) s_amax[threadIdx.x] = 0.0f;
+  __syncthreads();
+  encode_tile<float, F, true, kQWaves>(c, table, sA, sB, s_valid, act0, ld0, kQM);
+  __syncthreads();
+  float m0 = 0.0f;
+  for (int e = threadIdx.x; e < kQM * c.n_in; e += blockDim.x) {
+    const int m = e / c.n_in, k = e - m * c.n_in;
+    if (s_valid[m]) m0 = fmaxf(m0, fabsf(act0[(size_t)m * ld0 + k]));
+  }
+  m0 = wave_max(m0);
+  if ((threadIdx.x & 63) == 0) amax_lds(s_amax, m0);
+  mlp_forward_tile_keep<kQM, kQWaves, float>(c, W, act0, ld0, act1, ld1, z, kOutPad,
+                                             [&](int k, int m, int, f32x4 v) {
+                                               if (s_valid[m]) {
+                                                 const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
+                                                 amax_lds(s_amax + k + 1, mx);
+                                               }
+                                             });
+  __syncthreads();
+  if (threadIdx.x <= (unsigned)c.hidden) atomicMax((unsigned int*)(amax_act + threadIdx.x), __float_as_uint(s_amax[threadIdx.x]));
+}
+
+// scales from the amax values: 448 (the largest E4M3 value) / amax, 1 where
+// amax is zero
+__global__ __launch_bounds__(64) void k_fp8_scales(DevCfg c, float* __restrict__ f) {
+  const int k = threadIdx.x;
+  if (k > c.hidden) return;
+  const float aw = f[2 * kMaxLayers + k], aa = f[3 * kMaxLayers + k];
+  f[k] = aw > 0.0f ? 448.0f / aw : 1.0f;
+  f[kMaxLayers + k] = aa > 0.0f ? 448.0f / aa : 1.0f;
+}
+
+// E4M3 weights: W8_k = fp8(W_k * sw_k), four at a time; blockIdx.y = layer
+__global__ __launch_bounds__(256) void k_quantize_weights(DevCfg c, const float* __restrict__ params,
+                                                          const float* __restrict__ f, uint8_t* __restrict__ w8) {
+  const int k = blockIdx.y;
+  const float4* W = (const float4*)(params + c.w_off[k]);
+  uint32_t* dst = (uint32_t*)(w8 + (c.w_off[k] - c.w_off[0]));
+  const uint64_t cnt4 = (uint64_t)c.fan_in[k] * c.fan_out[k] / 4;
+  const float s = f[k];
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt4; i += (uint64_t)gridDim.x * blockDim.x) {
+    const float4 v = W[i];
+    dst[i] = pack_fp8x4(v.x * s, v.y * s, v.z * s, v.w * s);
+  }
+}
+
+nbvh_status launch_calibrate_fp8(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n) {
+  const DevCfg& c = L.cfg;
+  float* f = (float*)((char*)L.aux + fp8_scales_off(c));
+  uint8_t* w8 = (uint8_t*)L.aux + fp8_weights_off(c);
+  k_zero_u32<<<1, 64, 0, L.stream>>>((uint32_t*)(f + 2 * kMaxLayers), 2 * kMaxLayers);
+  k_weight_amax<<<dim3(64, c.hidden + 1), 256, 0, L.stream>>>(c, L.params, f + 2 * kMaxLayers);
+  const size_t lds = query_lds_bytes<float>(c.n_in, c.width);
+  const void* table = L.params_lp;
+  if (c.n_features == 2) {
+    set_lds(k_calib_act<2>, lds);
+    k_calib_act<2><<<(n + kQM - 1) / kQM, 64 * kQWaves, lds, L.stream>>>(c, table, L.params, probes, n, f + 3 * kMaxLayers);
+  } else {
+    set_lds(k_calib_act<4>, lds);
+    k_calib_act<4><<<(n + kQM - 1) / kQM, 64 * kQWaves, lds, L.stream>>>(c, table, L.params, probes, n, f + 3 * kMaxLayers);
+  }
+  k_fp8_scales<<<1, 64, 0, L.stream>>>(c, f);
+  k_quantize_weights<<<dim3(64, c.hidden + 1), 256, 0, L.stream>>>(c, L.params, f, w8);
+  return check_launch("calibrate_fp8");
 }
 
 }  // namespace nbvh

@@ -25,6 +25,8 @@ namespace nbvh {
 
 constexpr int kTM = 64;
 constexpr int kGPad = 32;  // gradient rows of the output layer padded to 32
+constexpr uint32_t kBinChunk = 16384;  // binned scatter: parameters (fp32) per bin
+constexpr int kBinWgs = 512;           // binned scatter: workgroups of the count / write passes
 
 __host__ __device__ inline int fan_out_pad(const DevCfg& c, int k) {
   return k == c.hidden ? kGPad : c.fan_out[k];
@@ -36,11 +38,17 @@ struct TrainLayout {
   size_t duT, wpart, loss_part, total;
   int nsplit;
   uint32_t n_tiles;
+  // binned scatter
+  int n_lds;
+  uint32_t lds_floats, n_bins;
+  uint64_t max_records;
+  size_t counts, offsets, scan_sums, rec_idx, rec_val;
 };
+static int coarse_lds_levels(const DevCfg& c, size_t budget_bytes, uint32_t* n_floats);
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_batch, int wgrad_splits) {
+static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_batch, const nbvh_tuning& tune) {
   TrainLayout T;
   const size_t es = precision == NBVH_FP32 ? 4 : 2;
   const uint64_t B = (max_batch + kTM - 1) / kTM * kTM;
@@ -55,19 +63,41 @@ static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_bat
   }
   T.duT = off;
   off = align256(off + (size_t)c.n_in * B * 4);
-  T.nsplit = wgrad_splits > 0 ? wgrad_splits : 32;
+  T.nsplit = tune.wgrad_splits > 0 ? tune.wgrad_splits : 32;
   T.wpart = off;
   off = align256(off + (size_t)T.nsplit * (c.n_params - c.w_off[0]) * 4);
   T.n_tiles = (uint32_t)(B / kTM);
   T.loss_part = off;
   off = align256(off + (size_t)T.n_tiles * 4 * 4);
+  const int budget_kb = tune.scatter_lds_kb < 0 ? 0 : (tune.scatter_lds_kb > 144 ? 144 : tune.scatter_lds_kb);
+  T.lds_floats = 0;
+  T.n_lds = budget_kb > 0 ? coarse_lds_levels(c, (size_t)budget_kb * 1024, &T.lds_floats) : 0;
+  T.n_bins = 0;
+  T.max_records = 0;
+  T.counts = T.offsets = T.scan_sums = T.rec_idx = T.rec_val = off;
+  if (tune.scatter_binned && T.n_lds < c.n_levels) {
+    const uint64_t off0 = c.level_off[T.n_lds];
+    T.n_bins = (uint32_t)((c.n_table - off0 + kBinChunk - 1) / kBinChunk);
+    T.max_records = B * (uint64_t)(c.n_levels - T.n_lds) * c.n_samples * 8;
+    const size_t cells = (size_t)T.n_bins * kBinWgs;
+    T.counts = off;
+    off = align256(off + cells * 4);
+    T.offsets = off;
+    off = align256(off + (cells + 1) * 4);
+    T.scan_sums = off;
+    off = align256(off + (cells / 1024 + 4) * 4);
+    T.rec_idx = off;
+    off = align256(off + T.max_records * 2);
+    T.rec_val = off;
+    off = align256(off + T.max_records * c.n_features * 4);
+  }
   T.total = off;
   return T;
 }
 
-size_t train_ws_bytes(const DevCfg& c, int precision, uint64_t max_batch, int wgrad_splits) {
+size_t train_ws_bytes(const DevCfg& c, int precision, uint64_t max_batch, const nbvh_tuning& tune) {
   if (max_batch == 0) return 0;
-  return train_layout(c, precision, max_batch, wgrad_splits).total;
+  return train_layout(c, precision, max_batch, tune).total;
 }
 
 template <typename AT>
@@ -482,21 +512,182 @@ __global__ __launch_bounds__(256) void k_scatter_pairs(DevCfg c, int l_begin, co
   }
 }
 
+// ---------------------------------------------------------------------------
+// Binned scatter for the levels outside LDS: a counting sort of the
+// contributions by 64 KiB table chunk, then one workgroup per chunk adds its
+// records with LDS atomics and updates its chunk of the gradient with plain
+// coalesced read-modify-writes (it is the chunk's only writer), so these
+// levels need no global atomics at all.
+
+// Walk the samples of probe p at level l, merging consecutive samples that
+// fall into the same cell, and hand every (entry, F values) contribution to
+// emit(param_index, vals).
+template <int F, typename Emit>
+__device__ inline void level_runs(const DevCfg& c, int l, const nbvh_probe* __restrict__ probes, uint32_t p,
+                                  const float* __restrict__ duT, uint64_t ldb, Emit emit) {
+  const int N = c.level_res[l];
+  const bool dense = (c.dense_mask >> l) & 1u;
+  const uint32_t mask = (1u << c.log2_T) - 1u;
+  const uint32_t base = c.level_off[l];
+  const float4* pp = (const float4*)(probes + p);
+  const float4 a = pp[0], b = pp[1];
+  const float o[3] = {a.x, a.y, a.z}, d[3] = {b.x, b.y, b.z};
+  int ccx = -1, ccy = -1, ccz = -1;
+  float acc[8][F];
+  float wxs = 0.f, wys = 0.f, wzs = 0.f;
+  (void)wxs;
+  (void)wys;
+  (void)wzs;
+  for (int s = 0; s < c.n_samples; ++s) {
+    float g[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) g[f] = duT[(size_t)((s * c.n_levels + l) * F + f) * ldb + p];
+    float x[3];
+    sample_position(c, o, d, a.w, b.w, s, x);
+    int cx, cy, cz;
+    float wx, wy, wz;
+    cell_weight(x[0], N, cx, wx);
+    cell_weight(x[1], N, cy, wy);
+    cell_weight(x[2], N, cz, wz);
+    if (cx != ccx || cy != ccy || cz != ccz) {
+      if (ccx >= 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          emit(base + corner_index(dense, N, mask, ccx + (k & 1), ccy + ((k >> 1) & 1), ccz + ((k >> 2) & 1)) * F,
+               acc[k]);
+      }
+      ccx = cx;
+      ccy = cy;
+      ccz = cz;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int f = 0; f < F; ++f) acc[k][f] = 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float w = ((k & 1) ? wx : 1.0f - wx) * (((k >> 1) & 1) ? wy : 1.0f - wy) * (((k >> 2) & 1) ? wz : 1.0f - wz);
+#pragma unroll
+      for (int f = 0; f < F; ++f) acc[k][f] = __builtin_fmaf(w, g[f], acc[k][f]);
+    }
+  }
+  if (ccx >= 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      emit(base + corner_index(dense, N, mask, ccx + (k & 1), ccy + ((k >> 1) & 1), ccz + ((k >> 2) & 1)) * F, acc[k]);
+  }
+}
+
+struct BinArgs {
+  int l_begin;        // first binned level
+  uint32_t off0;      // its first parameter
+  uint32_t n_bins;
+  uint32_t n_tasks;   // probes x binned levels
+  uint32_t per_wg;    // tasks per workgroup
+};
+
+// pass 1: per-workgroup histogram of record bins -> counts[bin][wg]
 template <int F>
-static void launch_scatter(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, const float* duT, uint64_t ldb) {
+__global__ __launch_bounds__(256) void k_bin_count(DevCfg c, BinArgs A, const nbvh_probe* __restrict__ probes,
+                                                   uint32_t n, const float* __restrict__ duT, uint64_t ldb,
+                                                   uint32_t* __restrict__ counts) {
+  extern __shared__ uint32_t hist[];
+  for (uint32_t i = threadIdx.x; i < A.n_bins; i += blockDim.x) hist[i] = 0u;
+  __syncthreads();
+  const uint32_t t0 = blockIdx.x * A.per_wg, t1 = min(A.n_tasks, t0 + A.per_wg);
+  for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+    const uint32_t li = t / n, p = t - li * n;
+    level_runs<F>(c, A.l_begin + (int)li, probes, p, duT, ldb, [&](uint32_t idx, const float*) {
+      atomicAdd(&hist[(idx - A.off0) / kBinChunk], 1u);
+    });
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < A.n_bins; i += blockDim.x) counts[(size_t)i * gridDim.x + blockIdx.x] = hist[i];
+}
+
+// pass 2: write every record at its place: offsets = exclusive scan of counts
+template <int F>
+__global__ __launch_bounds__(256) void k_bin_write(DevCfg c, BinArgs A, const nbvh_probe* __restrict__ probes,
+                                                   uint32_t n, const float* __restrict__ duT, uint64_t ldb,
+                                                   const uint32_t* __restrict__ offsets, uint16_t* __restrict__ rec_idx,
+                                                   float* __restrict__ rec_val) {
+  extern __shared__ uint32_t cursor[];
+  for (uint32_t i = threadIdx.x; i < A.n_bins; i += blockDim.x) cursor[i] = offsets[(size_t)i * gridDim.x + blockIdx.x];
+  __syncthreads();
+  const uint32_t t0 = blockIdx.x * A.per_wg, t1 = min(A.n_tasks, t0 + A.per_wg);
+  for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+    const uint32_t li = t / n, p = t - li * n;
+    level_runs<F>(c, A.l_begin + (int)li, probes, p, duT, ldb, [&](uint32_t idx, const float* v) {
+      const uint32_t rel = idx - A.off0;
+      const uint32_t slot = atomicAdd(&cursor[rel / kBinChunk], 1u);
+      rec_idx[slot] = (uint16_t)(rel % kBinChunk);
+#pragma unroll
+      for (int f = 0; f < F; ++f) rec_val[(size_t)slot * F + f] = v[f];
+    });
+  }
+}
+
+// pass 3: one workgroup per bin accumulates in LDS and updates its chunk
+template <int F>
+__global__ __launch_bounds__(1024) void k_bin_reduce(BinArgs A, const uint32_t* __restrict__ offsets, uint32_t n_wgs,
+                                                     const uint16_t* __restrict__ rec_idx,
+                                                     const float* __restrict__ rec_val, uint64_t n_table,
+                                                     float* __restrict__ grad) {
+  __shared__ float acc[kBinChunk];
+  const uint32_t bin = blockIdx.x;
+  for (uint32_t i = threadIdx.x; i < kBinChunk; i += blockDim.x) acc[i] = 0.0f;
+  __syncthreads();
+  const uint32_t r0 = offsets[(size_t)bin * n_wgs];
+  const uint32_t r1 = offsets[(size_t)(bin + 1) * n_wgs];  // offsets[n_bins * n_wgs] is the total
+  for (uint32_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const uint32_t e = rec_idx[r];
+#pragma unroll
+    for (int f = 0; f < F; ++f) atomicAdd(&acc[e + f], rec_val[(size_t)r * F + f]);
+  }
+  __syncthreads();
+  const uint64_t g0 = (uint64_t)A.off0 + (uint64_t)bin * kBinChunk;
+  const uint32_t len = (uint32_t)min((uint64_t)kBinChunk, n_table - g0);
+  for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+    const float v = acc[i];
+    if (v != 0.0f) grad[g0 + i] += v;
+  }
+}
+
+template <int F>
+static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char* w, const nbvh_probe* probes,
+                                  uint32_t n, const float* duT, uint64_t ldb) {
   const DevCfg& c = L.cfg;
-  uint32_t n_floats = 0;
-  const int budget_kb = L.tune.scatter_lds_kb < 0 ? 0 : (L.tune.scatter_lds_kb > 144 ? 144 : L.tune.scatter_lds_kb);
-  const int n_lds = budget_kb > 0 ? coarse_lds_levels(c, (size_t)budget_kb * 1024, &n_floats) : 0;
-  if (n_lds > 0) {
-    const size_t lds = (size_t)n_floats * 4;
+  if (T.n_lds > 0) {
+    const size_t lds = (size_t)T.lds_floats * 4;
     (void)hipFuncSetAttribute((const void*)k_scatter_lds<F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_scatter_lds<F><<<L.n_cu, 1024, lds, L.stream>>>(c, n_lds, n_floats, probes, n, duT, ldb, L.grad);
+    k_scatter_lds<F><<<L.n_cu, 1024, lds, L.stream>>>(c, T.n_lds, T.lds_floats, probes, n, duT, ldb, L.grad);
   }
-  if (n_lds < c.n_levels) {
-    const uint64_t threads = (uint64_t)n * (c.n_levels - n_lds) * 2 * F;
-    k_scatter_pairs<F><<<(uint32_t)((threads + 255) / 256), 256, 0, L.stream>>>(c, n_lds, probes, n, duT, ldb, L.grad);
+  if (T.n_lds >= c.n_levels) return check_launch("scatter");
+  if (T.n_bins == 0) {
+    const uint64_t threads = (uint64_t)n * (c.n_levels - T.n_lds) * 2 * F;
+    k_scatter_pairs<F><<<(uint32_t)((threads + 255) / 256), 256, 0, L.stream>>>(c, T.n_lds, probes, n, duT, ldb, L.grad);
+    return check_launch("scatter");
   }
+  BinArgs A;
+  A.l_begin = T.n_lds;
+  A.off0 = c.level_off[T.n_lds];
+  A.n_bins = T.n_bins;
+  A.n_tasks = n * (uint32_t)(c.n_levels - T.n_lds);
+  A.per_wg = (A.n_tasks + kBinWgs - 1) / kBinWgs;
+  uint32_t* counts = (uint32_t*)(w + T.counts);
+  uint32_t* offsets = (uint32_t*)(w + T.offsets);
+  uint32_t* sums = (uint32_t*)(w + T.scan_sums);
+  const size_t hist_lds = (size_t)T.n_bins * 4;
+  if (hist_lds > 64 * 1024) return set_error("too many gradient bins (%u) for LDS", T.n_bins), NBVH_ERR_UNSUPPORTED;
+  k_bin_count<F><<<kBinWgs, 256, hist_lds, L.stream>>>(c, A, probes, n, duT, ldb, counts);
+  const uint32_t cells = T.n_bins * (uint32_t)kBinWgs;
+  nbvh_status s = launch_exclusive_scan(L.stream, counts, cells, offsets, sums, sums + cells / 1024 + 3);
+  if (s != NBVH_OK) return s;
+  k_bin_write<F><<<kBinWgs, 256, hist_lds, L.stream>>>(c, A, probes, n, duT, ldb, offsets, (uint16_t*)(w + T.rec_idx),
+                                                      (float*)(w + T.rec_val));
+  k_bin_reduce<F><<<T.n_bins, 1024, 0, L.stream>>>(A, offsets, kBinWgs, (const uint16_t*)(w + T.rec_idx),
+                                                   (const float*)(w + T.rec_val), c.n_table, L.grad);
+  return check_launch("scatter");
 }
 
 // ---------------------------------------------------------------------------
@@ -683,7 +874,7 @@ template <typename AT, int F, bool LP>
 static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const nbvh_label* labels, const float* dz_in,
                            uint32_t n, float* loss_dev, void* ws, size_t ws_bytes) {
   const DevCfg& c = L.cfg;
-  const TrainLayout T = train_layout(c, L.precision, n, L.tune.wgrad_splits);
+  const TrainLayout T = train_layout(c, L.precision, n, L.tune);
   if (ws_bytes < T.total) {
     set_error("workspace too small for a batch of %u: need %zu bytes, got %zu", n, T.total, ws_bytes);
     return NBVH_ERR_CAPACITY;
@@ -738,7 +929,8 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
   }
   {
     ProfScope ps(L.prof, NBVH_K_SCATTER, L.stream);
-    launch_scatter<F>(L, probes, n, P.duT, kb);
+    nbvh_status s = launch_scatter<F>(L, T, w, probes, n, P.duT, kb);
+    if (s != NBVH_OK) return s;
   }
   return check_launch("train");
 }

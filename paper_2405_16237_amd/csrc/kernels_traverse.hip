@@ -242,12 +242,23 @@ __global__ __launch_bounds__(256) void k_scan_add(uint32_t* __restrict__ out, ui
   if (i == 0) {
     const uint32_t t = *total;
     out[n] = t;
-    state->last_n_segments = t;
-    if ((uint64_t)t > capacity) atomicOr(&state->flags, NBVH_FLAG_CAPACITY);
+    if (state) {
+      state->last_n_segments = t;
+      if ((uint64_t)t > capacity) atomicOr(&state->flags, NBVH_FLAG_CAPACITY);
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
+nbvh_status launch_exclusive_scan(hipStream_t s, const uint32_t* in, uint32_t n, uint32_t* out, uint32_t* sums,
+                                  uint32_t* total_out) {
+  const uint32_t n_tiles = (n + kScanTile - 1) / kScanTile;
+  if (n > 0) k_scan_tiles<<<n_tiles, 256, 0, s>>>(in, n, out, sums);
+  k_scan_sums<<<1, 1024, 0, s>>>(sums, n_tiles, total_out);
+  k_scan_add<<<n > 0 ? (n + 255) / 256 : 1, 256, 0, s>>>(out, n, sums, total_out, 0, nullptr);
+  return check_launch("scan");
+}
+
 nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n_rays, uint32_t* offsets,
                             nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
                             uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,

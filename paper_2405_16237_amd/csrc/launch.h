@@ -60,7 +60,8 @@ struct LaunchCtx {
   float* adam_m;
   float* adam_v;
   float* grad;
-  void* aux;  // transposed weight copies: fp32 [n_mlp] then bf16 [n_mlp]
+  void* aux;  // transposed weight copies: fp32 [n_wt] then bf16 [n_wt]; FP8 block
+  bool fp8;   // queries and forward run the MLP in FP8 (weights and scales in aux)
   int n_cu;
   // training hyper-parameters
   float w_hit, w_t, w_normal, w_albedo;
@@ -96,8 +97,16 @@ nbvh_status launch_encode(const LaunchCtx& L, const nbvh_probe* probes, uint32_t
 
 nbvh_status launch_forward(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, float* z);
 
+// FP8 calibration: weight scales from the FP32 master weights, activation
+// scales from an FP32 forward of the given segments, then E4M3 weights.
+nbvh_status launch_calibrate_fp8(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n);
+
 // training
-size_t train_ws_bytes(const DevCfg& c, int precision, uint64_t max_batch, int wgrad_splits);
+size_t train_ws_bytes(const DevCfg& c, int precision, uint64_t max_batch, const nbvh_tuning& tune);
+// out[0..n] = exclusive prefix sums of in[0..n) (out[n] = total); sums needs
+// n / 1024 + 2 words, total_out one word
+nbvh_status launch_exclusive_scan(hipStream_t s, const uint32_t* in, uint32_t n, uint32_t* out, uint32_t* sums,
+                                  uint32_t* total_out);
 nbvh_status launch_train_fwd_bwd(const LaunchCtx& L, const nbvh_probe* probes, const nbvh_label* labels,
                                  const float* dz_in, uint32_t n, float* loss_dev, void* ws, size_t ws_bytes,
                                  bool apply_grad);

@@ -15,8 +15,18 @@
 
 namespace nbvh {
 
+// FP8 E4M3 (OCP) activation byte
+struct fp8e4 {
+  uint8_t v;
+};
+
 template <typename AT>
 struct Pad;
+template <>
+struct Pad<fp8e4> {
+  static constexpr int v = 16;  // bytes: rows start 4 banks apart
+  static constexpr int kstep = 32;
+};
 template <>
 struct Pad<bf16> {
   static constexpr int v = 8;  // 16 bytes per row: rows start 4 banks apart
@@ -101,6 +111,84 @@ __device__ inline void gemm_tile_f32(const float* act_in, int ld_in, int K, cons
     const int col = nt * 16 + 4 * q;
 #pragma unroll
     for (int mt = 0; mt < M / 16; ++mt) epi(mt * 16 + r16, col, acc[mt]);
+  }
+}
+
+// FP8 x FP8 -> FP32, 16x16x32 MFMA: 8 bytes of k per lane, same lane layout
+// as the BF16 path.
+template <int M, int NWAVES, typename Epi>
+__device__ inline void gemm_tile_fp8(const uint8_t* act_in, int ld_in, int K, const uint8_t* __restrict__ W, int ldw,
+                                     int N, Epi epi) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int n_tiles = (N + 15) >> 4;
+  for (int nt = wave; nt < n_tiles; nt += NWAVES) {
+    f32x4 acc[M / 16];
+#pragma unroll
+    for (int mt = 0; mt < M / 16; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int n = nt * 16 + r16;
+    const bool nvalid = n < N;
+    const uint8_t* wrow = W + (size_t)(nvalid ? n : 0) * ldw + 8 * q;
+    const uint8_t* arow = act_in + (size_t)r16 * ld_in + 8 * q;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      const long a = nvalid ? *(const long*)(wrow + k0) : 0l;
+#pragma unroll
+      for (int mt = 0; mt < M / 16; ++mt) {
+        const long b = *(const long*)(arow + (size_t)mt * 16 * ld_in + k0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc[mt], 0, 0, 0);
+      }
+    }
+    const int col = nt * 16 + 4 * q;
+#pragma unroll
+    for (int mt = 0; mt < M / 16; ++mt) epi(mt * 16 + r16, col, acc[mt]);
+  }
+}
+
+// Quantise to FP8 E4M3 with saturation at +-448 (the format's largest value).
+__device__ inline uint32_t pack_fp8x4(float a, float b, float c, float d) {
+  a = fminf(fmaxf(a, -448.0f), 448.0f);
+  b = fminf(fmaxf(b, -448.0f), 448.0f);
+  c = fminf(fmaxf(c, -448.0f), 448.0f);
+  d = fminf(fmaxf(d, -448.0f), 448.0f);
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+  return (uint32_t)w;
+}
+
+// FP8 forward of a tile: act0 holds the input quantised with sa[0];
+// W8 the weights quantised with sw[k]; each hidden output is dequantised,
+// ReLU'd and requantised with sa[k+1]; z receives FP32 logits.
+template <int M, int NWAVES>
+__device__ inline void mlp_forward_tile_fp8(const DevCfg& c, const uint8_t* W8base, const float* scales,
+                                            uint8_t* act0, int ld0, uint8_t* act1, int ld1, float* z, int ldz) {
+  uint8_t* cur = act0;
+  int ldc = ld0;
+  uint8_t* nxt = act1;
+  int ldn = ld1;
+  for (int k = 0; k <= c.hidden; ++k) {
+    const bool last = (k == c.hidden);
+    const uint8_t* W = W8base + (c.w_off[k] - c.w_off[0]);
+    const float dq = 1.0f / (scales[k] * scales[kMaxLayers + k]);  // 1 / (sw_k * sa_k)
+    if (last) {
+      gemm_tile_fp8<M, NWAVES>(cur, ldc, c.fan_in[k], W, c.fan_in[k], c.fan_out[k], [&](int m, int col, f32x4 v) {
+        *(f32x4*)(z + (size_t)m * ldz + col) = v * dq;
+      });
+    } else {
+      const float qn = scales[kMaxLayers + k + 1];
+      gemm_tile_fp8<M, NWAVES>(cur, ldc, c.fan_in[k], W, c.fan_in[k], c.fan_out[k], [&](int m, int col, f32x4 v) {
+        f32x4 r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = fmaxf(v[i] * dq, 0.0f) * qn;
+        *(uint32_t*)(nxt + (size_t)m * ldn + col) = pack_fp8x4(r[0], r[1], r[2], r[3]);
+      });
+    }
+    __syncthreads();
+    uint8_t* t = cur;
+    cur = nxt;
+    nxt = t;
+    int tl = ldc;
+    ldc = ldn;
+    ldn = tl;
   }
 }
 

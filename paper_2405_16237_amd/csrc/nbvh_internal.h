@@ -51,6 +51,18 @@ struct DevCfg {
   int32_t fan_in[kMaxLayers], fan_out[kMaxLayers];
 };
 
+// FP8 block of the auxiliary buffer, after the transposed FP32 and BF16
+// weight copies (6 bytes per element): E4M3 weights, layer k at byte
+// w_off[k] - w_off[0] in the same row-major [fan_out][fan_in] order as the
+// parameters, then kFp8Floats floats: weight scales sw[k], activation scales
+// sa[k] (input of layer k), and the amax values they come from.
+constexpr int kFp8Floats = 4 * kMaxLayers;
+__host__ __device__ inline uint64_t fp8_weights_off(const DevCfg& c) { return (c.n_wt * 6 + 255) / 256 * 256; }
+__host__ __device__ inline uint64_t fp8_scales_off(const DevCfg& c) {
+  return (fp8_weights_off(c) + (c.n_params - c.w_off[0]) + 255) / 256 * 256;
+}
+__host__ __device__ inline uint64_t aux_total_bytes(const DevCfg& c) { return fp8_scales_off(c) + kFp8Floats * 4; }
+
 // ---------------------------------------------------------------------------
 // bf16 helpers (round to nearest even, as the hardware conversion)
 // ---------------------------------------------------------------------------

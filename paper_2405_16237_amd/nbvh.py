@@ -129,6 +129,21 @@ class NBVH:
     def reset_optimizer(self):
         check(self.lib.nbvh_reset_optimizer(self.ctx, _stream()))
 
+    def calibrate_fp8(self, probes: torch.Tensor):
+        """FP8 contexts: per-layer weight and activation scales from the
+        calibration segments probes [n][8] float32, then E4M3 weights.
+        Needed again after every parameter change."""
+        assert probes.is_cuda and probes.dtype == torch.float32 and probes.is_contiguous()
+        check(self.lib.nbvh_calibrate_fp8(self.ctx, _ptr(probes), probes.shape[0], _stream()))
+
+    def fp8_scales(self) -> dict:
+        """Weight scales sw[k] and activation scales sa[k] (k = 0..mlp_hidden)
+        written by the last calibration."""
+        n = self.net.mlp_hidden + 1
+        off = self.lib.nbvh_aux_bytes(ctypes.byref(self.cfg)) - 4 * 4 * 9
+        f = self.aux[off:off + 4 * 4 * 9].view(torch.float32).cpu().numpy()
+        return dict(sw=f[:n].copy(), sa=f[9:9 + n].copy(), amax_w=f[18:18 + n].copy(), amax_a=f[27:27 + n].copy())
+
     # -- workspace ------------------------------------------------------------------
     def workspace(self, max_rays=0, max_segments=0, max_batch=0) -> torch.Tensor:
         need = self.lib.nbvh_workspace_bytes(self.ctx, max_rays, max_segments, max_batch)

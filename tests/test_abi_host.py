@@ -23,7 +23,7 @@ def abi():
 def _declared():
     src = open(os.path.join(ROOT, "include", "nbvh.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(nbvh_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(nbvh_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_every_declared_symbol_is_exported(abi):

@@ -133,6 +133,12 @@ def test_autotuner_keeps_results(objects):
     P, objs = objects
     from paper_2405_16237_amd import autotune
     sc, net, params = objs[2]
+    # with these seeded weights almost every hit logit is negative; negating
+    # the hit row of the output layer makes most segments hits, so t and
+    # normals take part in the comparison
+    params = params.copy()
+    w_out = params.size - net.n_out * net.mlp_width
+    params[w_out:w_out + net.mlp_width] *= -1.0
     m = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16")
     m.set_params(params)
     centre = sc.lo.astype(np.float64) + sc.side / 2
@@ -143,9 +149,9 @@ def test_autotuner_keeps_results(objects):
     probes = torch.from_numpy(p).cuda()
     _say("autotune")
     rep = autotune.autotune(m, rays=rays, probes=probes, reps=1)
-    assert len(rep["query"]) == 24 and len(rep["train"]) == 18
+    assert len(rep["query"]) == 18 and len(rep["train"]) == 24
     assert m.get_tuning() == rep["tuning"]
-    for knobs in ({"query_waves": 4, "query_unroll": 1, "query_wgs_per_cu": 1}, {"query_waves": 8, "query_unroll": 2}):
+    for knobs in ({"query_waves": 4, "query_unroll": 2, "query_wgs_per_cu": 1}, {"query_waves": 8, "query_unroll": 4}):
         m.set_tuning(**knobs)
         got = m.query(rays).view(torch.int32)
         assert torch.equal(got, ref), knobs

@@ -131,6 +131,9 @@ NETS = {
     "c2": configs.C2_NET,
     # F = 4, hashed fine levels, width 32 (smallest tile shapes)
     "f4": _net(8, 4, 12, 4, [4, 6, 9, 14, 21, 32, 48, 72], 32, 2, 8),
+    # the secondary-ray workload's network (16 levels, F = 4, 4 samples,
+    # 256 -> 4x256 -> 8 with albedo) on a 2^16-entry table
+    "c5": configs.NetConfig(16, 4, 16, 4, 16, 1.38, 256, 4, 8),
 }
 
 
@@ -140,7 +143,7 @@ def _probes(sc, n, seed):
     return p[rng.permutation(p.shape[0])[:n]]
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "f4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "f4", "c5"])
 def test_encode_fp32(lib, c1, name):
     sc, _ = c1
     net = NETS[name]
@@ -155,7 +158,7 @@ def test_encode_fp32(lib, c1, name):
     assert r.max() <= 1e-5, r.max()
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "f4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "f4", "c5"])
 def test_encode_bf16_table(lib, c1, name):
     sc, _ = c1
     net = NETS[name]
@@ -170,7 +173,7 @@ def test_encode_bf16_table(lib, c1, name):
     assert r.max() <= 1e-5, r.max()
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "f4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "f4", "c5"])
 def test_forward_fp32(lib, c1, name):
     sc, _ = c1
     net = NETS[name]
@@ -185,7 +188,7 @@ def test_forward_fp32(lib, c1, name):
     assert r.max() <= 1e-5, r.max()
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "f4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "f4", "c5"])
 def test_forward_bf16(lib, c1, name):
     sc, _ = c1
     net = NETS[name]
@@ -287,7 +290,7 @@ def test_loss_matches_oracle(lib, c1):
     assert np.abs(dz.cpu().numpy() - dzo).max() <= 1e-5 * np.abs(dzo).max()
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "f4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "f4", "c5"])
 def test_backward_fp32(lib, c1, name):
     sc, _ = c1
     net = NETS[name]

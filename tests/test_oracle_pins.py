@@ -272,6 +272,45 @@ def test_mlp_identity_weights():
     assert np.array_equal(z, np.maximum(u, 0.0)[:, :5])
 
 
+def test_layer_amax_identity_network():
+    """With W_0 = +-I and W_1 = I the hidden layers carry ReLU(+-u), so the
+    per-layer maxima are max|u|, then the largest positive (or negated
+    negative) feature twice. The table is shifted negative so that max|u|,
+    max u+ and max (-u)+ all differ."""
+    net = Net(2, 2, 8, 2, [3, 5], mlp_width=8, mlp_hidden=2, n_out=5)
+    cfg = _cfg(net, (-1, -1, -1), 2.0)
+    rng = np.random.default_rng(33)
+    table = rng.normal(size=oracle.n_table_params(cfg)) - 0.4
+    segs = _random_segments(rng, 200)
+    u = oracle.encode(cfg, table, segs)
+    assert u.max() > 0 and -u.min() > u.max()
+    for sign in (1.0, -1.0):
+        W = np.concatenate([sign * np.eye(8).reshape(-1), np.eye(8).reshape(-1), np.eye(5, 8).reshape(-1)])
+        a = oracle.layer_amax(cfg, np.concatenate([table, W]), segs)
+        top = np.maximum(sign * u, 0.0).max()
+        assert a.shape == (3,)
+        assert a[0] == np.abs(u).max() and a[1] == top and a[2] == top
+
+
+def test_layer_amax_positive_homogeneity():
+    """ReLU(c x) = c ReLU(x) for c > 0: scaling W_1 by 3 triples the maximum
+    of layer 2's input only."""
+    net = Net(2, 2, 8, 2, [3, 5], mlp_width=16, mlp_hidden=3, n_out=5)
+    cfg = _cfg(net, (-1, -1, -1), 2.0)
+    rng = np.random.default_rng(34)
+    table = rng.normal(size=oracle.n_table_params(cfg))
+    W = rng.normal(size=oracle.n_mlp_params(cfg)) * 0.5
+    segs = _random_segments(rng, 300)
+    a = oracle.layer_amax(cfg, np.concatenate([table, W]), segs)
+    W3 = W.copy()
+    o = 8 * 16
+    W3[o:o + 16 * 16] *= 3.0
+    b = oracle.layer_amax(cfg, np.concatenate([table, W3]), segs)
+    assert np.all(a > 0)
+    assert b[0] == a[0] and b[1] == a[1]
+    assert abs(b[2] - 3.0 * a[2]) <= 1e-12 * a[2] and abs(b[3] - 3.0 * a[3]) <= 1e-12 * a[3]
+
+
 # ---------------------------------------------------------------- loss
 def _labels(rng, n, hit_frac=0.5):
     lab = np.zeros((n, 8), dtype=np.float32)
