@@ -62,6 +62,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true")
+    ap.add_argument("--copy-kernel-mib", type=int, default=0,
+                    help="first run a plain elementwise copy of this many MiB five times: the reference "
+                         "dispatch that scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the query shards by rays and the "
@@ -76,6 +79,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     P.load()
+    if args.copy_kernel_mib > 0:
+        # elementwise kernel reading and writing exactly n * 4 bytes
+        n = args.copy_kernel_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log("copy kernel: %d bytes read and %d written per dispatch" % (n * 4, n * 4))
+        del src, dst
     t0 = time.time()
     sc = configs.make_scene(1_003_520, 1024)
     rays_np = scene.pinhole_rays(1920, 1080)

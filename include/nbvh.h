@@ -173,16 +173,24 @@ typedef struct nbvh_ctx nbvh_ctx; /* opaque host handle */
 
 /* Launch-shape knobs (defaults shown). Results do not depend on them beyond
  * floating-point summation order; an autotuner may search them. Changing
- * wgrad_splits, scatter_lds_kb or scatter_binned changes nbvh_workspace_bytes. */
+ * wgrad_splits, scatter_lds_kb, scatter_binned or scatter_hash_levels changes
+ * nbvh_workspace_bytes. */
 typedef struct {
   int32_t query_waves;      /* waves per query workgroup: 4 or 8 (8) */
-  int32_t query_unroll;     /* (sample, level) pairs gathered together: 2, 3, 4; 0 = by entry size (0) */
+  int32_t query_unroll;     /* (sample, level) pairs gathered together: 2, 3, 4; 0 = 2, or 3 with pair
+                               loads of 4-byte entries (0) */
   int32_t query_wgs_per_cu; /* persistent query workgroups per compute unit; 0 = as many as LDS allows (0) */
   int32_t train_waves;      /* waves per training-tile workgroup: 4 or 8 (8) */
-  int32_t wgrad_splits;     /* batch splits of the weight-gradient GEMMs: 1..256 (32) */
-  int32_t scatter_lds_kb;   /* LDS budget for coarse levels in the table-gradient scatter: 0..144 (144) */
-  int32_t scatter_binned;   /* other levels: 1 = counting sort by 64 KiB table chunk, then per-chunk LDS
-                               accumulation (no global atomics); 0 = coalesced global atomics (1) */
+  int32_t wgrad_splits;     /* batch splits of the weight-gradient GEMMs: 1..256 (64) */
+  int32_t scatter_lds_kb;   /* LDS budget for coarse dense levels held whole per compute unit in the
+                               table-gradient scatter: 0..144 (0) */
+  int32_t scatter_binned;   /* levels after the LDS and hash levels: 1 = counting sort by 64 KiB table
+                               chunk, then per-chunk LDS accumulation (no global atomics); 0 = coalesced
+                               global atomics (1) */
+  int32_t scatter_hash_levels; /* levels after the LDS ones whose gradient is summed per 256-probe tile in
+                                  an LDS hash table before the global atomics: 0..32 (8) */
+  int32_t query_pairs;      /* 1 = fetch the x-neighbour corners of a cell with one load where they are
+                               adjacent in the table; 0 = one load per corner (0) */
 } nbvh_tuning;
 
 /* Read / replace the context's launch knobs (validated). */

@@ -1,10 +1,12 @@
 """Launch-shape autotuner for the N-BVH library.
 
 Times candidate knob settings (nbvh_tuning) on the caller's own workload with
-HIP events and keeps the fastest: query waves per workgroup, gather unroll and
-persistent workgroups per CU for the query; training-tile waves, weight-
-gradient split count and the scatter's LDS budget for back-propagation.
-Results can be cached in a JSON file keyed by the workload signature.
+HIP events and keeps the fastest. The search runs in stages, each a grid over
+a few knobs with the best of the earlier stages applied: for the query, waves
+per workgroup x gather unroll x pair loads, then persistent workgroups per CU;
+for back-propagation, training-tile waves x weight-gradient splits, then the
+scatter's LDS budget x hash-aggregated levels x binning. Results can be
+cached in a JSON file keyed by the workload signature.
 """
 from __future__ import annotations
 
@@ -14,8 +16,10 @@ import os
 
 import torch
 
-QUERY_SPACE = dict(query_waves=(4, 8), query_unroll=(2, 3, 4), query_wgs_per_cu=(0, 1, 2))
-TRAIN_SPACE = dict(train_waves=(4, 8), wgrad_splits=(16, 32, 64), scatter_lds_kb=(0, 144), scatter_binned=(0, 1))
+QUERY_STAGES = [dict(query_waves=(4, 8), query_unroll=(2, 3, 4), query_pairs=(0, 1)),
+                dict(query_wgs_per_cu=(0, 1, 2))]
+TRAIN_STAGES = [dict(train_waves=(4, 8), wgrad_splits=(16, 32, 64)),
+                dict(scatter_lds_kb=(0, 144), scatter_hash_levels=(0, 4, 8, 12), scatter_binned=(0, 1))]
 
 
 def _time(fn, reps):
@@ -53,33 +57,35 @@ def autotune(model, rays=None, probes=None, reps: int = 3, cache_path: str | Non
     if rays is not None:
         seg_cap = 16 * rays.shape[0]
         hits = torch.empty((rays.shape[0], 8), dtype=torch.float32, device=rays.device)
-        results = []
-        for vals in itertools.product(*QUERY_SPACE.values()):
-            knobs = dict(zip(QUERY_SPACE.keys(), vals))
-            model.set_tuning(**knobs)
-            ms = _time(lambda: model.query(rays, seg_cap, hits), reps)
-            results.append((ms, knobs))
-            if log:
-                log("query %s: %.3f ms" % (knobs, ms))
-        results.sort(key=lambda r: r[0])
-        best.update(results[0][1])
+        for space in QUERY_STAGES:
+            results = []
+            for vals in itertools.product(*space.values()):
+                knobs = dict(best, **dict(zip(space.keys(), vals)))
+                model.set_tuning(**knobs)
+                ms = _time(lambda: model.query(rays, seg_cap, hits), reps)
+                results.append((ms, knobs))
+                if log:
+                    log("query %s: %.3f ms" % (knobs, ms))
+            results.sort(key=lambda r: r[0])
+            best = dict(results[0][1])
+            report["query"] += [(ms, k) for ms, k in results]
         model.set_tuning(**best)
-        report["query"] = [(ms, k) for ms, k in results]
     if probes is not None:
         dz = torch.full((probes.shape[0], model.net.n_out), 1e-3, dtype=torch.float32, device=probes.device)
-        results = []
-        for vals in itertools.product(*TRAIN_SPACE.values()):
-            knobs = dict(zip(TRAIN_SPACE.keys(), vals))
-            model.set_tuning(**knobs)
-            ms = _time(lambda: model.backward(probes, dz), reps)
-            results.append((ms, knobs))
-            if log:
-                log("backward %s: %.3f ms" % (knobs, ms))
-        results.sort(key=lambda r: r[0])
-        best.update(results[0][1])
+        for space in TRAIN_STAGES:
+            results = []
+            for vals in itertools.product(*space.values()):
+                knobs = dict(best, **dict(zip(space.keys(), vals)))
+                model.set_tuning(**knobs)
+                ms = _time(lambda: model.backward(probes, dz), reps)
+                results.append((ms, knobs))
+                if log:
+                    log("backward %s: %.3f ms" % (knobs, ms))
+            results.sort(key=lambda r: r[0])
+            best = dict(results[0][1])
+            report["train"] += [(ms, k) for ms, k in results]
         model.set_tuning(**best)
         model.grad.zero_()
-        report["train"] = [(ms, k) for ms, k in results]
     report["tuning"] = best
     if cache_path:
         cached = {}

@@ -121,99 +121,110 @@ __device__ inline typename RawEntry<F, LP>::T pair_half(const typename RawPair<F
 }
 
 // Encode the M segments whose (o, t0) / (d, t1) sit in sA / sB into act0.
-// Each wave walks its (sample, level) pairs U at a time and issues all their
-// gathers before consuming any. Corners are fetched as x-neighbour pairs: on
-// dense levels (x, x+1) are adjacent entries; on hashed levels they are the
-// two halves of an aligned pair whenever x is even (the hash keeps x's low
-// bit), so one load serves both and lanes with odd x add one masked load.
-template <typename AT, int F, bool LP, int NWAVES, int UNROLL = 0>
+// Wave w owns levels w, w + NWAVES, ... and walks them U at a time; for each
+// group of levels it takes the samples in ray order, issuing the gathers of
+// all U levels before consuming any. Consecutive samples of a segment often
+// fall into the same cell at the coarser levels: such a lane keeps the
+// corner values it already holds and is masked out of the gathers.
+// With PAIRS, corners are fetched as x-neighbour pairs: on dense levels
+// (x, x+1) are adjacent entries; on hashed levels they are the two halves of
+// an aligned pair whenever x is even (the hash keeps x's low bit), so one
+// load serves both and lanes with odd x add one masked load.
+template <typename AT, int F, bool LP, int NWAVES, int UNROLL = 0, bool PAIRS = false>
 __device__ inline void encode_tile(const DevCfg& c, const void* table, const float4* sA, const float4* sB,
                                    const int* s_valid, AT* act0, int ld0, int M, float qscale = 1.0f) {
   typedef typename RawEntry<F, LP>::T Raw;
-  constexpr bool kPairs = !(F == 4 && !LP);  // a 32-byte fp32 pair has no single load
-  // by default 32..64 bytes of loads in flight per lane
-  constexpr int U = UNROLL > 0 ? UNROLL : (sizeof(Raw) >= 16 ? 1 : 16 / (int)sizeof(Raw));
+  constexpr bool kPairs = PAIRS && !(F == 4 && !LP);  // a 32-byte fp32 pair has no single load
+  constexpr int U = UNROLL > 0 ? UNROLL : 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int SL = c.n_samples * c.n_levels;
+  const int L = c.n_levels, S = c.n_samples;
   const uint32_t hmask = (1u << c.log2_T) - 1u;
   for (int m = lane; m < M; m += 64) {
     const bool valid = s_valid[m] != 0;
     const float4 a = sA[m], b = sB[m];
     const float o[3] = {a.x, a.y, a.z}, d[3] = {b.x, b.y, b.z};
-    for (int sl0 = wave; sl0 < SL; sl0 += NWAVES * U) {
+    for (int lg = wave; lg < L; lg += NWAVES * U) {
       Raw raw[U][8];
-      float wx[U], wy[U], wz[U];
-      int col[U];
+      int pcx[U], pcy[U], pcz[U];
       bool act[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int sl = sl0 + u * NWAVES;
-        act[u] = sl < SL;
-        const int s = act[u] ? sl / c.n_levels : 0;
-        const int l = act[u] ? sl - s * c.n_levels : 0;
-        col[u] = s * c.n_levels * F + l * F;
+        act[u] = lg + u * NWAVES < L;
+        pcx[u] = pcy[u] = pcz[u] = -1;
+      }
+      for (int s = 0; s < S; ++s) {
         float x[3];
         sample_position(c, o, d, a.w, b.w, s, x);
-        const int N = c.level_res[l];
-        const bool dense = (c.dense_mask >> l) & 1u;
-        int cx, cy, cz;
-        cell_weight(x[0], N, cx, wx[u]);
-        cell_weight(x[1], N, cy, wy[u]);
-        cell_weight(x[2], N, cz, wz[u]);
-        const uint32_t base = c.level_off[l];
-        const bool ld = act[u] && valid;
-        if constexpr (kPairs) {
-          if (dense) {
-            const uint32_t r1 = (uint32_t)N + 1u;
+        float wx[U], wy[U], wz[U];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const uint32_t i0 = base + ((uint32_t)cx + r1 * ((uint32_t)(cy + (j & 1)) + r1 * (uint32_t)(cz + (j >> 1)))) * F;
-              const auto p = load_pair<F, LP>(table, ld ? i0 : 0u);
-              raw[u][2 * j] = pair_half<F, LP>(p, false);
-              raw[u][2 * j + 1] = pair_half<F, LP>(p, true);
-            }
-          } else {
-            const bool even = (cx & 1) == 0;
+        for (int u = 0; u < U; ++u) {
+          const int l = act[u] ? lg + u * NWAVES : 0;
+          const int N = c.level_res[l];
+          const bool dense = (c.dense_mask >> l) & 1u;
+          int cx, cy, cz;
+          cell_weight(x[0], N, cx, wx[u]);
+          cell_weight(x[1], N, cy, wy[u]);
+          cell_weight(x[2], N, cz, wz[u]);
+          const bool need = act[u] && valid && (cx != pcx[u] || cy != pcy[u] || cz != pcz[u]);
+          pcx[u] = cx;
+          pcy[u] = cy;
+          pcz[u] = cz;
+          const uint32_t base = c.level_off[l];
+          if (need) {
+            if constexpr (kPairs) {
+              if (dense) {
+                const uint32_t r1 = (uint32_t)N + 1u;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const uint32_t hyz = ((uint32_t)(cy + (j & 1)) * 2654435761u) ^ ((uint32_t)(cz + (j >> 1)) * 805459861u);
-              const uint32_t h0 = ((uint32_t)cx ^ hyz) & hmask;
-              const uint32_t h1 = ((uint32_t)(cx + 1) ^ hyz) & hmask;
-              const auto p = load_pair<F, LP>(table, ld ? base + (h0 & ~1u) * F : 0u);
-              raw[u][2 * j] = pair_half<F, LP>(p, (h0 & 1u) != 0u);
-              raw[u][2 * j + 1] = even ? pair_half<F, LP>(p, (h1 & 1u) != 0u)
-                                       : load_raw<F, LP>(table, ld ? base + h1 * F : 0u);
+                for (int j = 0; j < 4; ++j) {
+                  const uint32_t i0 =
+                      base + ((uint32_t)cx + r1 * ((uint32_t)(cy + (j & 1)) + r1 * (uint32_t)(cz + (j >> 1)))) * F;
+                  const auto p = load_pair<F, LP>(table, i0);
+                  raw[u][2 * j] = pair_half<F, LP>(p, false);
+                  raw[u][2 * j + 1] = pair_half<F, LP>(p, true);
+                }
+              } else {
+                const bool even = (cx & 1) == 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  const uint32_t hyz =
+                      ((uint32_t)(cy + (j & 1)) * 2654435761u) ^ ((uint32_t)(cz + (j >> 1)) * 805459861u);
+                  const uint32_t h0 = ((uint32_t)cx ^ hyz) & hmask;
+                  const uint32_t h1 = ((uint32_t)(cx + 1) ^ hyz) & hmask;
+                  const auto p = load_pair<F, LP>(table, base + (h0 & ~1u) * F);
+                  raw[u][2 * j] = pair_half<F, LP>(p, (h0 & 1u) != 0u);
+                  raw[u][2 * j + 1] = even ? pair_half<F, LP>(p, (h1 & 1u) != 0u) : load_raw<F, LP>(table, base + h1 * F);
+                }
+              }
+            } else {
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                const uint32_t idx = base + corner_index(dense, N, hmask, cx + (k & 1), cy + ((k >> 1) & 1),
+                                                         cz + ((k >> 2) & 1)) * F;
+                raw[u][k] = load_raw<F, LP>(table, idx);
+              }
             }
           }
-        } else {
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const uint32_t idx = base + corner_index(dense, N, hmask, cx + (k & 1), cy + ((k >> 1) & 1),
-                                                     cz + ((k >> 2) & 1)) * F;
-            raw[u][k] = load_raw<F, LP>(table, ld ? idx : 0u);  // unconditional: no branch per gather
-          }
         }
-      }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (!act[u]) continue;
-        float out[F];
-#pragma unroll
-        for (int f = 0; f < F; ++f) out[f] = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const float w = ((k & 1) ? wx[u] : 1.0f - wx[u]) * (((k >> 1) & 1) ? wy[u] : 1.0f - wy[u]) *
-                          (((k >> 2) & 1) ? wz[u] : 1.0f - wz[u]);
-          float v[F];
-          unpack_raw<F, LP>(raw[u][k], v);
-#pragma unroll
-          for (int f = 0; f < F; ++f) out[f] = __builtin_fmaf(w, v[f], out[f]);
-        }
-        if (!valid) {
+        for (int u = 0; u < U; ++u) {
+          if (!act[u]) continue;
+          float out[F];
 #pragma unroll
           for (int f = 0; f < F; ++f) out[f] = 0.0f;
+          if (valid) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const float w = ((k & 1) ? wx[u] : 1.0f - wx[u]) * (((k >> 1) & 1) ? wy[u] : 1.0f - wy[u]) *
+                              (((k >> 2) & 1) ? wz[u] : 1.0f - wz[u]);
+              float v[F];
+              unpack_raw<F, LP>(raw[u][k], v);
+#pragma unroll
+              for (int f = 0; f < F; ++f) out[f] = __builtin_fmaf(w, v[f], out[f]);
+            }
+          }
+          const int col = s * L * F + (lg + u * NWAVES) * F;
+          store_features<AT, F>(act0 + (size_t)m * ld0 + col, out, qscale);
         }
-        store_features<AT, F>(act0 + (size_t)m * ld0 + col[u], out, qscale);
       }
     }
   }

@@ -22,20 +22,26 @@ constexpr int kQWaves = 8;   // waves per workgroup
 constexpr uint32_t kXcds = 8;  // accelerator complex dies of an MI355X; ray-queue partitions
 
 // Instantiation choice from the precision, feature count and the tuned
-// (waves, unroll) pair; unroll 0 means "by entry size".
-#define NBVH_DISPATCH_UNROLL(AT, F, LP, NW, UNR, M)   \
-  do {                                                 \
-    if ((UNR) == 2) M(AT, F, LP, NW, 2);                \
-    if ((UNR) == 3) M(AT, F, LP, NW, 3);                \
-    M(AT, F, LP, NW, 4);                               \
+// (waves, unroll, pairs) triple; unroll 0 means 2 (3 with pair loads of
+// 4-byte table entries).
+#define NBVH_DISPATCH_UNROLL(AT, F, LP, NW, UNR, PR, M) \
+  do {                                                   \
+    if ((UNR) == 2) M(AT, F, LP, NW, 2, PR);              \
+    if ((UNR) == 3) M(AT, F, LP, NW, 3, PR);              \
+    M(AT, F, LP, NW, 4, PR);                             \
   } while (0)
-// default unroll: 3 for 4-byte table entries (bf16 pairs), else 2
-#define NBVH_DISPATCH_WAVES(AT, F, LP, Lc, M)                                                     \
-  do {                                                                                            \
-    const int unr_ = (Lc).tune.query_unroll > 0 ? (Lc).tune.query_unroll                         \
-                                                : ((F) * ((LP) ? 2 : 4) == 4 ? 3 : 2);            \
-    if ((Lc).tune.query_waves == 4) NBVH_DISPATCH_UNROLL(AT, F, LP, 4, unr_, M);                 \
-    NBVH_DISPATCH_UNROLL(AT, F, LP, 8, unr_, M);                                                  \
+#define NBVH_DISPATCH_PAIRS(AT, F, LP, NW, Lc, M)                                                    \
+  do {                                                                                             \
+    const bool pr_ = (Lc).tune.query_pairs != 0;                                                   \
+    const int eb_ = (F) * ((LP) ? 2 : 4);                                                          \
+    const int unr_ = (Lc).tune.query_unroll > 0 ? (Lc).tune.query_unroll : (pr_ && eb_ == 4 ? 3 : 2);     \
+    if (pr_) NBVH_DISPATCH_UNROLL(AT, F, LP, NW, unr_, true, M);                                   \
+    NBVH_DISPATCH_UNROLL(AT, F, LP, NW, unr_, false, M);                                           \
+  } while (0)
+#define NBVH_DISPATCH_WAVES(AT, F, LP, Lc, M)                                     \
+  do {                                                                            \
+    if ((Lc).tune.query_waves == 4) NBVH_DISPATCH_PAIRS(AT, F, LP, 4, Lc, M);     \
+    NBVH_DISPATCH_PAIRS(AT, F, LP, 8, Lc, M);                                     \
   } while (0)
 #define NBVH_DISPATCH_QUERY(Lc, M)                                               \
   do {                                                                           \
@@ -81,7 +87,7 @@ struct QueryJob {
 // The persistent slot loop over one object's ray queue (see the file comment).
 // Returns with every slot drained, so a workgroup can move on to another
 // object afterwards.
-template <typename AT, int F, bool LP, int NW, int U>
+template <typename AT, int F, bool LP, int NW, int U, bool PR>
 __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsigned char* smem) {
   if ((uint64_t)*J.total_segs > J.capacity) return;  // segment queue overflowed: flagged, nothing to read
   const int ld0 = (c.n_in > c.width ? c.n_in : c.width) + Pad<AT>::v;
@@ -161,12 +167,12 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
     if (*s_any == 0) break;
 
     if constexpr (sizeof(AT) == 1) {
-      encode_tile<AT, F, LP, NW, U>(c, J.table, sA, sB, s_valid, act0, ld0, kQM, J.scales[kMaxLayers]);
+      encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM, J.scales[kMaxLayers]);
       __syncthreads();
       mlp_forward_tile_fp8<kQM, NW>(c, (const uint8_t*)J.W, J.scales, (uint8_t*)act0, ld0, (uint8_t*)act1, ld1, z,
                                     kOutPad);
     } else {
-      encode_tile<AT, F, LP, NW, U>(c, J.table, sA, sB, s_valid, act0, ld0, kQM);
+      encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM);
       __syncthreads();
       mlp_forward_tile<kQM, NW, AT>(c, (const AT*)J.W, act0, ld0, act1, ld1, z, kOutPad);
     }
@@ -230,10 +236,10 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
   }
 }
 
-template <typename AT, int F, bool LP, int NW, int U>
+template <typename AT, int F, bool LP, int NW, int U, bool PR>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_query_eval(DevCfg c, QueryJob J) {
   extern __shared__ __align__(16) unsigned char smem[];
-  query_eval_loop<AT, F, LP, NW, U>(c, J, smem);
+  query_eval_loop<AT, F, LP, NW, U, PR>(c, J, smem);
 }
 
 // Several objects (same network shape, own tables and weights) in one
@@ -245,13 +251,13 @@ struct QueryJobs {
   int n;
 };
 
-template <typename AT, int F, bool LP, int NW, int U>
+template <typename AT, int F, bool LP, int NW, int U, bool PR>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_query_eval_batch(
     const DevCfg* __restrict__ cfgs, QueryJobs jobs) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int i = 0; i < jobs.n; ++i) {
     const int k = (int)((blockIdx.x + (uint32_t)i) % (uint32_t)jobs.n);
-    query_eval_loop<AT, F, LP, NW, U>(cfgs[k], jobs.j[k], smem);
+    query_eval_loop<AT, F, LP, NW, U, PR>(cfgs[k], jobs.j[k], smem);
     __syncthreads();
   }
 }
@@ -386,12 +392,12 @@ __global__ __launch_bounds__(256) void k_merge_hits(const nbvh_hit* __restrict__
   o[1] = best1;
 }
 
-template <typename AT, int F, bool LP, int NW, int U>
+template <typename AT, int F, bool LP, int NW, int U, bool PR>
 static nbvh_status query_batch_t(const LaunchCtx* Ls, int n_obj, const DevCfg* cfgs_dev, const QueryJob* jobs,
                                  nbvh_hit* per_obj, nbvh_hit* hits, uint32_t n_rays) {
   const LaunchCtx& L = Ls[0];
   const size_t lds = query_lds_bytes<AT>(L.cfg.n_in, L.cfg.width);
-  auto kern = k_query_eval_batch<AT, F, LP, NW, U>;
+  auto kern = k_query_eval_batch<AT, F, LP, NW, U, PR>;
   set_lds(kern, lds);
   const int per_cu = query_per_cu(L, lds);
   QueryJobs Q;
@@ -429,18 +435,19 @@ nbvh_status launch_query_eval_batch(const LaunchCtx* Ls, int n_obj, const DevCfg
     J.capacity = capacity;
     J.state = Lk.state;
   }
-#define NBVH_QB(AT, F, LP, NW, U) return query_batch_t<AT, F, LP, NW, U>(Ls, n_obj, cfgs_dev, jobs, per_obj, hits, n_rays)
+#define NBVH_QB(AT, F, LP, NW, U, PR) \
+  return query_batch_t<AT, F, LP, NW, U, PR>(Ls, n_obj, cfgs_dev, jobs, per_obj, hits, n_rays)
   NBVH_DISPATCH_QUERY(Ls[0], NBVH_QB);
 #undef NBVH_QB
 }
 
-template <typename AT, int F, bool LP, int NW, int U>
+template <typename AT, int F, bool LP, int NW, int U, bool PR>
 static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
                                 const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
                                 uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity) {
   const DevCfg& c = L.cfg;
   const size_t lds = query_lds_bytes<AT>(c.n_in, c.width);
-  auto kern = k_query_eval<AT, F, LP, NW, U>;
+  auto kern = k_query_eval<AT, F, LP, NW, U, PR>;
   set_lds(kern, lds);
   uint32_t grid = (uint32_t)L.n_cu * query_per_cu(L, lds);
   const uint32_t need = (n_rays_bound + kQM - 1) / kQM;
@@ -469,8 +476,8 @@ static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const 
 nbvh_status launch_query_eval(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
                               const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
                               uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity) {
-#define NBVH_QE(AT, F, LP, NW, U) \
-  return query_eval_t<AT, F, LP, NW, U>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity)
+#define NBVH_QE(AT, F, LP, NW, U, PR) \
+  return query_eval_t<AT, F, LP, NW, U, PR>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity)
   NBVH_DISPATCH_QUERY(L, NBVH_QE);
 #undef NBVH_QE
 }

@@ -38,8 +38,9 @@ struct TrainLayout {
   size_t duT, wpart, loss_part, total;
   int nsplit;
   uint32_t n_tiles;
-  // binned scatter
-  int n_lds;
+  // scatter: levels [0, n_lds) in LDS, [n_lds, hash_end) through the
+  // per-tile LDS hash, the rest binned or by pairs
+  int n_lds, hash_end;
   uint32_t lds_floats, n_bins;
   uint64_t max_records;
   size_t counts, offsets, scan_sums, rec_idx, rec_val;
@@ -72,13 +73,15 @@ static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_bat
   const int budget_kb = tune.scatter_lds_kb < 0 ? 0 : (tune.scatter_lds_kb > 144 ? 144 : tune.scatter_lds_kb);
   T.lds_floats = 0;
   T.n_lds = budget_kb > 0 ? coarse_lds_levels(c, (size_t)budget_kb * 1024, &T.lds_floats) : 0;
+  T.hash_end = T.n_lds + (tune.scatter_hash_levels > 0 ? tune.scatter_hash_levels : 0);
+  if (T.hash_end > c.n_levels) T.hash_end = c.n_levels;
   T.n_bins = 0;
   T.max_records = 0;
   T.counts = T.offsets = T.scan_sums = T.rec_idx = T.rec_val = off;
-  if (tune.scatter_binned && T.n_lds < c.n_levels) {
-    const uint64_t off0 = c.level_off[T.n_lds];
+  if (tune.scatter_binned && T.hash_end < c.n_levels) {
+    const uint64_t off0 = c.level_off[T.hash_end];
     T.n_bins = (uint32_t)((c.n_table - off0 + kBinChunk - 1) / kBinChunk);
-    T.max_records = B * (uint64_t)(c.n_levels - T.n_lds) * c.n_samples * 8;
+    T.max_records = B * (uint64_t)(c.n_levels - T.hash_end) * c.n_samples * 8;
     const size_t cells = (size_t)T.n_bins * kBinWgs;
     T.counts = off;
     off = align256(off + cells * 4);
@@ -513,6 +516,75 @@ __global__ __launch_bounds__(256) void k_scatter_pairs(DevCfg c, int l_begin, co
 }
 
 // ---------------------------------------------------------------------------
+// Mid levels: a workgroup takes 256 consecutive probes (a leaf's probes are
+// consecutive in a batch, so at these resolutions their corners repeat many
+// times) and, one level at a time, sums their contributions in an LDS
+// open-addressing table keyed by parameter index; the table is then flushed
+// with one global atomic per distinct entry and feature. A record that finds
+// no slot within kHashProbe steps goes straight to global memory.
+constexpr int kHashTile = 256;
+constexpr int kHashProbe = 16;
+constexpr uint32_t kHashEmpty = 0xffffffffu;
+template <int F>
+struct HashSlots {
+  static constexpr int log2n = F == 2 ? 12 : 11;  // 48 KiB of LDS either way
+  static constexpr int n = 1 << log2n;
+};
+
+template <int F>
+__global__ __launch_bounds__(kHashTile) void k_scatter_hash(DevCfg c, int l_begin, int l_end,
+                                                            const nbvh_probe* __restrict__ probes, uint32_t n,
+                                                            const float* __restrict__ duT, uint64_t ldb,
+                                                            float* __restrict__ grad) {
+  constexpr int NS = HashSlots<F>::n;
+  __shared__ uint32_t keys[NS];
+  __shared__ float vals[NS * F];
+  for (int i = threadIdx.x; i < NS; i += kHashTile) {
+    keys[i] = kHashEmpty;
+#pragma unroll
+    for (int f = 0; f < F; ++f) vals[i * F + f] = 0.0f;
+  }
+  __syncthreads();
+  const uint32_t p = blockIdx.x * kHashTile + threadIdx.x;
+  for (int l = l_begin; l < l_end; ++l) {
+    if (p < n) {
+      level_runs<F>(c, l, probes, p, duT, ldb, [&](uint32_t idx, const float* v) {
+        bool any = false;
+#pragma unroll
+        for (int f = 0; f < F; ++f) any = any || v[f] != 0.0f;
+        if (!any) return;
+        uint32_t h = ((idx / F) * 2654435761u) >> (32 - HashSlots<F>::log2n);
+        for (int step = 0; step < kHashProbe; ++step) {
+          const uint32_t k = atomicCAS(&keys[h], kHashEmpty, idx);
+          if (k == kHashEmpty || k == idx) {
+#pragma unroll
+            for (int f = 0; f < F; ++f) atomicAdd(&vals[h * F + f], v[f]);
+            return;
+          }
+          h = (h + 1) & (NS - 1);
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f) unsafeAtomicAdd(grad + idx + f, v[f]);
+      });
+    }
+    __syncthreads();
+    // flush and clear; lanes f of one entry update one contiguous run
+    for (int i = threadIdx.x; i < NS * F; i += kHashTile) {
+      const int slot = i / F, f = i - slot * F;
+      const uint32_t k = keys[slot];
+      if (k != kHashEmpty) {
+        const float v = vals[i];
+        if (v != 0.0f) unsafeAtomicAdd(grad + k + f, v);
+        vals[i] = 0.0f;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NS; i += kHashTile) keys[i] = kHashEmpty;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Binned scatter for the levels outside LDS: a counting sort of the
 // contributions by 64 KiB table chunk, then one workgroup per chunk adds its
 // records with LDS atomics and updates its chunk of the gradient with plain
@@ -662,17 +734,21 @@ static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char
     (void)hipFuncSetAttribute((const void*)k_scatter_lds<F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_scatter_lds<F><<<L.n_cu, 1024, lds, L.stream>>>(c, T.n_lds, T.lds_floats, probes, n, duT, ldb, L.grad);
   }
-  if (T.n_lds >= c.n_levels) return check_launch("scatter");
+  if (T.hash_end > T.n_lds)
+    k_scatter_hash<F><<<(n + kHashTile - 1) / kHashTile, kHashTile, 0, L.stream>>>(c, T.n_lds, T.hash_end, probes, n,
+                                                                                 duT, ldb, L.grad);
+  if (T.hash_end >= c.n_levels) return check_launch("scatter");
   if (T.n_bins == 0) {
-    const uint64_t threads = (uint64_t)n * (c.n_levels - T.n_lds) * 2 * F;
-    k_scatter_pairs<F><<<(uint32_t)((threads + 255) / 256), 256, 0, L.stream>>>(c, T.n_lds, probes, n, duT, ldb, L.grad);
+    const uint64_t threads = (uint64_t)n * (c.n_levels - T.hash_end) * 2 * F;
+    k_scatter_pairs<F><<<(uint32_t)((threads + 255) / 256), 256, 0, L.stream>>>(c, T.hash_end, probes, n, duT, ldb,
+                                                                               L.grad);
     return check_launch("scatter");
   }
   BinArgs A;
-  A.l_begin = T.n_lds;
-  A.off0 = c.level_off[T.n_lds];
+  A.l_begin = T.hash_end;
+  A.off0 = c.level_off[T.hash_end];
   A.n_bins = T.n_bins;
-  A.n_tasks = n * (uint32_t)(c.n_levels - T.n_lds);
+  A.n_tasks = n * (uint32_t)(c.n_levels - T.hash_end);
   A.per_wg = (A.n_tasks + kBinWgs - 1) / kBinWgs;
   uint32_t* counts = (uint32_t*)(w + T.counts);
   uint32_t* offsets = (uint32_t*)(w + T.offsets);

@@ -312,6 +312,40 @@ def test_backward_fp32(lib, c1, name):
     assert np.abs(gt - rt).max() <= 1e-5 * np.abs(rt).max(), np.abs(gt - rt).max() / np.abs(rt).max()
 
 
+SCATTER_PATHS = {
+    "pairs": dict(scatter_lds_kb=0, scatter_hash_levels=0, scatter_binned=0),
+    "binned": dict(scatter_lds_kb=144, scatter_hash_levels=0, scatter_binned=1),
+    # every level through the LDS hash: fine levels overflow the table and
+    # take the direct-atomic fallback
+    "hash_all": dict(scatter_lds_kb=0, scatter_hash_levels=32, scatter_binned=0),
+    "mixed": dict(scatter_lds_kb=144, scatter_hash_levels=4, scatter_binned=1),
+}
+
+
+@pytest.mark.parametrize("path", sorted(SCATTER_PATHS))
+@pytest.mark.parametrize("order", ["by_leaf", "shuffled"])
+def test_table_gradient_scatter_paths(lib, c1, path, order):
+    """Every table-gradient route (LDS levels, per-tile LDS hash, binned
+    counting sort, coalesced atomics) gives the oracle's table gradient, with
+    probes grouped by leaf (repeated corners) and shuffled."""
+    sc, _ = c1
+    net = NETS["c2"]
+    params = _params(net, scale=1.0)
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32", loss_scale=1.0)
+    m.set_params(params)
+    m.set_tuning(**SCATTER_PATHS[path])
+    p, _ = scene.leaf_probes(sc.boxes, 40, seed=17)  # grouped by leaf
+    if order == "shuffled":
+        p = p[np.random.default_rng(18).permutation(p.shape[0])]
+    n = p.shape[0]
+    dz = (np.random.default_rng(19).normal(size=(n, net.n_out)) / n).astype(np.float32)
+    _say("scatter path", path, order, n)
+    m.backward(torch.from_numpy(p).cuda(), torch.from_numpy(dz).cuda())
+    g = m.unpad(m.grad)[: net.n_table_params]
+    ref = oracle.backward(_ocfg(net, sc), params.astype(np.float64), p, dz.astype(np.float64))[: net.n_table_params]
+    assert np.abs(g - ref).max() <= 1e-5 * np.abs(ref).max(), np.abs(g - ref).max() / np.abs(ref).max()
+
+
 @pytest.mark.parametrize("name", ["c1", "c2"])
 def test_backward_bf16(lib, c1, name):
     sc, _ = c1
