@@ -1,15 +1,24 @@
 #!/usr/bin/env python3
 """N-BVH neural ray query + training step benchmark on one MI355X.
 
-Workload: 1920x1080 primary camera rays against a 1,003,520-triangle
-displaced icosphere clustered into 1,024 neural leaves; hash grid L=16,
-F=2, T=2^19 (N_min 16, growth 1.38), 8 samples per segment, MLP
-256 -> 4x128 -> 5; training batches of 2^18 probe segments (256 per leaf)
-labelled by Moller-Trumbore. The network is first trained (untimed) so the
-hit decisions are meaningful; then each timed step is one full query of the
-frame plus one training step, in BF16 (the primary path). The same trained
-parameters are timed through the FP32 path, and both paths' hit error
-against the triangle ground truth is reported ("matched hit error").
+Default workload ("frame"): 1920x1080 primary camera rays against a
+1,003,520-triangle displaced icosphere clustered into 1,024 neural leaves;
+hash grid L=16, F=2, T=2^19 (N_min 16, growth 1.38), 8 samples per segment,
+MLP 256 -> 4x128 -> 5; training batches of 2^18 probe segments (256 per
+leaf) labelled by Moller-Trumbore. The network is first trained (untimed) so
+the hit decisions are meaningful; then each timed step is one full query of
+the frame plus one training step, in BF16 (the primary path). The same
+trained parameters are timed through the FP32 and FP8 paths, and each path's
+hit error against the triangle ground truth is reported ("matched hit
+error").
+
+--workload secondary: 2^24 cosine-weighted bounce rays from the frame's
+primary hits on a 3,996,180-triangle mesh with per-vertex albedo, 16,384
+leaves, L=16 F=4 T=2^22, 4 samples, MLP 256 -> 4x256 -> 8.
+--workload batched: 8 objects of 50,000 .. 1,997,120 triangles with their own
+tables (T = 2^16 .. 2^20), 2^22 rays with a log-uniform mix of 1..32 crossed
+leaves through one grouped query, and a HIP-graph-captured training step of
+2^18 probes per object.
 
 Prints ONE JSON line.
 """
@@ -18,6 +27,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,6 +40,18 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
 METRIC = "neural ray queries/s + train segs/s, BF16-MFMA vs FP32, at matched hit error"
+TRAFFIC_FILES = {"frame": "traffic_1920x1080_frame_2e18_batch.txt",
+                 "secondary": "traffic_2e24_secondary_2e18_batch.txt"}
+# kernels behind each library group, as rocprofv3 names them (BF16 instantiations)
+TRAFFIC_KERNELS = {
+    "query_eval": r"^nbvh::k_query_eval<(bool _Accum|__bf16)",
+    "train_tile": r"^nbvh::k_train_tile<(bool _Accum|__bf16)",
+    "scatter": r"^nbvh::k_scatter_(hash|lds|pairs)<",
+    "scatter_sort": r"^nbvh::k_bin_(count|write)<",
+    "scatter_reduce": r"^nbvh::k_bin_reduce<",
+    "wgrad": r"k_wgrad",
+    "optimizer": r"^nbvh::k_(adam|check_finite)",
+}
 
 
 def log(*a):
@@ -51,11 +73,394 @@ def hit_error(hits, gt, diag):
                 predicted_hits=int(pred.sum()), true_hits=int(truth.sum()))
 
 
+class Workload:
+    """Inputs of one benchmark workload (all host arrays, seeded)."""
+
+
+def build_frame(configs, scene):
+    W = Workload()
+    W.name = "frame"
+    W.sc = configs.make_scene(1_003_520, 1024)
+    W.rays = scene.pinhole_rays(1920, 1080)
+    W.gt_idx = None
+    W.gt = scene.ray_ground_truth(W.sc.mesh, W.rays)
+    W.net = configs.C2_NET
+    W.params0 = configs.init_params(W.net, "normal", 1e-2)
+    W.per_leaf = 256
+    W.seg_cap_per_ray = 16
+    W.describe = ("1920x1080 primary rays on a 1,003,520-triangle displaced icosphere, 1,024 neural leaves; "
+                  "hash grid L=16 F=2 T=2^19, 8 samples/segment, MLP 256-4x128-5; train batch 2^18 probes")
+    W.cpu_sample = lambda stride: (W.rays.reshape(1080, 1920, 8)[::stride, ::stride].reshape(-1, 8),
+                                   ("every %dth row and column of the 1920x1080 frame" % stride) if stride > 1 else "the whole 1920x1080 frame")
+    return W
+
+
+def build_secondary(configs, scene):
+    W = Workload()
+    W.name = "secondary"
+    W.sc = configs.make_scene(3_996_180, 16384, albedo_seed=scene.SEED_ALBEDO)
+    primary = scene.pinhole_rays(1920, 1080)
+    g = scene.ray_ground_truth(W.sc.mesh, primary)
+    hit = g["hit"]
+    pts = primary[hit, 0:3].astype(np.float64) + g["t"][hit, None] * primary[hit, 4:7].astype(np.float64)
+    W.rays = scene.cosine_bounces(pts, g["n"][hit], 1 << 24, seed=scene.SEED_SECONDARY,
+                                  offset=1e-4 * W.sc.diagonal)
+    # ground truth on every 16th ray
+    W.gt_idx = np.arange(0, W.rays.shape[0], 16)
+    W.gt = scene.ray_ground_truth(W.sc.mesh, W.rays[W.gt_idx])
+    W.net = configs.C5_NET
+    W.params0 = configs.init_params(W.net, "normal", 1e-2)
+    W.per_leaf = 16
+    W.seg_cap_per_ray = 8
+    W.describe = ("2^24 cosine-weighted bounce rays from the 1920x1080 frame's primary hits on a 3,996,180-triangle "
+                  "displaced icosphere with per-vertex albedo, 16,384 neural leaves; hash grid L=16 F=4 T=2^22, "
+                  "4 samples/segment, MLP 256-4x256-8 (hit, t, normal, albedo); train batch 2^18 probes")
+    W.cpu_sample = lambda stride: (W.rays[::stride * stride * 16], "every %dth ray" % (stride * stride * 16))
+    return W
+
+
+def timer(torch):
+    def time_loop(fn, n):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for i in range(n):
+            fn(i)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+    return time_loop
+
+
+def copy_kernel(torch, mib):
+    """Elementwise kernel reading and writing exactly mib MiB (the reference
+    dispatch for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    log("copy kernel: %d bytes read and %d written per dispatch" % (n * 4, n * 4))
+
+
+def run_single(args, W, P, torch, configs, scene):
+    t0 = time.time()
+    sc, net = W.sc, W.net
+    batches = []
+    for i in range(args.batches):
+        pr, _ = scene.leaf_probes(sc.boxes, W.per_leaf, seed=scene.SEED_PROBES + i)
+        lb = scene.probe_labels(sc.mesh, pr)
+        batches.append((torch.from_numpy(pr).cuda(), torch.from_numpy(lb).cuda()))
+    B = batches[0][0].shape[0]
+    rays = torch.from_numpy(W.rays).cuda()
+    R = rays.shape[0]
+    seg_cap = W.seg_cap_per_ray * R
+    log("data ready in %.1fs: %d rays, %d triangles, %d leaves, batch %d" %
+        (time.time() - t0, R, sc.tris.shape[0], sc.boxes.shape[0], B))
+
+    def accuracy(hits):
+        h = hits.cpu().numpy()
+        return hit_error(h if W.gt_idx is None else h[W.gt_idx], W.gt, sc.diagonal)
+
+    bf = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", loss_scale=1024.0)
+    bf.set_params(W.params0)
+    bf.workspace(R, seg_cap, B)
+    # pre-training (untimed): the trained network of the training workload
+    t1 = time.time()
+    loss = None
+    for i in range(args.pretrain):
+        p, l = batches[i % len(batches)]
+        loss = bf.train_step(p, l)
+    torch.cuda.synchronize()
+    log("pretrain %d steps in %.1fs, loss %s" % (args.pretrain, time.time() - t1,
+                                                 None if loss is None else loss.cpu().numpy().round(4).tolist()))
+    hits_bf = torch.empty((R, 8), dtype=torch.float32, device="cuda")
+
+    def run_steps(m, n):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for i in range(n):
+            m.query(rays, seg_cap, hits_bf)
+            m.train_step(*batches[i % len(batches)])
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    # BF16 primary path: timed steps, then query-only and train-only loops
+    run_steps(bf, args.warmup)
+    st0 = bf.read_state()
+    total_ms = run_steps(bf, args.steps)
+    st1 = bf.read_state()
+    assert st1["flags"] & 1 == 0, "segment capacity exceeded"
+    evaluated = (st1["n_evaluated"] - st0["n_evaluated"]) / max(1, args.steps)
+    n_segments = st1["last_n_segments"]
+    time_loop = timer(torch)
+    q_ms = time_loop(lambda i: bf.query(rays, seg_cap, hits_bf), args.steps)
+    t_ms = time_loop(lambda i: bf.train_step(*batches[i % len(batches)]), args.steps)
+    # per-kernel-group device time (HIP events on the launch stream)
+    bf.profile_begin()
+    run_steps(bf, args.steps)
+    prof = bf.profile_end()
+    bf.query(rays, seg_cap, hits_bf)
+    torch.cuda.synchronize()
+    acc_bf = accuracy(hits_bf)
+    log("bf16: step %.3f ms (query %.3f, train %.3f), evaluated %.0f / %d segments, hit acc %.4f" %
+        (total_ms / args.steps, q_ms, t_ms, evaluated, n_segments, acc_bf["hit_accuracy"]))
+    log("profile:", {k: (round(v[0] / max(1, v[1]), 4), v[1]) for k, v in prof.items()})
+    trained = bf.get_params()
+
+    # FP32 path with the same trained parameters
+    fp32 = None
+    if not args.no_fp32:
+        fp = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32", loss_scale=1024.0)
+        fp.set_params(trained)
+        fp.workspace(R, seg_cap, B)
+        hits_fp = torch.empty((R, 8), dtype=torch.float32, device="cuda")
+        fp.query(rays, seg_cap, hits_fp)
+        torch.cuda.synchronize()
+        acc_fp = accuracy(hits_fp)
+        fq_ms = time_loop(lambda i: fp.query(rays, seg_cap, hits_fp), args.steps)
+        ft_ms = time_loop(lambda i: fp.train_step(*batches[i % len(batches)]), args.steps)
+        fp32 = dict(query_ms=fq_ms, train_ms=ft_ms, rays_per_s=R / (fq_ms * 1e-3), train_segs_per_s=B / (ft_ms * 1e-3),
+                    accuracy=acc_fp)
+        log("fp32: query %.3f ms, train %.3f ms, hit acc %.4f" % (fq_ms, ft_ms, acc_fp["hit_accuracy"]))
+        del fp, hits_fp
+
+    # FP8 inference option with the same trained parameters: per-layer scales
+    # calibrated on 2^16 seeded probe segments
+    fp8 = None
+    if not args.no_fp8:
+        f8 = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp8")
+        f8.set_params(trained)
+        f8.calibrate_fp8(batches[0][0][: 1 << 16].contiguous())
+        f8.workspace(R, seg_cap, 0)
+        hits_f8 = torch.empty((R, 8), dtype=torch.float32, device="cuda")
+        f8.query(rays, seg_cap, hits_f8)
+        torch.cuda.synchronize()
+        acc_f8 = accuracy(hits_f8)
+        f8_ms = time_loop(lambda i: f8.query(rays, seg_cap, hits_f8), args.steps)
+        fp8 = dict(query_ms=f8_ms, rays_per_s=R / (f8_ms * 1e-3), accuracy=acc_f8,
+                   calibration="2^16 probe segments of the first training batch")
+        log("fp8: query %.3f ms, hit acc %.4f" % (f8_ms, acc_f8["hit_accuracy"]))
+        del f8, hits_f8
+
+    roofline = rooflines(prof, net, bf.get_tuning(), evaluated, B, R, n_segments, W.name)
+
+    # CPU baseline: the oracle on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cfg = oracle.make_cfg(net, sc.lo, sc.side)
+        params = trained.astype(np.float64)
+        stride = 16
+        sample, what = W.cpu_sample(stride)
+        t2 = time.time()
+        oracle.query(cfg, params, sample, sc.boxes)
+        dt = time.time() - t2
+        # grow the sample towards the target time
+        if dt < args.cpu_seconds / 2 and stride > 1:
+            stride = max(1, int(stride / np.sqrt(args.cpu_seconds / max(dt, 1e-3))))
+            sample, what = W.cpu_sample(stride)
+            t2 = time.time()
+            oracle.query(cfg, params, sample, sc.boxes)
+            dt = time.time() - t2
+        cpu = dict(value=sample.shape[0] / dt, unit="rays/s", cores=oracle.num_threads(), kind="oracle",
+                   sample="%s (%d rays), full query in FP64 (every-leaf traversal, encode, MLP, resolve), %.1f s"
+                          % (what, sample.shape[0], dt))
+        log("cpu baseline:", cpu)
+
+    return {
+        "metric": METRIC,
+        "value": R / (q_ms * 1e-3),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": W.describe,
+            "rays": R, "segments": int(n_segments), "segments_evaluated": int(evaluated), "train_batch": B,
+            "step": "one full query + one training step (forward, loss, backward, Adam)",
+        },
+        "query_ms": q_ms,
+        "train_ms": t_ms,
+        "segments_per_s": evaluated / (q_ms * 1e-3),
+        "train_segs_per_s": B / (t_ms * 1e-3),
+        "accuracy": acc_bf,
+        "fp32": fp32,
+        "fp8": fp8,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+
+
+def rooflines(prof, net, tune, evaluated, B, R, n_segments, workload):
+    """Per-group rooflines; the dominant group is the one with the most device
+    time in the timed step. Algorithmic work per launch:
+      query_eval / train_tile: table bytes gathered, S*L*8 corners x F x 2 B;
+      scatter routes: one 4-byte read-modify-write per corner and feature of
+        the levels each route handles;
+      wgrad: 2 FLOPs per weight and probe; optimizer: 34 B per parameter;
+      traverse: rays, two passes over the segment queue and the counts."""
+    per = {k: (v[0] / max(1, v[1]), v[1], v[0]) for k, v in prof.items() if v[1] > 0}
+    c = net
+    S, L, F = c.n_samples, c.n_levels, c.n_features
+    lds_levels = 0
+    if tune["scatter_lds_kb"] > 0:
+        acc = 0
+        for l, (dense, size) in enumerate(zip(c.level_dense(), c.level_sizes())):
+            if not dense or (acc + size * F) * 4 > tune["scatter_lds_kb"] * 1024:
+                break
+            acc += size * F
+            lds_levels = l + 1
+    hash_end = min(L, lds_levels + tune["scatter_hash_levels"])
+    sorted_levels = L - hash_end if tune["scatter_binned"] else 0
+    work = {
+        "query_eval": ("hbm", evaluated * S * L * 8 * F * 2, "GB/s"),
+        "train_tile": ("hbm", B * S * L * 8 * F * 2, "GB/s"),
+        "scatter": ("hbm", B * S * (L - sorted_levels) * 8 * F * 4, "GB/s"),
+        "scatter_sort": ("hbm", B * S * sorted_levels * 8 * F * 4, "GB/s"),
+        "scatter_reduce": ("hbm", B * S * sorted_levels * 8 * F * 4, "GB/s"),
+        "wgrad": ("mfma", B * 2 * c.n_mlp_params, "TFLOP/s"),
+        "optimizer": ("hbm", (c.n_table_params + c.n_mlp_params) * 34, "GB/s"),
+        "traverse": ("hbm", R * 32 + n_segments * 16 * 2 + R * 12, "GB/s"),
+    }
+
+    def roof(group):
+        bound, amount, unit = work[group]
+        avg_ms = per[group][0]
+        if unit == "GB/s":
+            achieved, peak = amount / (avg_ms * 1e-3) / 1e9, HBM_PEAK_GBS
+        else:
+            achieved, peak = amount / (avg_ms * 1e-3) / 1e12, BF16_PEAK_TFLOPS
+        return dict(bound=bound, kernel=group, achieved=round(achieved, 2), peak=peak, unit=unit,
+                    frac=round(achieved / peak, 4), avg_ms=round(avg_ms, 4), algorithmic=amount)
+
+    dom = max((k for k in per if k in work), key=lambda k: per[k][2])
+    roofline = roof(dom)
+    # memory traffic per launch from the committed rocprofv3 counter summary of
+    # this workload, valid only for the kernel sources it was taken on
+    from paper_2405_16237_amd import profiling
+    roofline["traffic"] = None
+    tr = profiling.read_traffic(os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(workload, "")))
+    if tr is not None and tr.get("source_digest") == profiling.source_digest():
+        pat = TRAFFIC_KERNELS.get(dom)
+        found = [v for k, v in tr["kernels"].items() if pat and re.search(pat, k)]
+        if found:
+            roofline["traffic"] = sum(v["bytes"] for v in found)
+    roofline["per_kernel"] = {k: roof(k) for k in per if k in work}
+    return roofline
+
+
+def run_batched(args, P, torch, configs, scene):
+    t0 = time.time()
+    objs = []
+    for o in configs.c4_objects():
+        sc = configs.make_scene(o["n_tris"], o["n_leaves"], seed=o["seed"], offset=o["offset"])
+        objs.append((sc, o["net"]))
+    boxes_all = np.concatenate([sc.boxes for sc, _ in objs])
+    rays_np, counts = configs.c4_rays(boxes_all, 1 << 22)
+    gt_idx = np.arange(0, rays_np.shape[0], 16)
+    gts = [scene.ray_ground_truth(sc.mesh, rays_np[gt_idx]) for sc, _ in objs]
+    gt_t = np.stack([np.where(g["hit"], g["t"], np.inf) for g in gts])
+    gt = dict(hit=np.isfinite(gt_t.min(0)), t=gt_t.min(0))
+    diag = float(np.linalg.norm(boxes_all[:, 3:].max(0) - boxes_all[:, :3].min(0)))
+    batches = []
+    for k, (sc, net) in enumerate(objs):
+        pr, _ = scene.leaf_probes(sc.boxes, (1 << 18) // sc.boxes.shape[0], seed=scene.SEED_PROBES + 10 * k)
+        batches.append((torch.from_numpy(pr).cuda(), torch.from_numpy(scene.probe_labels(sc.mesh, pr)).cuda()))
+    rays = torch.from_numpy(rays_np).cuda()
+    R = rays.shape[0]
+    seg_cap = 8 * R  # per object
+    log("data ready in %.1fs: %d rays (%.1f leaves crossed on average), %d objects" %
+        (time.time() - t0, R, counts.mean(), len(objs)))
+    models = []
+    for k, (sc, net) in enumerate(objs):
+        m = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", loss_scale=1024.0)
+        m.set_params(configs.init_params(net, "normal", 1e-2, seed_features=200 + k, seed_mlp=300 + k))
+        m.workspace(0, 0, batches[k][0].shape[0])
+        models.append(m)
+    batch = P.NBVHBatch(models)
+    hits = torch.empty((R, 8), dtype=torch.float32, device="cuda")
+    for i in range(args.pretrain):
+        for m, (p, l) in zip(models, batches):
+            m.train_step(p, l)
+    torch.cuda.synchronize()
+    # the training step of all objects as one HIP graph
+    losses = torch.zeros((len(models), 4), dtype=torch.float32, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for k, m in enumerate(models):
+            m.train_step(*batches[k], loss=losses[k])
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for k, m in enumerate(models):
+            m.train_step(*batches[k], loss=losses[k])
+    time_loop = timer(torch)
+    for _ in range(args.warmup):
+        batch.query(rays, seg_cap, hits)
+        g.replay()
+    torch.cuda.synchronize()
+
+    def step(i):
+        batch.query(rays, seg_cap, hits)
+        g.replay()
+    step_ms = time_loop(step, args.steps)
+    q_ms = time_loop(lambda i: batch.query(rays, seg_cap, hits), args.steps)
+    t_ms = time_loop(lambda i: g.replay(), args.steps)
+    batch.query(rays, seg_cap, hits)
+    torch.cuda.synchronize()
+    assert all(m.read_state()["flags"] & 1 == 0 for m in models), "segment capacity exceeded"
+    acc = hit_error(hits.cpu().numpy()[gt_idx], gt, diag)
+    nb = sum(p.shape[0] for p, _ in batches)
+    log("batched: step %.3f ms (query %.3f, train graph %.3f), hit acc %.4f" % (step_ms, q_ms, t_ms,
+                                                                               acc["hit_accuracy"]))
+    return {
+        "metric": METRIC,
+        "value": R / (q_ms * 1e-3),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": "8 displaced icospheres (50,000..1,997,120 triangles, 256..8,192 leaves, own tables "
+                        "T=2^16..2^20, L=16 F=2, 8 samples, MLP 256-4x128-5) queried together by 2^22 rays "
+                        "crossing 1..32 leaves (log-uniform); training step of 2^18 probes per object as one "
+                        "HIP graph",
+            "rays": R, "objects": len(objs), "train_batch": nb,
+            "step": "one grouped query + one graph-captured training step of every object",
+        },
+        "query_ms": q_ms,
+        "train_ms": t_ms,
+        "train_segs_per_s": nb / (t_ms * 1e-3),
+        "accuracy": acc,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=("frame", "secondary", "batched"), default="frame")
     ap.add_argument("--pretrain", type=int, default=600, help="untimed BF16 training steps before timing")
     ap.add_argument("--batches", type=int, default=4, help="distinct 2^18-probe batches cycled in training")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
@@ -80,214 +485,12 @@ def main():
     torch.cuda.set_device(0)
     P.load()
     if args.copy_kernel_mib > 0:
-        # elementwise kernel reading and writing exactly n * 4 bytes
-        n = args.copy_kernel_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        log("copy kernel: %d bytes read and %d written per dispatch" % (n * 4, n * 4))
-        del src, dst
-    t0 = time.time()
-    sc = configs.make_scene(1_003_520, 1024)
-    rays_np = scene.pinhole_rays(1920, 1080)
-    gt = scene.ray_ground_truth(sc.mesh, rays_np)
-    batches = []
-    for i in range(args.batches):
-        pr, _ = scene.leaf_probes(sc.boxes, 256, seed=scene.SEED_PROBES + i)
-        lb = scene.probe_labels(sc.mesh, pr)
-        batches.append((torch.from_numpy(pr).cuda(), torch.from_numpy(lb).cuda()))
-    B = batches[0][0].shape[0]
-    log("data ready in %.1fs: %d rays, %d triangles, %d leaves, batch %d" %
-        (time.time() - t0, rays_np.shape[0], sc.tris.shape[0], sc.boxes.shape[0], B))
-    net = configs.C2_NET
-    params0 = configs.init_params(net, "normal", 1e-2)
-    rays = torch.from_numpy(rays_np).cuda()
-    R = rays.shape[0]
-    seg_cap = 16 * R
-
-    bf = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", loss_scale=1024.0)
-    bf.set_params(params0)
-    bf.workspace(R, seg_cap, B)
-    # pre-training (untimed): the trained network of the training workload
-    t1 = time.time()
-    loss = None
-    for i in range(args.pretrain):
-        p, l = batches[i % len(batches)]
-        loss = bf.train_step(p, l)
-    torch.cuda.synchronize()
-    log("pretrain %d steps in %.1fs, loss %s" % (args.pretrain, time.time() - t1,
-                                                 None if loss is None else loss.cpu().numpy().round(4).tolist()))
-
-    def run_steps(m, n, timed):
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        hits = torch.empty((R, 8), dtype=torch.float32, device="cuda")
-        torch.cuda.synchronize()
-        qms = 0.0
-        ev0.record()
-        for i in range(n):
-            q0.record()
-            m.query(rays, seg_cap, hits)
-            q1.record()
-            p, l = batches[i % len(batches)]
-            m.train_step(p, l)
-            if timed:
-                q1.synchronize()
-                qms += q0.elapsed_time(q1)
-        ev1.record()
-        torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1), qms, hits
-
-    # BF16 primary path
-    run_steps(bf, args.warmup, False)
-    st0 = bf.read_state()
-    total_ms, _, _ = run_steps(bf, args.steps, False)
-    st1 = bf.read_state()
-    evaluated = (st1["n_evaluated"] - st0["n_evaluated"]) / max(1, args.steps)
-    n_segments = st1["last_n_segments"]
-    # query-only and train-only timing of the same path (separate loops)
-    def time_loop(fn, n):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record()
-        for i in range(n):
-            fn(i)
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / n
-
-    hits_bf = torch.empty((R, 8), dtype=torch.float32, device="cuda")
-    q_ms = time_loop(lambda i: bf.query(rays, seg_cap, hits_bf), args.steps)
-    t_ms = time_loop(lambda i: bf.train_step(*batches[i % len(batches)]), args.steps)
-    # per-kernel device time (HIP events around each kernel group on the launch stream)
-    bf.profile_begin()
-    run_steps(bf, args.steps, False)
-    prof = bf.profile_end()
-    torch.cuda.synchronize()
-    acc_bf = hit_error(hits_bf.cpu().numpy(), gt, sc.diagonal)
-    log("bf16: step %.3f ms (query %.3f, train %.3f), evaluated %.0f / %d segments" %
-        (total_ms / args.steps, q_ms, t_ms, evaluated, n_segments))
-    log("profile:", {k: (round(v[0] / max(1, v[1]), 4), v[1]) for k, v in prof.items()})
-
-    # FP32 path with the same trained parameters
-    fp32 = None
-    if not args.no_fp32:
-        fp = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32", loss_scale=1024.0)
-        fp.set_params(bf.get_params())
-        fp.workspace(R, seg_cap, B)
-        hits_fp = torch.empty((R, 8), dtype=torch.float32, device="cuda")
-        fp.query(rays, seg_cap, hits_fp)
-        torch.cuda.synchronize()
-        acc_fp = hit_error(hits_fp.cpu().numpy(), gt, sc.diagonal)
-        fq_ms = time_loop(lambda i: fp.query(rays, seg_cap, hits_fp), args.steps)
-        fp.set_params(bf.get_params())
-        ft_ms = time_loop(lambda i: fp.train_step(*batches[i % len(batches)]), args.steps)
-        fp32 = dict(query_ms=fq_ms, train_ms=ft_ms, rays_per_s=R / (fq_ms * 1e-3), train_segs_per_s=B / (ft_ms * 1e-3),
-                    accuracy=acc_fp)
-        log("fp32: query %.3f ms, train %.3f ms, hit acc %.4f (bf16 %.4f)" %
-            (fq_ms, ft_ms, acc_fp["hit_accuracy"], acc_bf["hit_accuracy"]))
-
-    # FP8 inference option with the same trained parameters: per-layer scales
-    # calibrated on 2^16 seeded probe segments
-    fp8 = None
-    if not args.no_fp8:
-        f8 = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp8")
-        f8.set_params(bf.get_params())
-        f8.calibrate_fp8(batches[0][0][: 1 << 16].contiguous())
-        f8.workspace(R, seg_cap, 0)
-        hits_f8 = torch.empty((R, 8), dtype=torch.float32, device="cuda")
-        f8.query(rays, seg_cap, hits_f8)
-        torch.cuda.synchronize()
-        acc_f8 = hit_error(hits_f8.cpu().numpy(), gt, sc.diagonal)
-        f8_ms = time_loop(lambda i: f8.query(rays, seg_cap, hits_f8), args.steps)
-        fp8 = dict(query_ms=f8_ms, rays_per_s=R / (f8_ms * 1e-3), accuracy=acc_f8,
-                   calibration="2^16 probe segments of the first training batch")
-        log("fp8: query %.3f ms, hit acc %.4f (bf16 %.4f)" % (f8_ms, acc_f8["hit_accuracy"], acc_bf["hit_accuracy"]))
-        del f8
-
-    # dominant kernel group and its roofline
-    per = {k: (v[0] / max(1, v[1]), v[1], v[0]) for k, v in prof.items() if v[1] > 0}
-    dom = max(per, key=lambda k: per[k][2])
-    avg_ms = per[dom][0]
-    c = net
-    S, L, F = c.n_samples, c.n_levels, c.n_features
-    flops_fwd = 2 * c.n_mlp_params
-    work = {
-        # bytes of table entries gathered: S*L*8 corners x F features x 2 B (bf16)
-        "query_eval": ("hbm", evaluated * S * L * 8 * F * 2, "GB/s"),
-        "train_tile": ("hbm", B * S * L * 8 * F * 2, "GB/s"),
-        # one 4-byte atomic add per corner and feature
-        "scatter": ("hbm", B * S * L * 8 * F * 4, "GB/s"),
-        "wgrad": ("mfma", B * flops_fwd, "TFLOP/s"),
-        "optimizer": ("hbm", (c.n_table_params + c.n_mlp_params) * 34, "GB/s"),
-        "traverse": ("hbm", R * 32 + n_segments * 16 * 2 + R * 12, "GB/s"),
-    }
-    bound, amount, unit = work.get(dom, ("hbm", 0, "GB/s"))
-    if unit == "GB/s":
-        achieved = amount / (avg_ms * 1e-3) / 1e9
-        peak = HBM_PEAK_GBS
+        copy_kernel(torch, args.copy_kernel_mib)
+    if args.workload == "batched":
+        out = run_batched(args, P, torch, configs, scene)
     else:
-        achieved = amount / (avg_ms * 1e-3) / 1e12
-        peak = BF16_PEAK_TFLOPS
-    roofline = dict(bound=bound, kernel=dom, achieved=round(achieved, 2), peak=peak, unit=unit,
-                    frac=round(achieved / peak, 4), traffic=None, avg_ms=round(avg_ms, 4),
-                    algorithmic=amount, per_kernel_ms={k: round(v[0], 4) for k, v in per.items()})
-
-    # CPU baseline: the oracle on a bounded sample of the same workload
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        cfg = oracle.make_cfg(net, sc.lo, sc.side)
-        params = bf.get_params().astype(np.float64)
-        stride = 16
-        sample = rays_np.reshape(1080, 1920, 8)[::stride, ::stride].reshape(-1, 8)
-        t2 = time.time()
-        oracle.query(cfg, params, sample, sc.boxes)
-        dt = time.time() - t2
-        # grow the sample towards the target time
-        if dt < args.cpu_seconds / 4 and stride > 4:
-            stride = max(4, int(stride / np.sqrt(args.cpu_seconds / max(dt, 1e-3))))
-            sample = rays_np.reshape(1080, 1920, 8)[::stride, ::stride].reshape(-1, 8)
-            t2 = time.time()
-            oracle.query(cfg, params, sample, sc.boxes)
-            dt = time.time() - t2
-        cpu = dict(value=sample.shape[0] / dt, unit="rays/s", cores=oracle.num_threads(), kind="oracle",
-                   sample="every %dth row and column of the 1920x1080 frame (%d rays), full query in FP64 "
-                          "(every-leaf traversal, encode, MLP, resolve), %.1f s" % (stride, sample.shape[0], dt))
-        log("cpu baseline:", cpu)
-
-    step_ms = total_ms / args.steps
-    out = {
-        "metric": METRIC,
-        "value": R / (q_ms * 1e-3),
-        "unit": "rays/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": step_ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "bf16",
-        "data": "synthetic",
-        "config": {
-            "workload": "1920x1080 primary rays on a 1,003,520-triangle displaced icosphere, 1,024 neural leaves; "
-                        "hash grid L=16 F=2 T=2^19, 8 samples/segment, MLP 256-4x128-5; train batch 2^18 probes",
-            "rays": R, "segments": int(n_segments), "segments_evaluated": int(evaluated), "train_batch": B,
-            "step": "one full-frame query + one training step (forward, loss, backward, Adam)",
-        },
-        "query_ms": q_ms,
-        "train_ms": t_ms,
-        "segments_per_s": evaluated / (q_ms * 1e-3),
-        "train_segs_per_s": B / (t_ms * 1e-3),
-        "accuracy": acc_bf,
-        "fp32": fp32,
-        "fp8": fp8,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
+        W = build_frame(configs, scene) if args.workload == "frame" else build_secondary(configs, scene)
+        out = run_single(args, W, P, torch, configs, scene)
     print(json.dumps(out), flush=True)
 
 

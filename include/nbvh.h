@@ -362,9 +362,11 @@ typedef enum {
   NBVH_K_FORWARD = 2,    /* forward tile kernel */
   NBVH_K_TRAIN_TILE = 3, /* fused encode + forward + loss + dgrad */
   NBVH_K_WGRAD = 4,      /* weight-gradient GEMMs + reduction */
-  NBVH_K_SCATTER = 5,    /* table-gradient scatter */
+  NBVH_K_SCATTER = 5,    /* table-gradient scatter: LDS levels, per-tile hash levels, direct atomics */
   NBVH_K_OPTIMIZER = 6,  /* finite check + Adam */
-  NBVH_K_COUNT = 7
+  NBVH_K_SCATTER_SORT = 7,   /* binned scatter: count + scan + record write */
+  NBVH_K_SCATTER_REDUCE = 8, /* binned scatter: per-chunk accumulation */
+  NBVH_K_COUNT = 9
 } nbvh_kernel_id;
 
 typedef struct {

@@ -39,8 +39,9 @@ class NbvhParams(ctypes.Structure):
                 ("aux_dev", ctypes.c_void_p)]
 
 
-NBVH_K_COUNT = 7
-KERNEL_GROUPS = ["traverse", "query_eval", "forward", "train_tile", "wgrad", "scatter", "optimizer"]
+NBVH_K_COUNT = 9
+KERNEL_GROUPS = ["traverse", "query_eval", "forward", "train_tile", "wgrad", "scatter", "optimizer", "scatter_sort",
+                 "scatter_reduce"]
 
 
 class NbvhProfile(ctypes.Structure):

@@ -18,14 +18,12 @@ __device__ inline void store_features(AT* dst, const float v[F], float qscale = 
     else
       *(uint32_t*)dst = w;
   } else if constexpr (sizeof(AT) == 2) {
+    // round to nearest even on the hardware converter (one instruction per pair)
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
     if constexpr (F == 2) {
-      uint32_t w = (uint32_t)f32_to_bf16_bits(v[0]) | ((uint32_t)f32_to_bf16_bits(v[1]) << 16);
-      *(uint32_t*)dst = w;
+      *(bf16x2*)dst = bf16x2{(bf16)v[0], (bf16)v[1]};
     } else {
-      uint2 w;
-      w.x = (uint32_t)f32_to_bf16_bits(v[0]) | ((uint32_t)f32_to_bf16_bits(v[1]) << 16);
-      w.y = (uint32_t)f32_to_bf16_bits(v[2]) | ((uint32_t)f32_to_bf16_bits(v[3]) << 16);
-      *(uint2*)dst = w;
+      *(bf16x4*)dst = bf16x4{(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
     }
   } else {
     if constexpr (F == 2)

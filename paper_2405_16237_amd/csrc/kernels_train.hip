@@ -729,20 +729,23 @@ template <int F>
 static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char* w, const nbvh_probe* probes,
                                   uint32_t n, const float* duT, uint64_t ldb) {
   const DevCfg& c = L.cfg;
-  if (T.n_lds > 0) {
-    const size_t lds = (size_t)T.lds_floats * 4;
-    (void)hipFuncSetAttribute((const void*)k_scatter_lds<F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_scatter_lds<F><<<L.n_cu, 1024, lds, L.stream>>>(c, T.n_lds, T.lds_floats, probes, n, duT, ldb, L.grad);
-  }
-  if (T.hash_end > T.n_lds)
-    k_scatter_hash<F><<<(n + kHashTile - 1) / kHashTile, kHashTile, 0, L.stream>>>(c, T.n_lds, T.hash_end, probes, n,
-                                                                                 duT, ldb, L.grad);
-  if (T.hash_end >= c.n_levels) return check_launch("scatter");
-  if (T.n_bins == 0) {
-    const uint64_t threads = (uint64_t)n * (c.n_levels - T.hash_end) * 2 * F;
-    k_scatter_pairs<F><<<(uint32_t)((threads + 255) / 256), 256, 0, L.stream>>>(c, T.hash_end, probes, n, duT, ldb,
-                                                                               L.grad);
-    return check_launch("scatter");
+  {
+    ProfScope ps(L.prof, NBVH_K_SCATTER, L.stream);
+    if (T.n_lds > 0) {
+      const size_t lds = (size_t)T.lds_floats * 4;
+      (void)hipFuncSetAttribute((const void*)k_scatter_lds<F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      k_scatter_lds<F><<<L.n_cu, 1024, lds, L.stream>>>(c, T.n_lds, T.lds_floats, probes, n, duT, ldb, L.grad);
+    }
+    if (T.hash_end > T.n_lds)
+      k_scatter_hash<F><<<(n + kHashTile - 1) / kHashTile, kHashTile, 0, L.stream>>>(c, T.n_lds, T.hash_end, probes,
+                                                                                   n, duT, ldb, L.grad);
+    if (T.hash_end >= c.n_levels) return check_launch("scatter");
+    if (T.n_bins == 0) {
+      const uint64_t threads = (uint64_t)n * (c.n_levels - T.hash_end) * 2 * F;
+      k_scatter_pairs<F><<<(uint32_t)((threads + 255) / 256), 256, 0, L.stream>>>(c, T.hash_end, probes, n, duT,
+                                                                                 ldb, L.grad);
+      return check_launch("scatter");
+    }
   }
   BinArgs A;
   A.l_begin = T.hash_end;
@@ -755,14 +758,20 @@ static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char
   uint32_t* sums = (uint32_t*)(w + T.scan_sums);
   const size_t hist_lds = (size_t)T.n_bins * 4;
   if (hist_lds > 64 * 1024) return set_error("too many gradient bins (%u) for LDS", T.n_bins), NBVH_ERR_UNSUPPORTED;
-  k_bin_count<F><<<kBinWgs, 256, hist_lds, L.stream>>>(c, A, probes, n, duT, ldb, counts);
-  const uint32_t cells = T.n_bins * (uint32_t)kBinWgs;
-  nbvh_status s = launch_exclusive_scan(L.stream, counts, cells, offsets, sums, sums + cells / 1024 + 3);
-  if (s != NBVH_OK) return s;
-  k_bin_write<F><<<kBinWgs, 256, hist_lds, L.stream>>>(c, A, probes, n, duT, ldb, offsets, (uint16_t*)(w + T.rec_idx),
-                                                      (float*)(w + T.rec_val));
-  k_bin_reduce<F><<<T.n_bins, 1024, 0, L.stream>>>(A, offsets, kBinWgs, (const uint16_t*)(w + T.rec_idx),
-                                                   (const float*)(w + T.rec_val), c.n_table, L.grad);
+  {
+    ProfScope ps(L.prof, NBVH_K_SCATTER_SORT, L.stream);
+    k_bin_count<F><<<kBinWgs, 256, hist_lds, L.stream>>>(c, A, probes, n, duT, ldb, counts);
+    const uint32_t cells = T.n_bins * (uint32_t)kBinWgs;
+    nbvh_status s = launch_exclusive_scan(L.stream, counts, cells, offsets, sums, sums + cells / 1024 + 3);
+    if (s != NBVH_OK) return s;
+    k_bin_write<F><<<kBinWgs, 256, hist_lds, L.stream>>>(c, A, probes, n, duT, ldb, offsets,
+                                                        (uint16_t*)(w + T.rec_idx), (float*)(w + T.rec_val));
+  }
+  {
+    ProfScope ps(L.prof, NBVH_K_SCATTER_REDUCE, L.stream);
+    k_bin_reduce<F><<<T.n_bins, 1024, 0, L.stream>>>(A, offsets, kBinWgs, (const uint16_t*)(w + T.rec_idx),
+                                                     (const float*)(w + T.rec_val), c.n_table, L.grad);
+  }
   return check_launch("scatter");
 }
 
@@ -1003,11 +1012,8 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
     const uint64_t span = c.n_params - c.w_off[0];
     k_wgrad_reduce<<<(uint32_t)((span + 255) / 256), 256, 0, L.stream>>>(c, wpart, T.nsplit, L.grad, L.state);
   }
-  {
-    ProfScope ps(L.prof, NBVH_K_SCATTER, L.stream);
-    nbvh_status s = launch_scatter<F>(L, T, w, probes, n, P.duT, kb);
-    if (s != NBVH_OK) return s;
-  }
+  nbvh_status s = launch_scatter<F>(L, T, w, probes, n, P.duT, kb);
+  if (s != NBVH_OK) return s;
   return check_launch("train");
 }
 

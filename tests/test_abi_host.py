@@ -89,3 +89,12 @@ def test_null_arguments_rejected_before_any_gpu_work(abi):
     assert L.nbvh_build(ctypes.byref(c), None, 0, None, 0, None, ctypes.byref(out)) == abi.NBVH_ERR_INVALID_ARG
     assert L.nbvh_query(None, None, 0, None, 0, None, 0, None) == abi.NBVH_ERR_INVALID_ARG
     assert L.nbvh_train_step(None, None, None, 0, None, None, 0, None) == abi.NBVH_ERR_INVALID_ARG
+
+
+def test_profile_groups_match_header(abi):
+    src = open(os.path.join(ROOT, "include", "nbvh.h")).read()
+    n = int(re.search(r"NBVH_K_COUNT\s*=\s*(\d+)", src).group(1))
+    assert abi.NBVH_K_COUNT == n == len(abi.KERNEL_GROUPS)
+    ids = re.findall(r"NBVH_K_([A-Z_]+)\s*=\s*(\d+)", src)
+    names = {int(v): k.lower() for k, v in ids if k != "COUNT"}
+    assert [names[i] for i in range(n)] == abi.KERNEL_GROUPS
