@@ -87,6 +87,7 @@ def build_frame(configs, scene):
     W.net = configs.C2_NET
     W.params0 = configs.init_params(W.net, "normal", 1e-2)
     W.per_leaf = 256
+    W.inside_fraction = 0.0
     W.seg_cap_per_ray = 16
     W.describe = ("1920x1080 primary rays on a 1,003,520-triangle displaced icosphere, 1,024 neural leaves; "
                   "hash grid L=16 F=2 T=2^19, 8 samples/segment, MLP 256-4x128-5; train batch 2^18 probes")
@@ -111,10 +112,12 @@ def build_secondary(configs, scene):
     W.net = configs.C5_NET
     W.params0 = configs.init_params(W.net, "normal", 1e-2)
     W.per_leaf = 16
+    W.inside_fraction = 0.5  # half the probes start inside their leaf, as the bounce rays do
     W.seg_cap_per_ray = 8
     W.describe = ("2^24 cosine-weighted bounce rays from the 1920x1080 frame's primary hits on a 3,996,180-triangle "
                   "displaced icosphere with per-vertex albedo, 16,384 neural leaves; hash grid L=16 F=4 T=2^22, "
-                  "4 samples/segment, MLP 256-4x256-8 (hit, t, normal, albedo); train batch 2^18 probes")
+                  "4 samples/segment, MLP 256-4x256-8 (hit, t, normal, albedo); train batch 2^18 probes, half of "
+                  "them starting inside their leaf")
     W.cpu_sample = lambda stride: (W.rays[::stride * stride * 16], "every %dth ray" % (stride * stride * 16))
     return W
 
@@ -149,7 +152,7 @@ def run_single(args, W, P, torch, configs, scene):
     sc, net = W.sc, W.net
     batches = []
     for i in range(args.batches):
-        pr, _ = scene.leaf_probes(sc.boxes, W.per_leaf, seed=scene.SEED_PROBES + i)
+        pr, _ = scene.leaf_probes(sc.boxes, W.per_leaf, seed=scene.SEED_PROBES + i, inside_fraction=W.inside_fraction)
         lb = scene.probe_labels(sc.mesh, pr)
         batches.append((torch.from_numpy(pr).cuda(), torch.from_numpy(lb).cuda()))
     B = batches[0][0].shape[0]

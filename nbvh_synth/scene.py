@@ -278,10 +278,15 @@ def _clip_box64(o, d, lo, hi):
     return tn, tf
 
 
-def leaf_probes(boxes: np.ndarray, per_leaf: int, seed: int = SEED_PROBES, radius_scale: float = 1.5):
+def leaf_probes(boxes: np.ndarray, per_leaf: int, seed: int = SEED_PROBES, radius_scale: float = 1.5,
+                inside_fraction: float = 0.0):
     """BVH-driven probe segments: for each leaf, origins uniform on the sphere
     around the box centre with radius radius_scale * half-diagonal, directions
     uniform on S^2, kept when the ray crosses the box (rejection sampling).
+    With inside_fraction > 0, that share of each leaf's probes (the last ones)
+    instead starts at a point uniform inside the box, direction uniform on
+    S^2, segment [0, exit] (rays that begin inside a leaf, as secondary rays
+    leaving a surface do).
     Returns (probes [n_leaves*per_leaf][8] float32 as o.xyz, t0, d.xyz, t1;
     leaf ids [n] int32), leaf-major."""
     rng = np.random.default_rng(seed)
@@ -317,6 +322,18 @@ def leaf_probes(boxes: np.ndarray, per_leaf: int, seed: int = SEED_PROBES, radiu
         row[:, 7] = tf[s]
         out[la, rank] = row
         np.add.at(have, la, 1)
+    k = int(round(inside_fraction * per_leaf))
+    if k > 0:
+        rng2 = np.random.default_rng(seed + 1000)
+        leaf = np.repeat(np.arange(nl), k)
+        o = lo[leaf] + rng2.uniform(size=(leaf.size, 3)) * (hi - lo)[leaf]
+        d = _unit_vectors(rng2, leaf.size)
+        _, tf = _clip_box64(o, d, lo[leaf], hi[leaf])
+        rows = np.zeros((leaf.size, 8), dtype=np.float32)
+        rows[:, 0:3] = o
+        rows[:, 4:7] = d
+        rows[:, 7] = np.maximum(tf, 0.0)
+        out[:, per_leaf - k:] = rows.reshape(nl, k, 8)
     leaf_ids = np.repeat(np.arange(nl, dtype=np.int32), per_leaf)
     return out.reshape(-1, 8), leaf_ids
 
