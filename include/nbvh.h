@@ -288,6 +288,33 @@ nbvh_status nbvh_query_segments(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_
                                 const uint32_t* seg_offsets_dev, const nbvh_segment* segs_dev,
                                 nbvh_hit* hits_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Training-ray selection for the error-driven construction (Sec. 5.3, "Ray
+ * distribution" and "Node error"). For each of the n_rays rays (device,
+ * typically sampled uniformly in the inflated root box) the N-BVH is
+ * traversed as by nbvh_traverse; the first leaf crossed (smallest t0, ties
+ * to the lower leaf id) is kept iff u_dev[r] < accept_dev[leaf] (u_dev:
+ * [n_rays] caller-drawn uniforms in [0, 1); accept_dev: [n_leaves]
+ * acceptance probabilities). Kept segments are written to probes_dev as
+ * (o, t0, d, t1) with their leaf id in leaf_ids_dev, in an unspecified
+ * order; both need room for n_rays entries. *n_out_dev (device) receives the
+ * number kept (cleared by the call). If leaf_hits_dev is not NULL, every
+ * leaf crossed by a ray has its counter incremented (the caller clears it),
+ * the numerator of the node's hit-probability estimate. Asynchronous. */
+nbvh_status nbvh_first_hits(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_rays, const float* u_dev,
+                            const float* accept_dev, nbvh_probe* probes_dev, uint32_t* leaf_ids_dev,
+                            uint32_t* n_out_dev, uint32_t* leaf_hits_dev, void* stream);
+
+/* Per-leaf training loss (Sec. 5.3, "Node error"): runs the network on the n
+ * segments probes_dev with labels_dev and adds each segment's combined loss
+ * (weights w_hit, w_t, w_normal; not divided by the batch size) to
+ * leaf_loss_dev[leaf_ids_dev[i]] (float, [n_leaves]) and one to
+ * leaf_count_dev[...] (uint32). The caller clears both. Needs n * n_out
+ * floats of workspace. Asynchronous; atomics make the sums' rounding order
+ * unspecified. */
+nbvh_status nbvh_leaf_loss(nbvh_ctx* ctx, const nbvh_probe* probes_dev, const nbvh_label* labels_dev,
+                           const uint32_t* leaf_ids_dev, uint64_t n, float* leaf_loss_dev,
+                           uint32_t* leaf_count_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Encoding only (Sec. 3/4): u_dev[n][n_in] FP32 features of each probe's
  * samples, read from the FP32 table (precision FP32) or the BF16 shadow. */
 nbvh_status nbvh_encode(nbvh_ctx* ctx, const nbvh_probe* probes_dev, uint64_t n, float* u_dev,

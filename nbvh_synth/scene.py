@@ -219,6 +219,59 @@ def median_split_leaves(verts: np.ndarray, tris: np.ndarray, n_leaves: int, pad_
     return boxes, tri_leaf
 
 
+def _padded_box(verts, tris, g, pad):
+    p = verts[tris[g]].reshape(-1, 3)
+    lo = p.min(axis=0) - pad
+    hi = p.max(axis=0) + pad
+    lo32 = lo.astype(np.float32)
+    hi32 = hi.astype(np.float32)
+    lo32 = np.where(lo32.astype(np.float64) > lo, np.nextafter(lo32, np.float32(-np.inf)), lo32)
+    hi32 = np.where(hi32.astype(np.float64) < hi, np.nextafter(hi32, np.float32(np.inf)), hi32)
+    return lo32, hi32
+
+
+def base_bvh(verts: np.ndarray, tris: np.ndarray, leaf_tris: int = 16, pad_rel: float = 1e-4):
+    """The input geometry's own BVH (the "base BVH" a cut is taken from): the
+    same median split as median_split_leaves (widest centroid axis, order by
+    (coordinate, triangle id), cut at floor(n/2)), recursed until a node holds
+    at most leaf_tris triangles. Node boxes are the triangles' bounds padded
+    by pad_rel * scene diagonal and rounded outward to float32, so a child's
+    box lies inside its parent's. Returns dict(lo [m][3], hi [m][3] float32,
+    left, right [m] int32 (-1 at leaves), n_tris [m] int32); node 0 is the
+    root, children follow their parent."""
+    cen = verts[tris].mean(axis=1)
+    diag = float(np.linalg.norm(verts.max(axis=0) - verts.min(axis=0)))
+    pad = pad_rel * diag
+    lo, hi, left, right, cnt = [], [], [], [], []
+
+    def new_node(g):
+        a, b = _padded_box(verts, tris, g, pad)
+        lo.append(a)
+        hi.append(b)
+        left.append(-1)
+        right.append(-1)
+        cnt.append(g.size)
+        return len(lo) - 1
+
+    stack = [(new_node(np.arange(tris.shape[0], dtype=np.int64)), np.arange(tris.shape[0], dtype=np.int64))]
+    while stack:
+        node, g = stack.pop()
+        if g.size <= leaf_tris:
+            continue
+        c = cen[g]
+        ax = int(np.argmax(c.max(axis=0) - c.min(axis=0)))
+        g = g[np.lexsort((g, c[:, ax]))]
+        h = g.size // 2
+        a, b = g[:h], g[h:]
+        left[node] = new_node(a)
+        right[node] = new_node(b)
+        stack.append((right[node], b))
+        stack.append((left[node], a))
+    return dict(lo=np.array(lo, dtype=np.float32), hi=np.array(hi, dtype=np.float32),
+                left=np.array(left, dtype=np.int32), right=np.array(right, dtype=np.int32),
+                n_tris=np.array(cnt, dtype=np.int32))
+
+
 def scene_cube(boxes: np.ndarray):
     """Normalisation cube: minimum corner of the leaf union and its largest extent (float32)."""
     lo = boxes[:, :3].min(axis=0).astype(np.float32)

@@ -61,6 +61,7 @@ def _lib():
             L.oc_encode.argtypes = [P, P, P, I, P]
             L.oc_mlp_forward.argtypes = [P, P, P, I, P]
             L.oc_loss.argtypes = [P, P, P, I, D, D, D, P, P]
+            L.oc_segment_loss.argtypes = [P, P, P, I, D, D, D, P]
             L.oc_backward.argtypes = [P, P, P, I, P, P]
             L.oc_adam.argtypes = [I, P, P, P, P, I, D, D, D, D, D]
             L.oc_min_abs_preact.argtypes = [P, P, P, I, P]
@@ -213,6 +214,32 @@ def loss(cfg, z, labels, weights=LOSS_WEIGHTS, with_grad=True):
     _lib().oc_loss(ctypes.byref(cfg), _p(z), _p(labels), z.shape[0], float(weights[0]), float(weights[1]),
                    float(weights[2]), _p(out), _p(dz))
     return out, dz
+
+
+def segment_loss(cfg, z, labels, weights=LOSS_WEIGHTS):
+    """[n] combined loss of each segment (weights applied, no 1/B)."""
+    z = _c(z, np.float64)
+    labels = _c(labels, np.float32)
+    out = np.zeros(z.shape[0], dtype=np.float64)
+    _lib().oc_segment_loss(ctypes.byref(cfg), _p(z), _p(labels), z.shape[0], float(weights[0]), float(weights[1]),
+                           float(weights[2]), _p(out))
+    return out
+
+
+def first_hits(rays, boxes, u, accept):
+    """Training-ray selection (Sec. 5.3): for each ray its first crossed leaf
+    (smallest t0, ties to the lower id, from the every-leaf traversal), kept
+    iff u[r] < accept[leaf] in binary32. Returns (ray indices kept, their
+    leaf, t0, t1) in ray order and the number of rays crossing each leaf."""
+    off, sr, sl, t0, t1 = traverse(rays, boxes)
+    off = off.astype(np.int64)
+    has = off[1:] > off[:-1]
+    first = off[:-1][has]  # runs are sorted by (t0, leaf): the first entry is the first leaf
+    ray = np.nonzero(has)[0]
+    leaf = sl[first].astype(np.int64)
+    keep = np.asarray(u, dtype=np.float32)[ray] < np.asarray(accept, dtype=np.float32)[leaf]
+    hits = np.bincount(sl.astype(np.int64), minlength=boxes.shape[0])
+    return ray[keep], leaf[keep], t0[first][keep], t1[first][keep], hits
 
 
 def backward(cfg, params, segs, dz):

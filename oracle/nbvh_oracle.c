@@ -424,6 +424,26 @@ void oc_loss(const oc_cfg* c, const double* z, const float* labels, int64_t n, d
   loss_out[0] = w_hit * loss_out[1] + w_t * loss_out[2] + w_n * loss_out[3];
 }
 
+/* Combined loss of each segment on its own (Sec. 5.3, "Node error": the
+ * training loss q of a node is taken over the segments that train it):
+ * out[i] = w_hit BCE + h (w_t |sigma(z1) - tau| + w_n (1/3) sum |n_hat - n|),
+ * not divided by the batch size. */
+void oc_segment_loss(const oc_cfg* c, const double* z, const float* labels, int64_t n, double w_hit, double w_t,
+                     double w_n, double* out) {
+  int no = c->n_out;
+  for (int64_t i = 0; i < n; ++i) {
+    const double* zi = z + (int64_t)no * i;
+    const float* lb = labels + 8 * i;
+    double h = (double)lb[4];
+    double z0 = zi[0];
+    double bce = (z0 > 0.0 ? z0 : 0.0) - z0 * h + log1p(exp(-fabs(z0)));
+    double lt = fabs(oc_sigmoid(zi[1]) - (double)lb[0]);
+    double ln = 0.0;
+    for (int a = 0; a < 3; ++a) ln += fabs(zi[2 + a] - (double)lb[1 + a]);
+    out[i] = w_hit * bce + h * (w_t * lt + w_n * ln / 3.0);
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Back-propagation of dL/dz into every parameter (Sec. 4: the loss is       */
 /* back-propagated to the learnable parameters): through the MLP layers      */

@@ -478,6 +478,33 @@ nbvh_status nbvh_query_segments(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_
                            0xffffffffull);
 }
 
+nbvh_status nbvh_first_hits(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, const float* u, const float* accept,
+                            nbvh_probe* probes, uint32_t* leaf_ids, uint32_t* n_out, uint32_t* leaf_hits,
+                            void* stream) {
+  if (!ctx) return set_error("ctx is NULL"), NBVH_ERR_INVALID_ARG;
+  if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
+  if (!n_out || (n_rays && (!rays || !u || !accept || !probes || !leaf_ids)))
+    return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  return launch_first_hits(make_launch(ctx, stream), rays, (uint32_t)n_rays, u, accept, probes, leaf_ids, n_out,
+                           leaf_hits);
+}
+
+nbvh_status nbvh_leaf_loss(nbvh_ctx* ctx, const nbvh_probe* probes, const nbvh_label* labels, const uint32_t* leaf_ids,
+                           uint64_t n, float* leaf_loss, uint32_t* leaf_count, void* ws, size_t ws_bytes,
+                           void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  s = require_fp8_ready(ctx);
+  if (s != NBVH_OK) return s;
+  if (n > 0x7fffffffull) return set_error("batch too large"), NBVH_ERR_UNSUPPORTED;
+  if (n && (!probes || !labels || !leaf_ids || !leaf_loss || !leaf_count || !ws))
+    return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  const size_t need = (size_t)n * ctx->cfg.n_out * sizeof(float);
+  if (ws_bytes < need) return set_error("workspace too small: need %zu", need), NBVH_ERR_CAPACITY;
+  return launch_leaf_loss(make_launch(ctx, stream), probes, labels, leaf_ids, (uint32_t)n, (float*)ws, leaf_loss,
+                          leaf_count);
+}
+
 nbvh_status nbvh_encode(nbvh_ctx* ctx, const nbvh_probe* probes, uint64_t n, float* u, void* stream) {
   nbvh_status s = require_bound(ctx);
   if (s != NBVH_OK) return s;

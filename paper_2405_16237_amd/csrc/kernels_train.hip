@@ -855,6 +855,36 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ z, const
   }
 }
 
+// Per-leaf sums of the segment loss (Sec. 5.3, "Node error": a node's
+// training loss q): the combined loss of each segment, unscaled and with the
+// loss weights, added to leaf_loss[leaf] with one count in leaf_count[leaf].
+__global__ __launch_bounds__(256) void k_leaf_loss(const float* __restrict__ z, const nbvh_label* __restrict__ labels,
+                                                   const uint32_t* __restrict__ leaf_ids, uint32_t n, int n_out,
+                                                   float w_hit, float w_t, float w_normal,
+                                                   float* __restrict__ leaf_loss, uint32_t* __restrict__ leaf_count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* zr = z + (size_t)i * n_out;
+  const nbvh_label lb = labels[i];
+  const float h = lb.hit, st = sigmoidf_(zr[1]);
+  float s = 0.f;
+  for (int a = 0; a < 3; ++a) s += fabsf(zr[2 + a] - lb.n[a]);
+  const float loss = w_hit * bce_logits(zr[0], h) + w_t * h * fabsf(st - lb.tau) + w_normal * h * s * (1.0f / 3.0f);
+  const uint32_t leaf = leaf_ids[i];
+  atomicAdd(&leaf_loss[leaf], loss);
+  atomicAdd(&leaf_count[leaf], 1u);
+}
+
+nbvh_status launch_leaf_loss(const LaunchCtx& L, const nbvh_probe* probes, const nbvh_label* labels,
+                             const uint32_t* leaf_ids, uint32_t n, float* z, float* leaf_loss, uint32_t* leaf_count) {
+  if (n == 0) return NBVH_OK;
+  nbvh_status s = launch_forward(L, probes, n, z);
+  if (s != NBVH_OK) return s;
+  k_leaf_loss<<<(n + 255) / 256, 256, 0, L.stream>>>(z, labels, leaf_ids, n, L.cfg.n_out, L.w_hit, L.w_t, L.w_normal,
+                                                     leaf_loss, leaf_count);
+  return check_launch("leaf_loss");
+}
+
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ g, uint64_t n,
                                                       DevState* __restrict__ state) {

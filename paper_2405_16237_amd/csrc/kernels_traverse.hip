@@ -165,6 +165,60 @@ __global__ __launch_bounds__(256) void k_traverse_fill(const Node* __restrict__ 
   });
 }
 
+// Training-ray selection (Sec. 5.3, "Ray distribution"): each ray trains only
+// the first leaf it crosses (smallest t0, ties to the lower leaf id), and that
+// leaf is kept with probability accept[leaf] (kept iff u[r] < accept[leaf]).
+// Every leaf a ray crosses also counts one hit towards its hit-probability
+// estimate (Sec. 5.3, "Node error"). Kept segments are appended in wave order.
+__global__ __launch_bounds__(256) void k_first_hits(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
+                                                    uint32_t n, const float* __restrict__ u,
+                                                    const float* __restrict__ accept, nbvh_probe* __restrict__ probes,
+                                                    uint32_t* __restrict__ leaf_out, uint32_t* __restrict__ n_out,
+                                                    uint32_t* __restrict__ leaf_hits) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  bool take = false;
+  int32_t best = -1;
+  float b0 = 0.f, b1 = 0.f;
+  RayPre R;
+  if (r < n) {
+    R = load_ray(rays, r);
+    walk(nodes, R, [&](int32_t leaf, float t0, float t1) {
+      if (leaf_hits) atomicAdd(&leaf_hits[leaf], 1u);
+      if (best < 0 || t0 < b0 || (t0 == b0 && leaf < best)) {
+        best = leaf;
+        b0 = t0;
+        b1 = t1;
+      }
+    });
+    take = best >= 0 && u[r] < accept[best];
+  }
+  const uint64_t mask = __ballot(take);
+  if (mask) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(n_out, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    if (take) {
+      const uint32_t k = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+      float4* p = (float4*)(probes + k);
+      p[0] = make_float4(R.o[0], R.o[1], R.o[2], b0);
+      p[1] = make_float4(R.d[0], R.d[1], R.d[2], b1);
+      leaf_out[k] = (uint32_t)best;
+    }
+  }
+}
+
+nbvh_status launch_first_hits(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n, const float* u,
+                              const float* accept, nbvh_probe* probes, uint32_t* leaf_out, uint32_t* n_out,
+                              uint32_t* leaf_hits) {
+  k_zero_u32<<<1, 64, 0, L.stream>>>(n_out, 1);
+  if (n > 0)
+    k_first_hits<<<(n + 255) / 256, 256, 0, L.stream>>>(L.nodes, rays, n, u, accept, probes, leaf_out, n_out,
+                                                        leaf_hits);
+  return check_launch("first_hits");
+}
+
 // ---------------------------------------------------------------------------
 // exclusive scan of uint32 counts (3 kernels: tile scan, scan of tile sums,
 // add). Tile = 256 threads x 4 items.

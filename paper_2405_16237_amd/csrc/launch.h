@@ -90,6 +90,13 @@ nbvh_status launch_query_eval_batch(const LaunchCtx* Ls, int n_obj, const DevCfg
                                     const uint32_t* const* n_active, uint32_t* const* counters, nbvh_hit* per_obj,
                                     nbvh_hit* hits, const nbvh_ray* rays, uint32_t n_rays, uint64_t capacity);
 
+nbvh_status launch_first_hits(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n, const float* u,
+                              const float* accept, nbvh_probe* probes, uint32_t* leaf_out, uint32_t* n_out,
+                              uint32_t* leaf_hits);
+
+nbvh_status launch_leaf_loss(const LaunchCtx& L, const nbvh_probe* probes, const nbvh_label* labels,
+                             const uint32_t* leaf_ids, uint32_t n, float* z, float* leaf_loss, uint32_t* leaf_count);
+
 nbvh_status launch_active_rays(const LaunchCtx& L, const uint32_t* offsets, uint32_t n_rays, nbvh_hit* hits,
                                uint32_t* active, uint32_t* misc);
 

@@ -80,6 +80,7 @@ class NBVH:
                             _ptr(self.aux).value)
         check(self.lib.nbvh_bind_params(self.ctx, ctypes.byref(p)))
         check(self.lib.nbvh_reset_optimizer(self.ctx, _stream()))
+        self._p = p
         self._ws = None
 
     def __del__(self):
@@ -151,7 +152,48 @@ class NBVH:
             self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
         return self._ws
 
+    def rebuild(self, leaf_boxes):
+        """Build the N-BVH over new leaf boxes (for instance a longer cut of a
+        base BVH), keeping the network parameters, optimiser moments, device
+        state and launch knobs. The hash-grid domain (scene_lo, scene_side)
+        is unchanged, so the boxes must stay inside it."""
+        lb = np.ascontiguousarray(leaf_boxes, dtype=np.float32)
+        nb = self.lib.nbvh_nodes_bytes(lb.shape[0])
+        nodes = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        tuning = self.get_tuning()
+        ctx = ctypes.c_void_p()
+        check(self.lib.nbvh_build(ctypes.byref(self.cfg), lb.ctypes.data_as(ctypes.c_void_p), lb.shape[0],
+                                  _ptr(nodes), nb, _stream(), ctypes.byref(ctx)))
+        check(self.lib.nbvh_bind_params(ctx, ctypes.byref(self._p)))
+        old, self.ctx = self.ctx, ctx
+        self.lib.nbvh_destroy(old)
+        self.nodes, self.n_leaves = nodes, lb.shape[0]
+        self.set_tuning(**tuning)
+
     # -- calls --------------------------------------------------------------------
+    def first_hits(self, rays: torch.Tensor, u: torch.Tensor, accept: torch.Tensor,
+                   leaf_hits: torch.Tensor | None = None):
+        """Training-ray selection: (probes [k][8], leaf ids [k] int32) of the
+        first leaf each ray crosses, kept where u < accept[leaf]; leaf_hits
+        ([n_leaves] int32, optional) counts every leaf crossing."""
+        n = rays.shape[0]
+        probes = torch.empty((max(n, 1), 8), dtype=torch.float32, device=self.device)
+        leaf = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        cnt = torch.zeros(1, dtype=torch.int32, device=self.device)
+        check(self.lib.nbvh_first_hits(self.ctx, _ptr(rays), n, _ptr(u), _ptr(accept), _ptr(probes), _ptr(leaf),
+                                       _ptr(cnt), _ptr(leaf_hits), _stream()))
+        k = int(cnt.item())
+        return probes[:k], leaf[:k]
+
+    def leaf_loss(self, probes: torch.Tensor, labels: torch.Tensor, leaf_ids: torch.Tensor,
+                  leaf_loss: torch.Tensor, leaf_count: torch.Tensor):
+        """Adds each segment's combined loss to leaf_loss[leaf] (float32) and
+        one to leaf_count[leaf] (int32)."""
+        n = probes.shape[0]
+        ws = self.workspace(0, 0, n)
+        check(self.lib.nbvh_leaf_loss(self.ctx, _ptr(probes), _ptr(labels), _ptr(leaf_ids), n, _ptr(leaf_loss),
+                                      _ptr(leaf_count), _ptr(ws), ws.numel(), _stream()))
+
     def traverse(self, rays: torch.Tensor, seg_capacity: int):
         n = rays.shape[0]
         offsets = torch.empty(n + 1, dtype=torch.int32, device=self.device)

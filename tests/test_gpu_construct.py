@@ -1,0 +1,139 @@
+"""Error-driven construction through the C ABI: first-hit training-ray
+selection and per-leaf losses against the oracle, then a small construction
+run (Sec. 5.3) on the 20,480-triangle mesh."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from nbvh_synth import configs, scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_16237_amd as P
+    P.load()
+    return P
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return configs.make_scene(20480, 64)
+
+
+def _box_rays(sc, n, seed):
+    """Rays uniform in the 50 %-inflated scene box, uniform directions."""
+    rng = np.random.default_rng(seed)
+    lo = sc.boxes[:, :3].min(0).astype(np.float64)
+    hi = sc.boxes[:, 3:].max(0).astype(np.float64)
+    ext = hi - lo
+    r = np.zeros((n, 8), dtype=np.float32)
+    r[:, 0:3] = lo - 0.25 * ext + rng.uniform(size=(n, 3)) * 1.5 * ext
+    d = rng.normal(size=(n, 3))
+    r[:, 4:7] = d / np.linalg.norm(d, axis=1, keepdims=True)
+    r[:, 7] = np.inf
+    return r
+
+
+def test_first_hits_match_oracle(lib, c1):
+    sc = c1
+    m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="fp32")
+    rays = _box_rays(sc, 50_000 + 33, 71)
+    rng = np.random.default_rng(72)
+    u = rng.uniform(size=rays.shape[0]).astype(np.float32)
+    accept = rng.uniform(0.0, 1.0, size=sc.boxes.shape[0]).astype(np.float32)
+    accept[:5] = 1.0
+    accept[5:8] = 0.0
+    hits = torch.zeros(sc.boxes.shape[0], dtype=torch.int32, device="cuda")
+    _say("first hits", rays.shape)
+    probes, leaf = m.first_hits(torch.from_numpy(rays).cuda(), torch.from_numpy(u).cuda(),
+                                torch.from_numpy(accept).cuda(), leaf_hits=hits)
+    ray, oleaf, t0, t1, ohits = oracle.first_hits(rays, sc.boxes, u, accept)
+    assert np.array_equal(hits.cpu().numpy(), ohits)
+    p = probes.cpu().numpy()
+    lf = leaf.cpu().numpy()
+    assert p.shape[0] == ray.size > 1000
+    # order is unspecified: sort both by (origin, direction) bits
+    key_g = np.lexsort(p.view(np.int32).T[::-1])
+    ref = np.zeros((ray.size, 8), dtype=np.float32)
+    ref[:, 0:3] = rays[ray, 0:3]
+    ref[:, 3] = t0
+    ref[:, 4:7] = rays[ray, 4:7]
+    ref[:, 7] = t1
+    key_o = np.lexsort(ref.view(np.int32).T[::-1])
+    assert np.array_equal(p[key_g].view(np.int32), ref[key_o].view(np.int32))
+    assert np.array_equal(lf[key_g].astype(np.int64), oleaf[key_o])
+
+
+def test_leaf_loss_matches_oracle(lib, c1):
+    sc = c1
+    net = configs.C1_NET
+    params = configs.init_params(net, "uniform", 0.5, seed_features=73, seed_mlp=74)
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32")
+    m.set_params(params)
+    probes, leaf_ids = scene.leaf_probes(sc.boxes, 40, seed=75)
+    labels = scene.probe_labels(sc.mesh, probes)
+    n_leaves = sc.boxes.shape[0]
+    loss = torch.zeros(n_leaves, dtype=torch.float32, device="cuda")
+    count = torch.zeros(n_leaves, dtype=torch.int32, device="cuda")
+    _say("leaf loss", probes.shape)
+    m.leaf_loss(torch.from_numpy(probes).cuda(), torch.from_numpy(labels).cuda(),
+                torch.from_numpy(leaf_ids).cuda(), loss, count)
+    cfg = oracle.make_cfg(net, sc.lo, sc.side)
+    z = oracle.forward(cfg, params.astype(np.float64), probes)
+    seg = oracle.segment_loss(cfg, z, labels)
+    ref = np.bincount(leaf_ids, weights=seg, minlength=n_leaves)
+    assert np.array_equal(count.cpu().numpy(), np.bincount(leaf_ids, minlength=n_leaves))
+    got = loss.double().cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max(), np.abs(got - ref).max() / np.abs(ref).max()
+
+
+def test_construction_grows_cut_and_learns(lib, c1):
+    """The cut grows from the root to the target through base-BVH nodes,
+    every expansion splits the leaves of largest rank, and the constructed
+    N-BVH answers camera rays better than its boxes alone."""
+    from paper_2405_16237_amd import construct as C
+    sc = c1
+    base = scene.base_bvh(sc.verts, sc.tris, leaf_tris=64)
+    net = configs.C1_NET
+    root = np.concatenate([base["lo"][0], base["hi"][0]])[None, :]
+    lo, side = scene.scene_cube(root)
+    sched = C.Schedule(target_leaves=32, iters=40, iters_growth=1.3, splits=2, splits_growth=1.6, final_iters=300,
+                       rays_per_step=1 << 15, stats_rays=1 << 15)
+    model, cut, hist = C.construct(net, base, lambda p: scene.probe_labels(sc.mesh, p), sched, lo, side,
+                                   params=configs.init_params(net, "normal", 1e-2), log=_say)
+    assert len(cut.nodes) == 32 and len(set(cut.nodes)) == 32
+    # the cut is a cut: no node is an ancestor of another, and together they hold every triangle
+    parent = np.full(base["lo"].shape[0], -1)
+    inner = np.nonzero(base["left"] >= 0)[0]
+    parent[base["left"][inner]] = inner
+    parent[base["right"][inner]] = inner
+    for nd in cut.nodes:
+        a = parent[nd]
+        while a >= 0:
+            assert a not in cut.nodes
+            a = parent[a]
+    assert base["n_tris"][cut.nodes].sum() == sc.tris.shape[0]
+    assert hist[-1]["loss"] < hist[0]["loss"]
+    rays = scene.pinhole_rays(256, 256)
+    gt = scene.ray_ground_truth(sc.mesh, rays)
+    h = model.query(torch.from_numpy(rays).cuda()).cpu().numpy()
+    pred = h[:, 7].view(np.uint32) != 0xFFFFFFFF
+    acc = float((pred == gt["hit"]).mean())
+    off, _ = model.traverse(torch.from_numpy(rays).cuda(), 64 * rays.shape[0])
+    off = off.cpu().numpy()
+    box_acc = float(((off[1:] > off[:-1]) == gt["hit"]).mean())
+    _say("construction: hit accuracy %.4f, boxes alone %.4f, history %s" % (acc, box_acc, hist))
+    assert acc > box_acc and acc > 0.9

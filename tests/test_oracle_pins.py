@@ -311,6 +311,40 @@ def test_layer_amax_positive_homogeneity():
     assert abs(b[2] - 3.0 * a[2]) <= 1e-12 * a[2] and abs(b[3] - 3.0 * a[3]) <= 1e-12 * a[3]
 
 
+def test_first_hits_hand_cases():
+    """The first leaf a ray crosses, the acceptance test and the crossing
+    counts on hand-placed boxes (two unit cubes on the x axis, and a copy of
+    the first to make a tie that the lower id wins)."""
+    boxes = np.array([[0, 0, 0, 1, 1, 1], [2, 0, 0, 3, 1, 1], [0, 0, 0, 1, 1, 1]], dtype=np.float32)
+    rays = np.array([[-1, .5, .5, 0, 1, 0, 0, np.inf],     # +x: crosses 0, 2 (tie at t=1) then 1
+                     [4, .5, .5, 0, -1, 0, 0, np.inf],     # -x: crosses 1 first
+                     [-1, 5, .5, 0, 1, 0, 0, np.inf]],     # misses everything
+                    dtype=np.float32)
+    u = np.array([0.5, 0.5, 0.0], dtype=np.float32)
+    ray, leaf, t0, t1, hits = oracle.first_hits(rays, boxes, u, np.array([1.0, 0.6, 1.0], dtype=np.float32))
+    assert ray.tolist() == [0, 1] and leaf.tolist() == [0, 1]
+    assert t0.tolist() == [1.0, 1.0] and t1.tolist() == [2.0, 2.0]
+    assert hits.tolist() == [2, 2, 2]
+    ray, leaf, *_ = oracle.first_hits(rays, boxes, u, np.array([0.5, 0.6, 1.0], dtype=np.float32))
+    assert ray.tolist() == [1]  # u = 0.5 is not below an acceptance of 0.5
+
+
+def test_segment_loss_closed_form_and_mean():
+    """At z = 0 each segment's loss is 2 log 2 + h (2 |1/2 - tau| + (1/3)
+    sum |n|); at any z the segment losses average to the batch loss."""
+    net = Net(1, 2, 8, 1, [3])
+    cfg = _cfg(net)
+    rng = np.random.default_rng(35)
+    lab = _labels(rng, 50)
+    z0 = np.zeros((50, 5))
+    h, tau, nn = lab[:, 4].astype(np.float64), lab[:, 0].astype(np.float64), lab[:, 1:4].astype(np.float64)
+    ref = 2 * np.log(2.0) + h * (2 * np.abs(0.5 - tau) + np.abs(nn).sum(1) / 3.0)
+    assert np.abs(oracle.segment_loss(cfg, z0, lab) - ref).max() < 1e-14
+    z = rng.normal(size=(50, 5))
+    terms, _ = oracle.loss(cfg, z, lab, with_grad=False)
+    assert abs(oracle.segment_loss(cfg, z, lab).mean() - terms[0]) < 1e-13
+
+
 # ---------------------------------------------------------------- loss
 def _labels(rng, n, hit_frac=0.5):
     lab = np.zeros((n, 8), dtype=np.float32)
