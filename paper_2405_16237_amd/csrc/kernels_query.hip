@@ -166,11 +166,24 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
     __syncthreads();
     if (*s_any == 0) break;
 
+    // wave 0 fetches each live slot's following segment now, so the load
+    // overlaps the encoding and the MLP instead of stalling the resolve
+    nbvh_segment nxt{0u, 0u, INFINITY, INFINITY};
+    if (wave == 0 && s_valid[lane]) {
+      const uint32_t c1 = s_cur[lane] + 1;
+      if (c1 < s_end[lane]) nxt = J.segs[c1];
+    }
     if constexpr (sizeof(AT) == 1) {
       encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM, J.scales[kMaxLayers]);
       __syncthreads();
       mlp_forward_tile_fp8<kQM, NW>(c, (const uint8_t*)J.W, J.scales, (uint8_t*)act0, ld0, (uint8_t*)act1, ld1, z,
                                     kOutPad);
+    } else if constexpr (sizeof(AT) == 2) {
+      // layer 0's first weight fragments travel while the table is gathered
+      const PreBf16 pre0 = prefetch_bf16<NW>((const bf16*)J.W + c.w_off[0], c.fan_in[0], c.fan_in[0], c.fan_out[0]);
+      encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM);
+      __syncthreads();
+      mlp_forward_tile<kQM, NW, AT>(c, (const AT*)J.W, act0, ld0, act1, ld1, z, kOutPad, &pre0);
     } else {
       encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM);
       __syncthreads();
@@ -202,14 +215,11 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
       const uint32_t cur = s_cur[lane] + 1;
       s_cur[lane] = cur;
       bool more = false;
-      if (cur < s_end[lane]) {
-        const nbvh_segment sg = J.segs[cur];
-        if (sg.t0 < best_t) {
-          more = true;
-          s_leaf[lane] = sg.leaf;
-          sA[lane].w = sg.t0;
-          sB[lane].w = sg.t1;
-        }
+      if (cur < s_end[lane] && nxt.t0 < best_t) {
+        more = true;
+        s_leaf[lane] = nxt.leaf;
+        sA[lane].w = nxt.t0;
+        sB[lane].w = nxt.t1;
       }
       if (!more) {
         float4* h = (float4*)(J.hits + ray);

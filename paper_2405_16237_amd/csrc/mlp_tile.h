@@ -45,10 +45,31 @@ __device__ inline bf16x8 zero_bf16x8() {
   return z;
 }
 
+// The first two weight fragments (k = 0..63 of its first n-tile) a wave
+// needs in a BF16 layer, fetched ahead so that they are in flight while the
+// previous layer (or the encoding) still computes.
+struct PreBf16 {
+  bf16x8 a0, a1;
+};
+
+template <int NWAVES>
+__device__ inline PreBf16 prefetch_bf16(const bf16* __restrict__ W, int ldw, int K, int N) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = wave * 16 + (lane & 15);
+  PreBf16 p{zero_bf16x8(), zero_bf16x8()};
+  if (n < N) {
+    const bf16* wrow = W + (size_t)n * ldw + 8 * (lane >> 4);
+    p.a0 = *(const bf16x8*)wrow;
+    if (32 < K) p.a1 = *(const bf16x8*)(wrow + 32);
+  }
+  return p;
+}
+
 // out^T tile loop. Epi(m, col, f32x4) receives rows m, columns col..col+3.
+// `pre`, if given, holds the wave's first two fragments (prefetch_bf16).
 template <int M, int NWAVES, typename Epi>
 __device__ inline void gemm_tile_bf16(const bf16* act_in, int ld_in, int K, const bf16* __restrict__ W, int ldw,
-                                      int N, Epi epi) {
+                                      int N, Epi epi, const PreBf16* pre = nullptr) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, q = lane >> 4;
   const int n_tiles = (N + 15) >> 4;
@@ -62,8 +83,14 @@ __device__ inline void gemm_tile_bf16(const bf16* act_in, int ld_in, int K, cons
     const bf16* arow = act_in + (size_t)r16 * ld_in + 8 * q;
     for (int k0 = 0; k0 < K; k0 += 64) {
       const bool two = k0 + 32 < K;
-      bf16x8 a0 = nvalid ? *(const bf16x8*)(wrow + k0) : zero_bf16x8();
-      bf16x8 a1 = (nvalid && two) ? *(const bf16x8*)(wrow + k0 + 32) : zero_bf16x8();
+      bf16x8 a0, a1;
+      if (pre && k0 == 0 && nt == wave) {
+        a0 = pre->a0;
+        a1 = pre->a1;
+      } else {
+        a0 = nvalid ? *(const bf16x8*)(wrow + k0) : zero_bf16x8();
+        a1 = (nvalid && two) ? *(const bf16x8*)(wrow + k0 + 32) : zero_bf16x8();
+      }
 #pragma unroll
       for (int mt = 0; mt < M / 16; ++mt) {
         bf16x8 b0 = *(const bf16x8*)(arow + (size_t)mt * 16 * ld_in + k0);
@@ -193,9 +220,10 @@ __device__ inline void mlp_forward_tile_fp8(const DevCfg& c, const uint8_t* W8ba
 }
 
 template <int M, int NWAVES, typename AT, typename Epi>
-__device__ inline void gemm_tile(const AT* act_in, int ld_in, int K, const AT* W, int ldw, int N, Epi epi) {
+__device__ inline void gemm_tile(const AT* act_in, int ld_in, int K, const AT* W, int ldw, int N, Epi epi,
+                                 const PreBf16* pre = nullptr) {
   if constexpr (sizeof(AT) == 2)
-    gemm_tile_bf16<M, NWAVES>(act_in, ld_in, K, W, ldw, N, epi);
+    gemm_tile_bf16<M, NWAVES>(act_in, ld_in, K, W, ldw, N, epi, pre);
   else
     gemm_tile_f32<M, NWAVES>(act_in, ld_in, K, W, ldw, N, epi);
 }
@@ -215,27 +243,45 @@ __device__ inline void store4(AT* dst, f32x4 v) {
 // Full forward of the tile: act0 holds the encoded input [M][n_in]; hidden
 // layers ping-pong between act0 and act1; z receives [M][kOutPad] fp32.
 // keep(k, m, col, relu_vals) sees every hidden output (k = layer index).
+// BF16: each layer's first weight fragments are prefetched while the
+// previous layer computes (layer 0's may come from the caller, `pre0`).
 template <int M, int NWAVES, typename AT, typename Keep>
 __device__ inline void mlp_forward_tile_keep(const DevCfg& c, const AT* Wbase, AT* act0, int ld0, AT* act1, int ld1,
-                                             float* z, int ldz, Keep keep) {
+                                             float* z, int ldz, Keep keep, const PreBf16* pre0 = nullptr) {
   AT* cur = act0;
   int ldc = ld0;
   AT* nxt = act1;
   int ldn = ld1;
+  PreBf16 pre{};
+  if constexpr (sizeof(AT) == 2) {
+    if (pre0) pre = *pre0;
+    else pre = prefetch_bf16<NWAVES>((const bf16*)Wbase + c.w_off[0], c.fan_in[0], c.fan_in[0], c.fan_out[0]);
+  }
   for (int k = 0; k <= c.hidden; ++k) {
     const bool last = (k == c.hidden);
     const AT* W = Wbase + c.w_off[k];
+    PreBf16 pre_next{};
+    if constexpr (sizeof(AT) == 2) {
+      if (!last)
+        pre_next = prefetch_bf16<NWAVES>((const bf16*)Wbase + c.w_off[k + 1], c.fan_in[k + 1], c.fan_in[k + 1],
+                                         c.fan_out[k + 1]);
+    }
+    const PreBf16* pp = sizeof(AT) == 2 ? &pre : nullptr;
     if (last) {
       gemm_tile<M, NWAVES, AT>(cur, ldc, c.fan_in[k], W, c.fan_in[k], c.fan_out[k],
-                               [&](int m, int col, f32x4 v) { *(f32x4*)(z + (size_t)m * ldz + col) = v; });
+                               [&](int m, int col, f32x4 v) { *(f32x4*)(z + (size_t)m * ldz + col) = v; }, pp);
     } else {
-      gemm_tile<M, NWAVES, AT>(cur, ldc, c.fan_in[k], W, c.fan_in[k], c.fan_out[k], [&](int m, int col, f32x4 v) {
+      gemm_tile<M, NWAVES, AT>(
+          cur, ldc, c.fan_in[k], W, c.fan_in[k], c.fan_out[k],
+          [&](int m, int col, f32x4 v) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.0f);
-        store4<AT>(nxt + (size_t)m * ldn + col, v);
-        keep(k, m, col, v);
-      });
+            for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.0f);
+            store4<AT>(nxt + (size_t)m * ldn + col, v);
+            keep(k, m, col, v);
+          },
+          pp);
     }
+    pre = pre_next;
     __syncthreads();
     AT* t = cur;
     cur = nxt;
@@ -248,8 +294,8 @@ __device__ inline void mlp_forward_tile_keep(const DevCfg& c, const AT* Wbase, A
 
 template <int M, int NWAVES, typename AT>
 __device__ inline void mlp_forward_tile(const DevCfg& c, const AT* Wbase, AT* act0, int ld0, AT* act1, int ld1,
-                                        float* z, int ldz) {
-  mlp_forward_tile_keep<M, NWAVES, AT>(c, Wbase, act0, ld0, act1, ld1, z, ldz, [](int, int, int, f32x4) {});
+                                        float* z, int ldz, const PreBf16* pre0 = nullptr) {
+  mlp_forward_tile_keep<M, NWAVES, AT>(c, Wbase, act0, ld0, act1, ld1, z, ldz, [](int, int, int, f32x4) {}, pre0);
 }
 
 }  // namespace nbvh
