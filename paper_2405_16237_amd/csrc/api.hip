@@ -22,6 +22,7 @@ struct nbvh_ctx {
   nbvh::Profiler* prof;
   nbvh_tuning tune;
   bool fp8_ready;  // FP8 weights and scales in aux match the current parameters
+  int tree_depth;  // inner levels of the N-BVH (traversal stack entries)
 };
 
 namespace nbvh {
@@ -219,6 +220,7 @@ static LaunchCtx make_launch(const nbvh_ctx* ctx, void* stream) {
   L.grad = ctx->p.grad_dev;
   L.aux = ctx->p.aux_dev;
   L.fp8 = ctx->cfg.precision == NBVH_FP8;
+  L.stack_depth = ctx->tree_depth > 0 ? ctx->tree_depth : 1;
   L.n_cu = ctx->n_cu;
   L.w_hit = ctx->cfg.w_hit;
   L.w_t = ctx->cfg.w_t;
@@ -236,7 +238,7 @@ static LaunchCtx make_launch(const nbvh_ctx* ctx, void* stream) {
 
 // query workspace carve-up
 struct QueryLayout {
-  size_t offsets, counts, active, sums, misc, segs, total;
+  size_t offsets, counts, active, sums, misc, staging, segs, total;
 };
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -254,6 +256,8 @@ static QueryLayout query_layout(uint64_t n_rays, uint64_t cap) {
   off = a256(off + (n_rays / 1024 + 2) * 4);
   Q.misc = off;
   off = a256(off + 16 * 4);
+  Q.staging = off;
+  off = a256(off + traverse_staging_bytes(n_rays));
   Q.segs = off;
   off = a256(off + cap * sizeof(nbvh_segment));
   Q.total = off;
@@ -347,6 +351,7 @@ nbvh_status nbvh_build(const nbvh_config* cfg, const float* leaf_boxes_host, uin
   }
   nbvh_ctx* ctx = new nbvh_ctx;
   memset(ctx, 0, sizeof(*ctx));
+  ctx->tree_depth = B.max_depth;
   ctx->cfg = *cfg;
   ctx->dev = d;
   ctx->n_leaves = n_leaves;
@@ -430,7 +435,7 @@ nbvh_status nbvh_traverse(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, 
   char* w = (char*)ws;
   uint32_t* misc = (uint32_t*)(w + Q.misc);
   return launch_traverse(L, rays, (uint32_t)n_rays, seg_offsets, segs, seg_capacity, nullptr, nullptr, nullptr,
-                         (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12);
+                         (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12, (float*)(w + Q.staging));
 }
 
 nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbvh_hit* hits, uint64_t seg_capacity,
@@ -451,7 +456,7 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbv
   uint32_t* misc = (uint32_t*)(w + Q.misc);
   nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
   s = launch_traverse(L, rays, (uint32_t)n_rays, offsets, segs, seg_capacity, hits, (uint32_t*)(w + Q.active), misc + 0,
-                      (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12);
+                      (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12, (float*)(w + Q.staging));
   if (s != NBVH_OK) return s;
   return launch_query_eval(L, rays, offsets, segs, (const uint32_t*)(w + Q.active), misc + 0, misc + 1, hits,
                            (uint32_t)n_rays, seg_capacity);
@@ -706,7 +711,8 @@ nbvh_status nbvh_batch_query(nbvh_batch* b, const nbvh_ray* rays, uint64_t n_ray
     nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
     nbvh_status s = launch_traverse(Ls[k], rays, (uint32_t)n_rays, offsets, segs, seg_capacity,
                                     per_obj + (size_t)k * n_rays, (uint32_t*)(w + Q.active), misc + 0,
-                                    (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12);
+                                    (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12,
+                                    (float*)(w + Q.staging));
     if (s != NBVH_OK) return s;
     offs[k] = offsets;
     sg[k] = segs;

@@ -58,10 +58,13 @@ __device__ inline bool slab(const RayPre& R, const float lo[3], const float hi[3
   return ok && (tn <= tf);
 }
 
-// Walk the tree; Emit(leaf, t0, t1) is called for every leaf crossed.
+// Walk the tree; Emit(leaf, t0, t1) is called for every leaf crossed. The
+// per-lane stack lives in LDS, entry i of this lane at stk[i * stride]
+// (lane-contiguous, so a wave's pushes and pops touch consecutive words);
+// it needs as many entries as the tree has inner levels.
 template <typename Emit>
-__device__ inline void walk(const Node* __restrict__ nodes, const RayPre& R, Emit emit) {
-  int32_t stack[kMaxDepth];
+__device__ inline void walk(const Node* __restrict__ nodes, const RayPre& R, Emit emit, int32_t* stk,
+                            uint32_t stride) {
   int sp = 0;
   int32_t node = 0;
   while (true) {
@@ -86,10 +89,10 @@ __device__ inline void walk(const Node* __restrict__ nodes, const RayPre& R, Emi
       } else {
         // both inner children: go to the nearer one first
         if (b0 < a0) {
-          stack[sp++] = next;
+          stk[(sp++) * stride] = next;
           next = c1;
         } else {
-          stack[sp++] = c1;
+          stk[(sp++) * stride] = c1;
         }
       }
     }
@@ -97,23 +100,57 @@ __device__ inline void walk(const Node* __restrict__ nodes, const RayPre& R, Emi
       node = next;
     } else {
       if (sp == 0) break;
-      node = stack[--sp];
+      node = stk[(--sp) * stride];
     }
   }
 }
 
+// Staged runs are plane-major: record i of ray r is (leaf, t0, t1) at
+// planes 3i, 3i+1, 3i+2 of n_rays floats each, so that neighbouring rays
+// (lanes) touch neighbouring words. Insert (leaf, t0, t1) into ray r's
+// sorted run of k records (order (t0, leaf id)).
+__device__ inline void insert_staged(float* st, size_t plane, uint32_t k, int32_t leaf, float t0, float t1) {
+  uint32_t j = k;
+  while (j > 0) {
+    const float p0 = st[(3 * (j - 1) + 1) * plane];
+    const uint32_t pl = __float_as_uint(st[(3 * (j - 1)) * plane]);
+    if (p0 > t0 || (p0 == t0 && pl > (uint32_t)leaf)) {
+      st[(3 * j) * plane] = __uint_as_float(pl);
+      st[(3 * j + 1) * plane] = p0;
+      st[(3 * j + 2) * plane] = st[(3 * (j - 1) + 2) * plane];
+      --j;
+    } else {
+      break;
+    }
+  }
+  st[(3 * j) * plane] = __uint_as_float((uint32_t)leaf);
+  st[(3 * j + 1) * plane] = t0;
+  st[(3 * j + 2) * plane] = t1;
+}
+
 // counts[r] = leaves crossed. If `hits` is given (full query), rays with no
 // segment get their miss record here and rays with segments are appended to
-// `active` (wave-aggregated atomic).
+// `active` (wave-aggregated atomic). If `staging` is given, the first
+// kStage segments of ray r are also kept there, sorted, so that the
+// compaction after the scan need not walk the tree again.
+constexpr uint32_t kStage = 12;
 __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
                                                         uint32_t n_rays, uint32_t* __restrict__ counts,
                                                         nbvh_hit* __restrict__ hits, uint32_t* __restrict__ active,
-                                                        uint32_t* __restrict__ n_active) {
+                                                        uint32_t* __restrict__ n_active, float* __restrict__ staging) {
+  extern __shared__ int32_t s_stack[];
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t cnt = 0;
   if (r < n_rays) {
     RayPre R = load_ray(rays, r);
-    walk(nodes, R, [&](int32_t, float, float) { ++cnt; });
+    float* run = staging ? staging + r : nullptr;
+    walk(
+        nodes, R,
+        [&](int32_t leaf, float t0, float t1) {
+          if (run && cnt < kStage) insert_staged(run, n_rays, cnt, leaf, t0, t1);
+          ++cnt;
+        },
+        s_stack + threadIdx.x, blockDim.x);
     counts[r] = cnt;
     if (hits && cnt == 0) {
       float4* h = (float4*)(hits + r);
@@ -141,6 +178,7 @@ __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__
 __global__ __launch_bounds__(256) void k_traverse_fill(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
                                                        uint32_t n_rays, const uint32_t* __restrict__ offsets,
                                                        nbvh_segment* __restrict__ segs, uint64_t capacity) {
+  extern __shared__ int32_t s_stack[];
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_rays) return;
   if ((uint64_t)offsets[n_rays] > capacity) return;  // overflow flagged by the scan
@@ -148,21 +186,66 @@ __global__ __launch_bounds__(256) void k_traverse_fill(const Node* __restrict__ 
   if (beg == end) return;
   RayPre R = load_ray(rays, r);
   uint32_t k = beg;
-  walk(nodes, R, [&](int32_t leaf, float t0, float t1) {
-    // insertion into the sorted run [beg, k)
-    uint32_t j = k;
-    while (j > beg) {
-      nbvh_segment prev = segs[j - 1];
-      if (prev.t0 > t0 || (prev.t0 == t0 && prev.leaf > (uint32_t)leaf)) {
-        segs[j] = prev;
-        --j;
-      } else {
-        break;
-      }
-    }
-    segs[j] = nbvh_segment{r, (uint32_t)leaf, t0, t1};
-    ++k;
-  });
+  walk(
+      nodes, R,
+      [&](int32_t leaf, float t0, float t1) {
+        // insertion into the sorted run [beg, k)
+        uint32_t j = k;
+        while (j > beg) {
+          nbvh_segment prev = segs[j - 1];
+          if (prev.t0 > t0 || (prev.t0 == t0 && prev.leaf > (uint32_t)leaf)) {
+            segs[j] = prev;
+            --j;
+          } else {
+            break;
+          }
+        }
+        segs[j] = nbvh_segment{r, (uint32_t)leaf, t0, t1};
+        ++k;
+      },
+      s_stack + threadIdx.x, blockDim.x);
+}
+
+// Compaction from the staging runs (rays with more than kStage segments walk
+// the tree again, as k_traverse_fill does).
+__global__ __launch_bounds__(256) void k_traverse_compact(const Node* __restrict__ nodes,
+                                                          const nbvh_ray* __restrict__ rays, uint32_t n_rays,
+                                                          const uint32_t* __restrict__ offsets,
+                                                          const float* __restrict__ staging,
+                                                          nbvh_segment* __restrict__ segs, uint64_t capacity) {
+  extern __shared__ int32_t s_stack[];
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rays) return;
+  if ((uint64_t)offsets[n_rays] > capacity) return;  // overflow flagged by the scan
+  const uint32_t beg = offsets[r], end = offsets[r + 1];
+  if (beg == end) return;
+  if (end - beg <= kStage) {
+    const float* run = staging + r;
+    const size_t plane = n_rays;
+    for (uint32_t i = 0; i < end - beg; ++i)
+      segs[beg + i] = nbvh_segment{r, __float_as_uint(run[(3 * i) * plane]), run[(3 * i + 1) * plane],
+                                   run[(3 * i + 2) * plane]};
+    return;
+  }
+  RayPre R = load_ray(rays, r);
+  uint32_t k = beg;
+  walk(
+      nodes, R,
+      [&](int32_t leaf, float t0, float t1) {
+        uint32_t j = k;
+        while (j > beg) {
+          nbvh_segment prev = segs[j - 1];
+          if (prev.t0 > t0 || (prev.t0 == t0 && prev.leaf > (uint32_t)leaf)) {
+            segs[j] = prev;
+            --j;
+          } else {
+            break;
+          }
+        }
+        segs[j] = nbvh_segment{r, (uint32_t)leaf, t0, t1};
+        ++k;
+      },
+      s_stack + threadIdx.x, blockDim.x);
 }
 
 // Training-ray selection (Sec. 5.3, "Ray distribution"): each ray trains only
@@ -175,6 +258,7 @@ __global__ __launch_bounds__(256) void k_first_hits(const Node* __restrict__ nod
                                                     const float* __restrict__ accept, nbvh_probe* __restrict__ probes,
                                                     uint32_t* __restrict__ leaf_out, uint32_t* __restrict__ n_out,
                                                     uint32_t* __restrict__ leaf_hits) {
+  extern __shared__ int32_t s_stack[];
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   bool take = false;
   int32_t best = -1;
@@ -182,14 +266,17 @@ __global__ __launch_bounds__(256) void k_first_hits(const Node* __restrict__ nod
   RayPre R;
   if (r < n) {
     R = load_ray(rays, r);
-    walk(nodes, R, [&](int32_t leaf, float t0, float t1) {
-      if (leaf_hits) atomicAdd(&leaf_hits[leaf], 1u);
-      if (best < 0 || t0 < b0 || (t0 == b0 && leaf < best)) {
-        best = leaf;
-        b0 = t0;
-        b1 = t1;
-      }
-    });
+    walk(
+        nodes, R,
+        [&](int32_t leaf, float t0, float t1) {
+          if (leaf_hits) atomicAdd(&leaf_hits[leaf], 1u);
+          if (best < 0 || t0 < b0 || (t0 == b0 && leaf < best)) {
+            best = leaf;
+            b0 = t0;
+            b1 = t1;
+          }
+        },
+        s_stack + threadIdx.x, blockDim.x);
     take = best >= 0 && u[r] < accept[best];
   }
   const uint64_t mask = __ballot(take);
@@ -209,12 +296,15 @@ __global__ __launch_bounds__(256) void k_first_hits(const Node* __restrict__ nod
   }
 }
 
+// LDS for the walk stacks of a 256-thread workgroup
+static size_t stack_lds(const LaunchCtx& L) { return (size_t)256 * (L.stack_depth > 0 ? L.stack_depth : 1) * 4; }
+
 nbvh_status launch_first_hits(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n, const float* u,
                               const float* accept, nbvh_probe* probes, uint32_t* leaf_out, uint32_t* n_out,
                               uint32_t* leaf_hits) {
   k_zero_u32<<<1, 64, 0, L.stream>>>(n_out, 1);
   if (n > 0)
-    k_first_hits<<<(n + 255) / 256, 256, 0, L.stream>>>(L.nodes, rays, n, u, accept, probes, leaf_out, n_out,
+    k_first_hits<<<(n + 255) / 256, 256, stack_lds(L), L.stream>>>(L.nodes, rays, n, u, accept, probes, leaf_out, n_out,
                                                         leaf_hits);
   return check_launch("first_hits");
 }
@@ -313,24 +403,31 @@ nbvh_status launch_exclusive_scan(hipStream_t s, const uint32_t* in, uint32_t n,
   return check_launch("scan");
 }
 
+size_t traverse_staging_bytes(uint64_t n_rays) { return (size_t)n_rays * kStage * 3 * sizeof(float); }
+
 nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n_rays, uint32_t* offsets,
                             nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
                             uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
-                            uint32_t* scratch_total) {
+                            uint32_t* scratch_total, float* staging) {
   ProfScope ps(L.prof, NBVH_K_TRAVERSE, L.stream);
   const int grid = (int)((n_rays + 255) / 256);
   if (n_active) {
     k_zero_u32<<<1, 64, 0, L.stream>>>(n_active, 9);  // n_active and the query's 8 ray-queue counters
   }
   if (n_rays > 0)
-    k_traverse_count<<<grid, 256, 0, L.stream>>>(L.nodes, rays, n_rays, scratch_counts, hits, active, n_active);
+    k_traverse_count<<<grid, 256, stack_lds(L), L.stream>>>(L.nodes, rays, n_rays, scratch_counts, hits, active, n_active,
+                                                 segs ? staging : nullptr);
   const uint32_t n_tiles = (n_rays + kScanTile - 1) / kScanTile;
   if (n_rays > 0) k_scan_tiles<<<n_tiles, 256, 0, L.stream>>>(scratch_counts, n_rays, offsets, scratch_sums);
   k_scan_sums<<<1, 1024, 0, L.stream>>>(scratch_sums, n_tiles, scratch_total);
   k_scan_add<<<grid > 0 ? grid : 1, 256, 0, L.stream>>>(offsets, n_rays, scratch_sums, scratch_total, capacity,
                                                         L.state);
-  if (segs && n_rays > 0)
-    k_traverse_fill<<<grid, 256, 0, L.stream>>>(L.nodes, rays, n_rays, offsets, segs, capacity);
+  if (segs && n_rays > 0) {
+    if (staging)
+      k_traverse_compact<<<grid, 256, stack_lds(L), L.stream>>>(L.nodes, rays, n_rays, offsets, staging, segs, capacity);
+    else
+      k_traverse_fill<<<grid, 256, stack_lds(L), L.stream>>>(L.nodes, rays, n_rays, offsets, segs, capacity);
+  }
   return check_launch("traverse");
 }
 

@@ -62,6 +62,7 @@ struct LaunchCtx {
   float* grad;
   void* aux;  // transposed weight copies: fp32 [n_wt] then bf16 [n_wt]; FP8 block
   bool fp8;   // queries and forward run the MLP in FP8 (weights and scales in aux)
+  int stack_depth;  // inner levels of the N-BVH: entries of a traversal stack
   int n_cu;
   // training hyper-parameters
   float w_hit, w_t, w_normal, w_albedo;
@@ -76,10 +77,13 @@ void set_error(const char* fmt, ...);
 __global__ void k_zero_u32(uint32_t* p, uint32_t n);
 __global__ void k_zero_f32(float* p, uint64_t n);
 
+// `staging` (optional, traverse_staging_bytes(n_rays)): sorted per-ray runs
+// kept by the counting pass so that the fill copies instead of walking again.
+size_t traverse_staging_bytes(uint64_t n_rays);
 nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n_rays, uint32_t* offsets,
                             nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
                             uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
-                            uint32_t* scratch_total);
+                            uint32_t* scratch_total, float* staging);
 
 nbvh_status launch_query_eval(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
                               const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,

@@ -112,6 +112,24 @@ def test_traverse_tiny_scenes(lib):
         _check_traverse(lib, rays, boxes, boxes[:, :3].min(0), np.float32(4.0), net)
 
 
+def test_traverse_many_overlapping_leaves(lib):
+    """Rays crossing up to 40 leaves: longer runs than the counting pass
+    keeps sorted per ray, so the fill walks the tree again for them."""
+    rng = np.random.default_rng(6)
+    lo = rng.uniform(-1.0, -0.2, (40, 3))
+    hi = rng.uniform(0.2, 1.0, (40, 3))
+    boxes = np.concatenate([lo, hi], 1).astype(np.float32)
+    n = 4000 + 17
+    rays = np.zeros((n, 8), np.float32)
+    rays[:, 0:3] = rng.uniform(-3, 3, (n, 3))
+    d = -rays[:, 0:3] + rng.uniform(-0.3, 0.3, (n, 3))
+    rays[:, 4:7] = d / np.linalg.norm(d, axis=1, keepdims=True)
+    rays[:, 7] = np.inf
+    _say("traverse 40 overlapping leaves")
+    total = _check_traverse(lib, rays, boxes, boxes[:, :3].min(0), np.float32(4.0), configs.C1_NET)
+    assert total > 20 * n
+
+
 def test_traverse_capacity_flag(lib, c1):
     sc, rays = c1
     m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="fp32")
