@@ -25,7 +25,7 @@ namespace nbvh {
 
 constexpr int kTM = 64;
 constexpr int kGPad = 32;  // gradient rows of the output layer padded to 32
-constexpr uint32_t kBinChunk = 16384;  // binned scatter: parameters (fp32) per bin
+constexpr uint32_t kBinChunk = 8192;   // binned scatter: parameters per bin (64-bit accumulators in LDS)
 constexpr int kBinWgs = 512;           // binned scatter: workgroups of the count / write passes
 
 __host__ __device__ inline int fan_out_pad(const DevCfg& c, int k) {
@@ -35,7 +35,7 @@ __host__ __device__ inline int fan_out_pad(const DevCfg& c, int k) {
 // workspace carve-up (offsets in bytes)
 struct TrainLayout {
   size_t hT[kMaxLayers], gT[kMaxLayers];
-  size_t duT, wpart, loss_part, total;
+  size_t duT, wpart, loss_part, gmax, total;
   int nsplit;
   uint32_t n_tiles;
   // scatter: levels [0, n_lds) in LDS, [n_lds, hash_end) through the
@@ -70,6 +70,8 @@ static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_bat
   T.n_tiles = (uint32_t)(B / kTM);
   T.loss_part = off;
   off = align256(off + (size_t)T.n_tiles * 4 * 4);
+  T.gmax = off;
+  off = align256(off + 4);
   const int budget_kb = tune.scatter_lds_kb < 0 ? 0 : (tune.scatter_lds_kb > 144 ? 144 : tune.scatter_lds_kb);
   T.lds_floats = 0;
   T.n_lds = budget_kb > 0 ? coarse_lds_levels(c, (size_t)budget_kb * 1024, &T.lds_floats) : 0;
@@ -118,7 +120,8 @@ struct TrainPtrs {
   void* gT[kMaxLayers];
   float* duT;
   float* loss_part;
-  uint64_t ldb;  // batch stride of the feature-major buffers
+  uint32_t* gmax;  // bits of max |dL/du| over the batch (+inf bits if a value is not finite)
+  uint64_t ldb;    // batch stride of the feature-major buffers
 };
 
 template <typename AT>
@@ -279,11 +282,23 @@ __global__ __launch_bounds__(64 * kTWaves) __attribute__((amdgpu_waves_per_eu(4)
       which ^= 1;
     } else {
       float* du = P.duT;
+      float gm = 0.0f;
+      bool bad = false;
       gemm_tile<kTM, kTWaves, AT>(gcur, ldcur, K, Wt, ldw, c.fan_in[0], [&](int m, int col, f32x4 v) {
         const bool ok = s_valid[m] != 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) du[(size_t)(col + i) * ldb + base + m] = ok ? v[i] : 0.0f;
+        for (int i = 0; i < 4; ++i) {
+          const float x = ok ? v[i] : 0.0f;
+          du[(size_t)(col + i) * ldb + base + m] = x;
+          gm = fmaxf(gm, fabsf(x));
+          bad = bad || !isfinite(x);
+        }
       });
+      // the scatter's fixed-point scale comes from the largest |dL/du|
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) gm = fmaxf(gm, __shfl_xor(gm, off));
+      const bool any_bad = __ballot(bad) != 0ull;
+      if ((threadIdx.x & 63) == 0) atomicMax(P.gmax, any_bad ? 0x7f800000u : __float_as_uint(gm));
     }
   }
 }
@@ -522,12 +537,38 @@ __global__ __launch_bounds__(256) void k_scatter_pairs(DevCfg c, int l_begin, co
 // open-addressing table keyed by parameter index; the table is then flushed
 // with one global atomic per distinct entry and feature. A record that finds
 // no slot within kHashProbe steps goes straight to global memory.
+// Fixed-point accumulation. On this hardware LDS float atomics run at a
+// fraction of the rate of LDS integer atomics, so the scatter routes that sum
+// in LDS add 64-bit integers: a contribution v becomes round(v * 2^e). With
+// g = max |dL/du| over the batch, a contribution (a run of at most S samples
+// times trilinear weights <= 1) is below S g, so n_terms of them stay below
+// 2^62 when e = 62 - ceil(log2 n_terms) - ceil(log2 S) - E, g < 2^E. The
+// rounding error is at most 2^-(e+1) per term, 2^-38 of g or less here.
+// A non-finite g flags the step (the optimiser then skips it) and the
+// route adds nothing.
+__device__ inline int ceil_log2(uint32_t x) { return x <= 1u ? 0 : 32 - __clz(x - 1u); }
+
+__device__ inline bool fixed_exponent(const uint32_t* gmax, uint32_t log2_terms, int S, DevState* state, int* e) {
+  const float g = __uint_as_float(*gmax);
+  if (!(g <= 3.0e38f)) {
+    if (threadIdx.x == 0) atomicOr(&state->nonfinite_pending, 1u);
+    return false;
+  }
+  int E = 0;
+  if (g > 0.0f) (void)frexpf(g, &E);  // g < 2^E
+  *e = 62 - (int)log2_terms - ceil_log2((uint32_t)S) - E;
+  return true;
+}
+
+__device__ inline long long to_fixed(float v, int e) { return __float2ll_rn(ldexpf(v, e)); }
+__device__ inline float from_fixed(long long q, int e) { return ldexpf((float)q, -e); }
+
 constexpr int kHashTile = 256;
 constexpr int kHashProbe = 16;
 constexpr uint32_t kHashEmpty = 0xffffffffu;
 template <int F>
 struct HashSlots {
-  static constexpr int log2n = F == 2 ? 12 : 11;  // 48 KiB of LDS either way
+  static constexpr int log2n = F == 2 ? 12 : 11;  // 80 KiB of LDS either way
   static constexpr int n = 1 << log2n;
 };
 
@@ -535,14 +576,18 @@ template <int F>
 __global__ __launch_bounds__(kHashTile) void k_scatter_hash(DevCfg c, int l_begin, int l_end,
                                                             const nbvh_probe* __restrict__ probes, uint32_t n,
                                                             const float* __restrict__ duT, uint64_t ldb,
+                                                            const uint32_t* __restrict__ gmax, DevState* state,
                                                             float* __restrict__ grad) {
   constexpr int NS = HashSlots<F>::n;
   __shared__ uint32_t keys[NS];
-  __shared__ float vals[NS * F];
+  __shared__ long long vals[NS * F];
+  int e;
+  // per entry: at most kHashTile probes x S runs
+  if (!fixed_exponent(gmax, ceil_log2((uint32_t)(kHashTile * c.n_samples)), c.n_samples, state, &e)) return;
   for (int i = threadIdx.x; i < NS; i += kHashTile) {
     keys[i] = kHashEmpty;
 #pragma unroll
-    for (int f = 0; f < F; ++f) vals[i * F + f] = 0.0f;
+    for (int f = 0; f < F; ++f) vals[i * F + f] = 0ll;
   }
   __syncthreads();
   const uint32_t p = blockIdx.x * kHashTile + threadIdx.x;
@@ -558,7 +603,8 @@ __global__ __launch_bounds__(kHashTile) void k_scatter_hash(DevCfg c, int l_begi
           const uint32_t k = atomicCAS(&keys[h], kHashEmpty, idx);
           if (k == kHashEmpty || k == idx) {
 #pragma unroll
-            for (int f = 0; f < F; ++f) atomicAdd(&vals[h * F + f], v[f]);
+            for (int f = 0; f < F; ++f)
+              atomicAdd((unsigned long long*)&vals[h * F + f], (unsigned long long)to_fixed(v[f], e));
             return;
           }
           h = (h + 1) & (NS - 1);
@@ -573,9 +619,9 @@ __global__ __launch_bounds__(kHashTile) void k_scatter_hash(DevCfg c, int l_begi
       const int slot = i / F, f = i - slot * F;
       const uint32_t k = keys[slot];
       if (k != kHashEmpty) {
-        const float v = vals[i];
-        if (v != 0.0f) unsafeAtomicAdd(grad + k + f, v);
-        vals[i] = 0.0f;
+        const long long q = vals[i];
+        if (q != 0ll) unsafeAtomicAdd(grad + k + f, from_fixed(q, e));
+        vals[i] = 0ll;
       }
     }
     __syncthreads();
@@ -699,35 +745,56 @@ __global__ __launch_bounds__(256) void k_bin_write(DevCfg c, BinArgs A, const nb
   }
 }
 
-// pass 3: one workgroup per bin accumulates in LDS and updates its chunk
+// pass 3: one workgroup per bin accumulates in LDS (64-bit fixed point) and
+// updates its chunk with plain read-modify-writes
 template <int F>
 __global__ __launch_bounds__(1024) void k_bin_reduce(BinArgs A, const uint32_t* __restrict__ offsets, uint32_t n_wgs,
                                                      const uint16_t* __restrict__ rec_idx,
                                                      const float* __restrict__ rec_val, uint64_t n_table,
-                                                     float* __restrict__ grad) {
-  __shared__ float acc[kBinChunk];
+                                                     const uint32_t* __restrict__ gmax, uint32_t log2_terms, int S,
+                                                     DevState* state, float* __restrict__ grad) {
+  __shared__ long long acc[kBinChunk];
+  int e;
+  if (!fixed_exponent(gmax, log2_terms, S, state, &e)) return;
   const uint32_t bin = blockIdx.x;
-  for (uint32_t i = threadIdx.x; i < kBinChunk; i += blockDim.x) acc[i] = 0.0f;
+  for (uint32_t i = threadIdx.x; i < kBinChunk; i += blockDim.x) acc[i] = 0ll;
   __syncthreads();
   const uint32_t r0 = offsets[(size_t)bin * n_wgs];
   const uint32_t r1 = offsets[(size_t)(bin + 1) * n_wgs];  // offsets[n_bins * n_wgs] is the total
-  for (uint32_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const uint32_t e = rec_idx[r];
+  // kUnroll records per thread in flight before their LDS atomics
+  constexpr int kUnroll = 4;
+  for (uint32_t r = r0 + threadIdx.x; r < r1; r += blockDim.x * kUnroll) {
+    uint32_t ix[kUnroll];
+    float v[kUnroll][F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) atomicAdd(&acc[e + f], rec_val[(size_t)r * F + f]);
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint32_t rr = r + u * blockDim.x;
+      const bool ok = rr < r1;
+      ix[u] = ok ? (uint32_t)rec_idx[rr] : 0xffffffffu;
+#pragma unroll
+      for (int f = 0; f < F; ++f) v[u][f] = ok ? rec_val[(size_t)rr * F + f] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (ix[u] != 0xffffffffu) {
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+          atomicAdd((unsigned long long*)&acc[ix[u] + f], (unsigned long long)to_fixed(v[u][f], e));
+      }
+    }
   }
   __syncthreads();
   const uint64_t g0 = (uint64_t)A.off0 + (uint64_t)bin * kBinChunk;
   const uint32_t len = (uint32_t)min((uint64_t)kBinChunk, n_table - g0);
   for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-    const float v = acc[i];
-    if (v != 0.0f) grad[g0 + i] += v;
+    const long long q = acc[i];
+    if (q != 0ll) grad[g0 + i] += from_fixed(q, e);
   }
 }
 
 template <int F>
 static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char* w, const nbvh_probe* probes,
-                                  uint32_t n, const float* duT, uint64_t ldb) {
+                                  uint32_t n, const float* duT, uint64_t ldb, const uint32_t* gmax) {
   const DevCfg& c = L.cfg;
   {
     ProfScope ps(L.prof, NBVH_K_SCATTER, L.stream);
@@ -738,7 +805,8 @@ static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char
     }
     if (T.hash_end > T.n_lds)
       k_scatter_hash<F><<<(n + kHashTile - 1) / kHashTile, kHashTile, 0, L.stream>>>(c, T.n_lds, T.hash_end, probes,
-                                                                                   n, duT, ldb, L.grad);
+                                                                                   n, duT, ldb, gmax, L.state,
+                                                                                   L.grad);
     if (T.hash_end >= c.n_levels) return check_launch("scatter");
     if (T.n_bins == 0) {
       const uint64_t threads = (uint64_t)n * (c.n_levels - T.hash_end) * 2 * F;
@@ -769,8 +837,11 @@ static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char
   }
   {
     ProfScope ps(L.prof, NBVH_K_SCATTER_REDUCE, L.stream);
+    // per entry: at most n probes x S runs
+    const uint32_t log2_terms = (uint32_t)(32 - __builtin_clz(n * (uint32_t)c.n_samples - 1u));
     k_bin_reduce<F><<<T.n_bins, 1024, 0, L.stream>>>(A, offsets, kBinWgs, (const uint16_t*)(w + T.rec_idx),
-                                                     (const float*)(w + T.rec_val), c.n_table, L.grad);
+                                                     (const float*)(w + T.rec_val), c.n_table, gmax, log2_terms,
+                                                     c.n_samples, L.state, L.grad);
   }
   return check_launch("scatter");
 }
@@ -1002,6 +1073,7 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
   }
   P.duT = (float*)(w + T.duT);
   P.loss_part = (float*)(w + T.loss_part);
+  P.gmax = (uint32_t*)(w + T.gmax);
   const uint32_t kb = T.n_tiles * kTM;  // padded batch
   P.ldb = kb;
   const AT* W = (sizeof(AT) == 2) ? (const AT*)L.params_lp : (const AT*)L.params;
@@ -1014,6 +1086,7 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
   }
   {
     ProfScope ps(L.prof, NBVH_K_TRAIN_TILE, L.stream);
+    k_zero_u32<<<1, 64, 0, L.stream>>>(P.gmax, 1);
     const int nw = L.tune.train_waves == 4 ? 4 : 8;
 #define NBVH_TT(LAB, NW)                                                                                  \
   do {                                                                                                    \
@@ -1042,7 +1115,7 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
     const uint64_t span = c.n_params - c.w_off[0];
     k_wgrad_reduce<<<(uint32_t)((span + 255) / 256), 256, 0, L.stream>>>(c, wpart, T.nsplit, L.grad, L.state);
   }
-  nbvh_status s = launch_scatter<F>(L, T, w, probes, n, P.duT, kb);
+  nbvh_status s = launch_scatter<F>(L, T, w, probes, n, P.duT, kb, P.gmax);
   if (s != NBVH_OK) return s;
   return check_launch("train");
 }
