@@ -67,10 +67,13 @@ def hit_error(hits, gt, diag):
     agree = float((pred == truth).mean())
     both = pred & truth
     dep = np.abs(hits[both, 0].astype(np.float64) - gt["t"][both]) / diag
-    return dict(hit_accuracy=agree, hit_error_pct=100.0 * (1.0 - agree),
-                depth_err_mean=float(dep.mean()) if both.any() else None,
-                depth_err_p99=float(np.quantile(dep, 0.99)) if both.any() else None,
-                predicted_hits=int(pred.sum()), true_hits=int(truth.sum()))
+    out = dict(hit_accuracy=agree, hit_error_pct=100.0 * (1.0 - agree),
+               depth_err_mean=float(dep.mean()) if both.any() else None,
+               depth_err_p99=float(np.quantile(dep, 0.99)) if both.any() else None,
+               predicted_hits=int(pred.sum()), true_hits=int(truth.sum()))
+    if "albedo" in gt and both.any():
+        out["albedo_err_mean"] = float(np.abs(hits[both, 4:7].astype(np.float64) - gt["albedo"][both]).mean())
+    return out
 
 
 class Workload:

@@ -133,7 +133,7 @@ typedef struct {
   int32_t precision; /* nbvh_precision */
   float scene_lo[3];
   float scene_side;
-  float w_hit, w_t, w_normal, w_albedo;
+  float w_hit, w_t, w_normal, w_albedo; /* loss weights (Sec. 5.2: 2, 2, 1, 1); albedo only with n_out >= 8 */
   float lr, beta1, beta2, eps, loss_scale;
 } nbvh_config;
 
@@ -164,7 +164,8 @@ typedef struct {
   int64_t skipped;     /* steps skipped because of non-finite gradients */
   float loss_scale;    /* current loss scale */
   uint32_t flags;      /* NBVH_FLAG_* bits, sticky until nbvh_clear_flags */
-  float last_loss[4];  /* last train step: total, BCE, distance L1, normal L1 (unweighted) */
+  float last_loss[4];  /* last train step: total, BCE, distance L1, normal L1 (unweighted; the
+                          albedo term only enters the total) */
   uint64_t last_n_segments; /* segments produced by the last traversal */
   uint64_t n_evaluated;     /* segments evaluated by queries since the last nbvh_reset_optimizer */
 } nbvh_state_host;
@@ -306,7 +307,7 @@ nbvh_status nbvh_first_hits(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_
 
 /* Per-leaf training loss (Sec. 5.3, "Node error"): runs the network on the n
  * segments probes_dev with labels_dev and adds each segment's combined loss
- * (weights w_hit, w_t, w_normal; not divided by the batch size) to
+ * (weights w_hit, w_t, w_normal, w_albedo; not divided by the batch size) to
  * leaf_loss_dev[leaf_ids_dev[i]] (float, [n_leaves]) and one to
  * leaf_count_dev[...] (uint32). The caller clears both. Needs n * n_out
  * floats of workspace. Asynchronous; atomics make the sums' rounding order
@@ -341,9 +342,11 @@ nbvh_status nbvh_optimizer_step(nbvh_ctx* ctx, void* stream);
 
 /* One training step (Sec. 4, Sec. 5.2): forward on the probes, combined
  * loss L = (1/B) sum [w_hit BCE(z0, hit) + hit (w_t |sigmoid(z1) - tau| +
- * w_normal/3 sum |z2..4 - n|)], back-propagation into grad and an
- * optimiser step. loss_dev (nullable) receives [total, bce, dist, normal]
- * as FP32 (unweighted terms; total weighted). */
+ * w_normal/3 sum |z2..4 - n| + w_albedo/3 sum_c (a_c - alb_c)^2 / (a_c^2 + 0.01))]
+ * with a_c = sigmoid(z_{5+c}) (the relative-L2 albedo term only when
+ * n_out >= 8), back-propagation into grad and an optimiser step. loss_dev
+ * (nullable) receives [total, bce, dist, normal] as FP32 (unweighted terms;
+ * total weighted, albedo included). */
 nbvh_status nbvh_train_step(nbvh_ctx* ctx, const nbvh_probe* probes_dev, const nbvh_label* labels_dev,
                             uint64_t n, float* loss_dev, void* ws_dev, size_t ws_bytes, void* stream);
 

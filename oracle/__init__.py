@@ -60,8 +60,8 @@ def _lib():
             L.oc_mlp_params.restype = I
             L.oc_encode.argtypes = [P, P, P, I, P]
             L.oc_mlp_forward.argtypes = [P, P, P, I, P]
-            L.oc_loss.argtypes = [P, P, P, I, D, D, D, P, P]
-            L.oc_segment_loss.argtypes = [P, P, P, I, D, D, D, P]
+            L.oc_loss.argtypes = [P, P, P, I, D, D, D, D, P, P]
+            L.oc_segment_loss.argtypes = [P, P, P, I, D, D, D, D, P]
             L.oc_backward.argtypes = [P, P, P, I, P, P]
             L.oc_adam.argtypes = [I, P, P, P, P, I, D, D, D, D, D]
             L.oc_min_abs_preact.argtypes = [P, P, P, I, P]
@@ -202,7 +202,7 @@ def layer_amax(cfg, params, segs):
 
 
 # -- training ---------------------------------------------------------------------
-LOSS_WEIGHTS = (2.0, 2.0, 1.0)
+LOSS_WEIGHTS = (2.0, 2.0, 1.0, 1.0)  # visibility, distance, normal, albedo
 
 
 def loss(cfg, z, labels, weights=LOSS_WEIGHTS, with_grad=True):
@@ -211,8 +211,9 @@ def loss(cfg, z, labels, weights=LOSS_WEIGHTS, with_grad=True):
     labels = _c(labels, np.float32)
     out = np.zeros(4, dtype=np.float64)
     dz = np.zeros_like(z) if with_grad else None
-    _lib().oc_loss(ctypes.byref(cfg), _p(z), _p(labels), z.shape[0], float(weights[0]), float(weights[1]),
-                   float(weights[2]), _p(out), _p(dz))
+    w = tuple(weights) + (1.0,) * (4 - len(weights))
+    _lib().oc_loss(ctypes.byref(cfg), _p(z), _p(labels), z.shape[0], float(w[0]), float(w[1]), float(w[2]),
+                   float(w[3]), _p(out), _p(dz))
     return out, dz
 
 
@@ -221,8 +222,9 @@ def segment_loss(cfg, z, labels, weights=LOSS_WEIGHTS):
     z = _c(z, np.float64)
     labels = _c(labels, np.float32)
     out = np.zeros(z.shape[0], dtype=np.float64)
-    _lib().oc_segment_loss(ctypes.byref(cfg), _p(z), _p(labels), z.shape[0], float(weights[0]), float(weights[1]),
-                           float(weights[2]), _p(out))
+    w = tuple(weights) + (1.0,) * (4 - len(weights))
+    _lib().oc_segment_loss(ctypes.byref(cfg), _p(z), _p(labels), z.shape[0], float(w[0]), float(w[1]),
+                           float(w[2]), float(w[3]), _p(out))
     return out
 
 

@@ -382,19 +382,39 @@ void oc_layer_amax(const oc_cfg* c, const double* params, const float* segs, int
 /* Losses (Sec. 5.2): visibility is a binary cross-entropy on a sigmoid;     */
 /* the local distance (distance along the segment relative to its length,    */
 /* in [0,1]) takes an L1 loss on a sigmoid output; the normal an L1 loss on  */
-/* a linear output; both only where the label says the segment is hit.      */
-/* Combined with weights 2, 2, 1 ("Combined loss"). Means over the batch B. */
-/* labels rows: [tau, n.xyz, hit, albedo.rgb]. loss_out: total, bce, dist,   */
-/* normal (the last three unweighted). dz (optional) = dL/dz.               */
+/* a linear output; the albedo (n_out >= 8: outputs 5..7 through a sigmoid) */
+/* a relative L2 loss; all but visibility only where the label says the     */
+/* segment is hit. Combined with weights 2, 2, 1, 1 ("Combined loss").      */
+/* Means over the batch B. labels rows: [tau, n.xyz, hit, albedo.rgb].      */
+/* loss_out: total, bce, dist, normal (the last three unweighted; the       */
+/* albedo term only enters the total). dz (optional) = dL/dz.               */
+/* Relative L2 of one channel: (a_hat - a)^2 / (a_hat^2 + 0.01), mean over  */
+/* the three channels, differentiated through the denominator too.          */
 /* ------------------------------------------------------------------------ */
 static double oc_sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 static double oc_sgn(double v) { return (v > 0.0) - (v < 0.0); }
+static const double kRelEps = 0.01;
+
+static double oc_albedo_term(const double* zi, const float* lb, double* dterm /* [3] or NULL */) {
+  double s = 0.0;
+  for (int ch = 0; ch < 3; ++ch) {
+    double ah = oc_sigmoid(zi[5 + ch]), a = (double)lb[5 + ch];
+    double den = ah * ah + kRelEps;
+    s += (ah - a) * (ah - a) / den;
+    if (dterm) {
+      /* d/da_hat of (a_hat - a)^2 / (a_hat^2 + eps), times d a_hat / dz */
+      double d = (2.0 * (ah - a) * den - (ah - a) * (ah - a) * 2.0 * ah) / (den * den);
+      dterm[ch] = d * ah * (1.0 - ah) / 3.0;
+    }
+  }
+  return s / 3.0;
+}
 
 void oc_loss(const oc_cfg* c, const double* z, const float* labels, int64_t n, double w_hit, double w_t,
-             double w_n, double* loss_out, double* dz) {
+             double w_n, double w_a, double* loss_out, double* dz) {
   int no = c->n_out;
   double B = (double)n;
-  double s_bce = 0.0, s_t = 0.0, s_n = 0.0;
+  double s_bce = 0.0, s_t = 0.0, s_n = 0.0, s_a = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     const double* zi = z + (int64_t)no * i;
     const float* lb = labels + 8 * i;
@@ -407,29 +427,34 @@ void oc_loss(const oc_cfg* c, const double* z, const float* labels, int64_t n, d
     double ln = 0.0;
     for (int a = 0; a < 3; ++a) ln += fabs(zi[2 + a] - (double)lb[1 + a]);
     ln /= 3.0;
+    double da[3] = {0.0, 0.0, 0.0};
+    double la = no >= 8 ? oc_albedo_term(zi, lb, da) : 0.0;
     s_bce += bce;
     s_t += h * lt;
     s_n += h * ln;
+    s_a += h * la;
     if (dz) {
       double* g = dz + (int64_t)no * i;
       for (int o = 0; o < no; ++o) g[o] = 0.0;
       g[0] = w_hit * (oc_sigmoid(z0) - h) / B;
       g[1] = h * w_t * oc_sgn(st - tau) * st * (1.0 - st) / B;
       for (int a = 0; a < 3; ++a) g[2 + a] = h * w_n * oc_sgn(zi[2 + a] - (double)lb[1 + a]) / (3.0 * B);
+      if (no >= 8)
+        for (int ch = 0; ch < 3; ++ch) g[5 + ch] = h * w_a * da[ch] / B;
     }
   }
   loss_out[1] = s_bce / B;
   loss_out[2] = s_t / B;
   loss_out[3] = s_n / B;
-  loss_out[0] = w_hit * loss_out[1] + w_t * loss_out[2] + w_n * loss_out[3];
+  loss_out[0] = w_hit * loss_out[1] + w_t * loss_out[2] + w_n * loss_out[3] + w_a * s_a / B;
 }
 
 /* Combined loss of each segment on its own (Sec. 5.3, "Node error": the
  * training loss q of a node is taken over the segments that train it):
- * out[i] = w_hit BCE + h (w_t |sigma(z1) - tau| + w_n (1/3) sum |n_hat - n|),
- * not divided by the batch size. */
+ * out[i] = w_hit BCE + h (w_t |sigma(z1) - tau| + w_n (1/3) sum |n_hat - n|
+ * + w_a relative L2 of the albedo), not divided by the batch size. */
 void oc_segment_loss(const oc_cfg* c, const double* z, const float* labels, int64_t n, double w_hit, double w_t,
-                     double w_n, double* out) {
+                     double w_n, double w_a, double* out) {
   int no = c->n_out;
   for (int64_t i = 0; i < n; ++i) {
     const double* zi = z + (int64_t)no * i;
@@ -440,7 +465,8 @@ void oc_segment_loss(const oc_cfg* c, const double* z, const float* labels, int6
     double lt = fabs(oc_sigmoid(zi[1]) - (double)lb[0]);
     double ln = 0.0;
     for (int a = 0; a < 3; ++a) ln += fabs(zi[2 + a] - (double)lb[1 + a]);
-    out[i] = w_hit * bce + h * (w_t * lt + w_n * ln / 3.0);
+    double la = no >= 8 ? oc_albedo_term(zi, lb, NULL) : 0.0;
+    out[i] = w_hit * bce + h * (w_t * lt + w_n * ln / 3.0 + w_a * la);
   }
 }
 

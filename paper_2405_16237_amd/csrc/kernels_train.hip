@@ -129,6 +129,23 @@ __device__ inline void put(AT* p, float v) {
   p[0] = (AT)v;
 }
 
+// Albedo (outputs 5..7 through a sigmoid; Sec. 5.2 "Auxiliary data"): relative
+// L2, (a_hat - a)^2 / (a_hat^2 + 0.01) averaged over the channels, its
+// derivative taken through the denominator as well. Returns the term and
+// writes d(term)/dz for the three outputs.
+__device__ inline float albedo_term(const float* zr, const float* a, float dz[3]) {
+  float s = 0.0f;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    const float ah = sigmoidf_(zr[5 + ch]);
+    const float den = ah * ah + 0.01f;
+    const float d = ah - a[ch];
+    s += d * d / den;
+    dz[ch] = (2.0f * d * den - d * d * 2.0f * ah) / (den * den) * ah * (1.0f - ah) * (1.0f / 3.0f);
+  }
+  return s * (1.0f / 3.0f);
+}
+
 __device__ inline float bce_logits(float z, float h) {
   return fmaxf(z, 0.0f) - z * h + log1pf(__expf(-fabsf(z)));
 }
@@ -140,7 +157,7 @@ __global__ __launch_bounds__(64 * kTWaves) __attribute__((amdgpu_waves_per_eu(4)
                                                     const nbvh_label* __restrict__ labels,
                                                     const float* __restrict__ dz_in, uint32_t n, TrainPtrs P,
                                                     DevState* __restrict__ state, float w_hit, float w_t,
-                                                    float w_normal) {
+                                                    float w_normal, float w_albedo) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int ld0 = (c.n_in > c.width ? c.n_in : c.width) + Pad<AT>::v;
   const int ld1 = c.width + Pad<AT>::v;
@@ -197,7 +214,7 @@ __global__ __launch_bounds__(64 * kTWaves) __attribute__((amdgpu_waves_per_eu(4)
   // 3. loss and dL/dz (scaled) -> gz (LDS) and g_H^T (global)
   const float scale = state->loss_scale;
   const float invB = 1.0f / (float)n;
-  float l_bce = 0.f, l_t = 0.f, l_n = 0.f;
+  float l_bce = 0.f, l_t = 0.f, l_n = 0.f, l_a = 0.f;
   if (wave == 0) {
     const int m = lane;
     const bool ok = s_valid[m] != 0;
@@ -221,6 +238,12 @@ __global__ __launch_bounds__(64 * kTWaves) __attribute__((amdgpu_waves_per_eu(4)
         g[1] = h * w_t * sgnf(st - tau) * st * (1.0f - st) * sB_;
 #pragma unroll
         for (int a = 0; a < 3; ++a) g[2 + a] = h * w_normal * sgnf(zr[2 + a] - lb.n[a]) * (1.0f / 3.0f) * sB_;
+        if (c.n_out >= 8) {
+          float da[3];
+          l_a = h * albedo_term(zr, lb.albedo, da);
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) g[5 + ch] = h * w_albedo * da[ch] * sB_;
+        }
       } else {
         for (int o = 0; o < c.n_out; ++o) g[o] = dz_in[(size_t)(base + m) * c.n_out + o] * scale;
       }
@@ -242,12 +265,13 @@ __global__ __launch_bounds__(64 * kTWaves) __attribute__((amdgpu_waves_per_eu(4)
         l_bce += __shfl_xor(l_bce, off);
         l_t += __shfl_xor(l_t, off);
         l_n += __shfl_xor(l_n, off);
+        l_a += __shfl_xor(l_a, off);
       }
       if (lane == 0) {
         P.loss_part[blockIdx.x * 4 + 0] = l_bce;
         P.loss_part[blockIdx.x * 4 + 1] = l_t;
         P.loss_part[blockIdx.x * 4 + 2] = l_n;
-        P.loss_part[blockIdx.x * 4 + 3] = 0.f;
+        P.loss_part[blockIdx.x * 4 + 3] = l_a;
       }
     }
   }
@@ -848,28 +872,31 @@ static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_loss_finalize(const float* __restrict__ part, uint32_t n_tiles, uint32_t n,
-                                                       float w_hit, float w_t, float w_normal, float* __restrict__ out,
+                                                       float w_hit, float w_t, float w_normal, float w_albedo,
+                                                       float* __restrict__ out,
                                                        DevState* __restrict__ state) {
-  __shared__ float sh[3][256];
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  __shared__ float sh[4][256];
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
   for (uint32_t i = threadIdx.x; i < n_tiles; i += blockDim.x) {
     s0 += part[i * 4 + 0];
     s1 += part[i * 4 + 1];
     s2 += part[i * 4 + 2];
+    s3 += part[i * 4 + 3];
   }
   sh[0][threadIdx.x] = s0;
   sh[1][threadIdx.x] = s1;
   sh[2][threadIdx.x] = s2;
+  sh[3][threadIdx.x] = s3;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st)
-      for (int j = 0; j < 3; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + st];
+      for (int j = 0; j < 4; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     const float inv = 1.0f / (float)n;
     const float b = sh[0][0] * inv, t = sh[1][0] * inv, nn = sh[2][0] * inv;
-    const float tot = w_hit * b + w_t * t + w_normal * nn;
+    const float tot = w_hit * b + w_t * t + w_normal * nn + w_albedo * sh[3][0] * inv;
     if (!isfinite(tot)) atomicOr(&state->nonfinite_pending, 1u);
     state->last_loss[0] = tot;
     state->last_loss[1] = b;
@@ -886,11 +913,12 @@ __global__ __launch_bounds__(256) void k_loss_finalize(const float* __restrict__
 
 // plain loss / dz kernel (nbvh_loss): thread per probe, partial sums per block
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ z, const nbvh_label* __restrict__ labels,
-                                              uint32_t n, int n_out, float w_hit, float w_t, float w_normal,
+                                              uint32_t n, int n_out, float w_hit, float w_t, float w_normal, float w_albedo,
                                               float* __restrict__ dz, float* __restrict__ part) {
-  __shared__ float sh[3][256];
+  __shared__ float sh[4][256];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  float lb_ = 0.f, lt = 0.f, ln = 0.f;
+  float lb_ = 0.f, lt = 0.f, ln = 0.f, la = 0.f;
+  float da[3] = {0.f, 0.f, 0.f};
   if (i < n) {
     const float* zr = z + (size_t)i * n_out;
     const nbvh_label lb = labels[i];
@@ -900,6 +928,7 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ z, const
     float s = 0.f;
     for (int a = 0; a < 3; ++a) s += fabsf(zr[2 + a] - lb.n[a]);
     ln = h * s * (1.0f / 3.0f);
+    if (n_out >= 8) la = h * albedo_term(zr, lb.albedo, da);
     if (dz) {
       const float invB = 1.0f / (float)n;
       float* g = dz + (size_t)i * n_out;
@@ -907,22 +936,25 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ z, const
       g[0] = w_hit * (sigmoidf_(zr[0]) - h) * invB;
       g[1] = h * w_t * sgnf(st - tau) * st * (1.0f - st) * invB;
       for (int a = 0; a < 3; ++a) g[2 + a] = h * w_normal * sgnf(zr[2 + a] - lb.n[a]) * (1.0f / 3.0f) * invB;
+      if (n_out >= 8)
+        for (int ch = 0; ch < 3; ++ch) g[5 + ch] = h * w_albedo * da[ch] * invB;
     }
   }
   sh[0][threadIdx.x] = lb_;
   sh[1][threadIdx.x] = lt;
   sh[2][threadIdx.x] = ln;
+  sh[3][threadIdx.x] = la;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st)
-      for (int j = 0; j < 3; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + st];
+      for (int j = 0; j < 4; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     part[blockIdx.x * 4 + 0] = sh[0][0];
     part[blockIdx.x * 4 + 1] = sh[1][0];
     part[blockIdx.x * 4 + 2] = sh[2][0];
-    part[blockIdx.x * 4 + 3] = 0.f;
+    part[blockIdx.x * 4 + 3] = sh[3][0];
   }
 }
 
@@ -931,7 +963,7 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ z, const
 // loss weights, added to leaf_loss[leaf] with one count in leaf_count[leaf].
 __global__ __launch_bounds__(256) void k_leaf_loss(const float* __restrict__ z, const nbvh_label* __restrict__ labels,
                                                    const uint32_t* __restrict__ leaf_ids, uint32_t n, int n_out,
-                                                   float w_hit, float w_t, float w_normal,
+                                                   float w_hit, float w_t, float w_normal, float w_albedo,
                                                    float* __restrict__ leaf_loss, uint32_t* __restrict__ leaf_count) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -940,7 +972,11 @@ __global__ __launch_bounds__(256) void k_leaf_loss(const float* __restrict__ z, 
   const float h = lb.hit, st = sigmoidf_(zr[1]);
   float s = 0.f;
   for (int a = 0; a < 3; ++a) s += fabsf(zr[2 + a] - lb.n[a]);
-  const float loss = w_hit * bce_logits(zr[0], h) + w_t * h * fabsf(st - lb.tau) + w_normal * h * s * (1.0f / 3.0f);
+  float loss = w_hit * bce_logits(zr[0], h) + w_t * h * fabsf(st - lb.tau) + w_normal * h * s * (1.0f / 3.0f);
+  if (n_out >= 8) {
+    float da[3];
+    loss += w_albedo * h * albedo_term(zr, lb.albedo, da);
+  }
   const uint32_t leaf = leaf_ids[i];
   atomicAdd(&leaf_loss[leaf], loss);
   atomicAdd(&leaf_count[leaf], 1u);
@@ -952,7 +988,7 @@ nbvh_status launch_leaf_loss(const LaunchCtx& L, const nbvh_probe* probes, const
   nbvh_status s = launch_forward(L, probes, n, z);
   if (s != NBVH_OK) return s;
   k_leaf_loss<<<(n + 255) / 256, 256, 0, L.stream>>>(z, labels, leaf_ids, n, L.cfg.n_out, L.w_hit, L.w_t, L.w_normal,
-                                                     leaf_loss, leaf_count);
+                                                     L.w_albedo, leaf_loss, leaf_count);
   return check_launch("leaf_loss");
 }
 
@@ -1093,7 +1129,7 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
     auto kern = k_train_tile<AT, F, LP, LAB, NW>;                                                         \
     set_lds(kern, lds);                                                                                   \
     kern<<<T.n_tiles, 64 * NW, lds, L.stream>>>(c, table, W, WT, probes, labels, dz_in, n, P, L.state, L.w_hit, \
-                                               L.w_t, L.w_normal);                                       \
+                                               L.w_t, L.w_normal, L.w_albedo);                           \
   } while (0)
     if (labels) {
       if (nw == 4) NBVH_TT(true, 4);
@@ -1107,8 +1143,8 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
   {
     ProfScope ps(L.prof, NBVH_K_WGRAD, L.stream);
     if (labels)
-      k_loss_finalize<<<1, 256, 0, L.stream>>>(P.loss_part, T.n_tiles, n, L.w_hit, L.w_t, L.w_normal, loss_dev,
-                                               L.state);
+      k_loss_finalize<<<1, 256, 0, L.stream>>>(P.loss_part, T.n_tiles, n, L.w_hit, L.w_t, L.w_normal, L.w_albedo,
+                                               loss_dev, L.state);
     const WTiles tiles = make_tiles(c);
     float* wpart = (float*)(w + T.wpart);
     k_wgrad<AT><<<dim3(tiles.n, T.nsplit), 256, 0, L.stream>>>(c, tiles, P, kb, T.nsplit, wpart);
@@ -1142,8 +1178,8 @@ nbvh_status launch_loss(const LaunchCtx& L, const float* z, const nbvh_label* la
   }
   if (n == 0) return NBVH_OK;
   float* part = (float*)ws;
-  k_loss<<<nb, 256, 0, L.stream>>>(z, labels, n, L.cfg.n_out, L.w_hit, L.w_t, L.w_normal, dz, part);
-  k_loss_finalize<<<1, 256, 0, L.stream>>>(part, nb, n, L.w_hit, L.w_t, L.w_normal, loss_dev, L.state);
+  k_loss<<<nb, 256, 0, L.stream>>>(z, labels, n, L.cfg.n_out, L.w_hit, L.w_t, L.w_normal, L.w_albedo, dz, part);
+  k_loss_finalize<<<1, 256, 0, L.stream>>>(part, nb, n, L.w_hit, L.w_t, L.w_normal, L.w_albedo, loss_dev, L.state);
   return check_launch("loss");
 }
 

@@ -438,19 +438,48 @@ def test_nonfinite_gradient_skips_step(lib, c1):
     assert np.array_equal(m.get_params(), params)
 
 
-def test_train_step_matches_oracle_fp32(lib, c1):
+def _with_albedo(lab, seed):
+    """Labels with random albedo on hit segments (the synthetic mesh of these
+    tests carries none)."""
+    lab = lab.copy()
+    alb = np.random.default_rng(seed).uniform(0.05, 0.95, size=(lab.shape[0], 3)).astype(np.float32)
+    lab[:, 5:8] = np.where(lab[:, 4:5] > 0, alb, 0.0)
+    return lab
+
+
+def test_loss_with_albedo_matches_oracle(lib, c1):
+    """Eight outputs: the relative-L2 albedo term and its gradient."""
+    sc, _ = c1
+    net = NETS["f4"]
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32")
+    probes = _probes(sc, 3000 + 7, 19)
+    lab = _with_albedo(_labels_for(sc, probes), 20)
+    z = np.random.default_rng(21).normal(size=(probes.shape[0], 8)).astype(np.float32)
+    _say("loss with albedo")
+    loss, dz = m.loss(torch.from_numpy(z).cuda(), torch.from_numpy(lab).cuda())
+    terms, dzo = oracle.loss(_ocfg(net, sc), z.astype(np.float64), lab)
+    assert np.allclose(loss.cpu().numpy(), terms, rtol=1e-5, atol=1e-7)
+    assert np.abs(dz.cpu().numpy() - dzo).max() <= 1e-5 * np.abs(dzo).max()
+    assert np.abs(dzo[:, 5:8]).max() > 0
+
+
+@pytest.mark.parametrize("name", ["c1", "f4"])
+def test_train_step_matches_oracle_fp32(lib, c1, name):
     """One full training step (forward, loss, backward, Adam) in FP32 vs the
     oracle's step; Adam's first update is -lr*sign(g) where |g| >> eps, so
-    parameters are compared where the oracle gradient is clear of zero."""
+    parameters are compared where the oracle gradient is clear of zero. The
+    f4 network has eight outputs, so the albedo term trains too."""
     sc, _ = c1
-    net = configs.C1_NET
+    net = NETS[name]
     params = _params(net, scale=1.0)
     m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32", loss_scale=1.0)
     m.set_params(params)
     n = 4096 + 100
     probes = _clear_of_kinks(net, sc, params, _probes(sc, 2 * n, 18), n, 1e-4)
     lab = _labels_for(sc, probes)
-    _say("train step fp32 c1")
+    if net.n_out >= 8:
+        lab = _with_albedo(lab, 22)
+    _say("train step fp32", name)
     loss = m.train_step(torch.from_numpy(probes).cuda(), torch.from_numpy(lab).cuda()).cpu().numpy()
     cfg = _ocfg(net, sc)
     p64 = params.astype(np.float64)

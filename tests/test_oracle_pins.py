@@ -375,6 +375,53 @@ def test_loss_closed_form_at_zero():
     assert np.allclose(dz[:, 2:5], h[:, None] * np.sign(-n) / (3 * B), rtol=0, atol=1e-17)
 
 
+def _albedo_labels(rng, n):
+    lab = _labels(rng, n)
+    lab[:, 5:8] = rng.uniform(0.05, 0.95, size=(n, 3))
+    return lab
+
+
+def test_albedo_loss_closed_forms():
+    """With 8 outputs the albedo adds a relative L2 term, (a_hat - a)^2 /
+    (a_hat^2 + 0.01) averaged over the channels, masked by the hit label:
+    at z = 0 (a_hat = 1/2) it is (1/2 - a)^2 / 0.26 per channel, and it and
+    its gradient vanish where a_hat equals the label."""
+    net = Net(1, 2, 8, 1, [3], n_out=8)
+    cfg = _cfg(net)
+    rng = np.random.default_rng(36)
+    lab = _albedo_labels(rng, 40)
+    l64 = lab.astype(np.float64)
+    h, a = l64[:, 4], l64[:, 5:8]
+    base = 2 * np.log(2.0) + h * (2 * np.abs(0.5 - l64[:, 0]) + np.abs(l64[:, 1:4]).sum(1) / 3.0)
+    ref = base + h * ((0.5 - a) ** 2 / 0.26).mean(1)
+    assert np.abs(oracle.segment_loss(cfg, np.zeros((40, 8)), lab) - ref).max() < 1e-13
+    terms, _ = oracle.loss(cfg, np.zeros((40, 8)), lab, with_grad=False)
+    assert abs(terms[0] - ref.mean()) < 1e-13
+    z = rng.normal(size=(40, 8))
+    z[:, 5:8] = np.log(a / (1.0 - a))
+    _, dz = oracle.loss(cfg, z, lab)
+    assert np.abs(dz[:, 5:8]).max() < 1e-15
+    w0 = oracle.segment_loss(cfg, z, lab, weights=(2.0, 2.0, 1.0, 0.0))
+    assert np.abs(oracle.segment_loss(cfg, z, lab) - w0).max() < 1e-14
+
+
+def test_albedo_loss_gradient_finite_difference():
+    net = Net(1, 2, 8, 1, [3], n_out=8)
+    cfg = _cfg(net)
+    rng = np.random.default_rng(37)
+    lab = _albedo_labels(rng, 30)
+    z = rng.normal(size=(30, 8))
+    _, dz = oracle.loss(cfg, z, lab)
+    h = 1e-6
+    for i in range(0, 30, 7):
+        for o in (5, 6, 7):
+            zp, zm = z.copy(), z.copy()
+            zp[i, o] += h
+            zm[i, o] -= h
+            fd = (oracle.loss(cfg, zp, lab, with_grad=False)[0][0] - oracle.loss(cfg, zm, lab, with_grad=False)[0][0]) / (2 * h)
+            assert abs(fd - dz[i, o]) <= 1e-7 * max(1.0, abs(dz[i, o])) + 1e-9, (i, o, fd, dz[i, o])
+
+
 def test_loss_gradient_finite_difference():
     """dL/dz against central differences of the loss itself (BCE slope
     sigmoid(z) - h; L1 slopes away from their kinks)."""
