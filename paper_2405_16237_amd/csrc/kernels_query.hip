@@ -365,6 +365,15 @@ __global__ __launch_bounds__(256) void k_encode(DevCfg c, const void* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// A workgroup's LDS cannot exceed the CU's 160 KiB: wide networks in FP32
+// (n_in + width > ~600) do not fit the 64-row tiles and are refused.
+static nbvh_status lds_fits(size_t bytes, const char* what) {
+  if (bytes > 160 * 1024)
+    return set_error("%s needs %zu bytes of LDS (> 160 KiB) for this network and precision", what, bytes),
+           NBVH_ERR_UNSUPPORTED;
+  return NBVH_OK;
+}
+
 template <typename K>
 static void set_lds(K kernel, size_t bytes) {
   (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -407,6 +416,7 @@ static nbvh_status query_batch_t(const LaunchCtx* Ls, int n_obj, const DevCfg* c
                                  nbvh_hit* per_obj, nbvh_hit* hits, uint32_t n_rays) {
   const LaunchCtx& L = Ls[0];
   const size_t lds = query_lds_bytes<AT>(L.cfg.n_in, L.cfg.width);
+  if (lds_fits(lds, "the query") != NBVH_OK) return NBVH_ERR_UNSUPPORTED;
   auto kern = k_query_eval_batch<AT, F, LP, NW, U, PR>;
   set_lds(kern, lds);
   const int per_cu = query_per_cu(L, lds);
@@ -457,6 +467,7 @@ static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const 
                                 uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity) {
   const DevCfg& c = L.cfg;
   const size_t lds = query_lds_bytes<AT>(c.n_in, c.width);
+  if (lds_fits(lds, "the query") != NBVH_OK) return NBVH_ERR_UNSUPPORTED;
   auto kern = k_query_eval<AT, F, LP, NW, U, PR>;
   set_lds(kern, lds);
   uint32_t grid = (uint32_t)L.n_cu * query_per_cu(L, lds);
@@ -496,6 +507,7 @@ template <typename AT, int F, bool LP>
 static nbvh_status forward_t(const LaunchCtx& L, const nbvh_probe* probes, uint32_t n, float* z) {
   const DevCfg& c = L.cfg;
   const size_t lds = query_lds_bytes<AT>(c.n_in, c.width);
+  if (lds_fits(lds, "the forward pass") != NBVH_OK) return NBVH_ERR_UNSUPPORTED;
   auto kern = k_forward<AT, F, LP>;
   set_lds(kern, lds);
   const void* W = (sizeof(AT) == 1)   ? (const void*)((const char*)L.aux + fp8_weights_off(c))
@@ -637,6 +649,7 @@ nbvh_status launch_calibrate_fp8(const LaunchCtx& L, const nbvh_probe* probes, u
   k_zero_u32<<<1, 64, 0, L.stream>>>((uint32_t*)(f + 2 * kMaxLayers), 2 * kMaxLayers);
   k_weight_amax<<<dim3(64, c.hidden + 1), 256, 0, L.stream>>>(c, L.params, f + 2 * kMaxLayers);
   const size_t lds = query_lds_bytes<float>(c.n_in, c.width);
+  if (lds_fits(lds, "FP8 calibration (an FP32 forward)") != NBVH_OK) return NBVH_ERR_UNSUPPORTED;
   const void* table = L.params_lp;
   if (c.n_features == 2) {
     set_lds(k_calib_act<2>, lds);

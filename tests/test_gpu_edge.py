@@ -1,0 +1,136 @@
+"""Edge cases through the C ABI: empty inputs, rays that miss everything, a
+single-leaf scene, segment-queue overflow, and the largest network shapes
+the library accepts (32 levels x 2 features x 8 samples = 512 inputs,
+8 hidden layers of 256, 16 outputs)."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from nbvh_synth import configs, scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_16237_amd as P
+    P.load()
+    return P
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return configs.make_scene(20480, 64)
+
+
+def test_empty_inputs(lib, c1):
+    sc = c1
+    m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="bf16")
+    m.set_params(configs.init_params(configs.C1_NET))
+    none = torch.zeros((0, 8), dtype=torch.float32, device="cuda")
+    _say("empty inputs")
+    assert m.query(none).shape == (0, 8)
+    off, _ = m.traverse(none, 16)
+    assert off.cpu().tolist() == [0]
+    assert m.forward(none).shape == (0, configs.C1_NET.n_out)
+    assert m.encode(none).shape[0] == 0
+    p, lf = m.first_hits(none, torch.zeros(0, device="cuda"), torch.ones(64, device="cuda"))
+    assert p.shape[0] == 0 and lf.shape[0] == 0
+    with pytest.raises(lib.NbvhError):
+        m.train_step(none, none)
+    batch = lib.NBVHBatch([m])
+    assert batch.query(none).shape == (0, 8)
+    torch.cuda.synchronize()
+    assert m.read_state()["flags"] == 0
+
+
+def test_rays_that_miss_and_single_leaf(lib, c1):
+    sc = c1
+    net = configs.C1_NET
+    params = configs.init_params(net, "uniform", 1.0, seed_features=30, seed_mlp=31)
+    # every ray points away from the scene
+    rays = scene.pinhole_rays(64, 64, eye=(0.0, 0.0, 3.0), target=(0.0, 0.0, 6.0))
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32")
+    m.set_params(params)
+    _say("rays that miss every leaf")
+    h = m.query(torch.from_numpy(rays).cuda()).cpu().numpy()
+    assert np.all(h[:, 7].view(np.uint32) == 0xFFFFFFFF) and np.all(h[:, :7] == 0)
+    off, _ = m.traverse(torch.from_numpy(rays).cuda(), 16)
+    assert np.all(off.cpu().numpy() == 0)
+    # one leaf: the whole scene box
+    box = np.concatenate([sc.boxes[:, :3].min(0), sc.boxes[:, 3:].max(0)])[None, :].astype(np.float32)
+    m1 = lib.NBVH(net, box, sc.lo, sc.side, precision="fp32")
+    m1.set_params(params)
+    rays = scene.pinhole_rays(96, 96)
+    _say("single leaf query")
+    h = m1.query(torch.from_numpy(rays).cuda()).cpu().numpy()
+    out, tr, z = oracle.query(oracle.make_cfg(net, sc.lo, sc.side), params.astype(np.float64), rays, box)
+    clear = np.ones(rays.shape[0], bool)
+    clear[np.unique(tr[1][np.abs(z[:, 0]) <= 1e-4 * np.maximum(1.0, np.abs(z[:, 0]))])] = False
+    leaf = h[:, 7].view(np.uint32).astype(np.int64)
+    leaf[leaf == 0xFFFFFFFF] = -1
+    assert (leaf[clear] == out[clear, 4]).mean() >= 0.999
+    hit = clear & (out[:, 4] >= 0)
+    assert np.abs(h[hit, 0] - out[hit, 0]).max() <= 1e-5 * max(1.0, np.abs(out[hit, 0]).max())
+
+
+def test_query_segment_overflow_is_flagged(lib, c1):
+    sc = c1
+    m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="bf16")
+    m.set_params(configs.init_params(configs.C1_NET))
+    rays = torch.from_numpy(scene.pinhole_rays(128, 128)).cuda()
+    _say("query with a too small segment queue")
+    m.query(rays, seg_capacity=100)
+    torch.cuda.synchronize()
+    assert m.read_state()["flags"] & 1
+    m.clear_flags()
+    m.query(rays)
+    torch.cuda.synchronize()
+    assert m.read_state()["flags"] == 0
+
+
+MAX_NET = configs.NetConfig(32, 2, 14, 8, 4, 1.15, 256, 8, 16)
+
+
+def test_largest_network_bf16(lib, c1):
+    """512 inputs, 8 x 256 hidden, 16 outputs: BF16 forward against the
+    oracle on BF16-rounded parameters, and a training step that stays finite."""
+    sc = c1
+    net = MAX_NET
+    assert net.n_in == 512
+    params = configs.init_params(net, "uniform", 0.5, seed_features=32, seed_mlp=33)
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16")
+    m.set_params(params)
+    probes, _ = scene.leaf_probes(sc.boxes, 10, seed=34)
+    _say("largest network forward", probes.shape)
+    z = m.forward(torch.from_numpy(probes).cuda()).cpu().numpy().astype(np.float64)
+    pb = torch.from_numpy(params).to(torch.bfloat16).float().numpy().astype(np.float64)
+    ref = oracle.forward(oracle.make_cfg(net, sc.lo, sc.side), pb, probes)
+    err = np.abs(z - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.max() <= 2e-2, err.max()
+    lab = scene.probe_labels(sc.mesh, probes)
+    loss = m.train_step(torch.from_numpy(probes).cuda(), torch.from_numpy(lab).cuda())
+    torch.cuda.synchronize()
+    assert torch.isfinite(loss).all() and m.read_state()["skipped"] == 0
+
+
+def test_largest_network_fp32_is_refused(lib, c1):
+    """In FP32 the 64-row activation tiles of the largest network need more
+    than a CU's 160 KiB of LDS: the call fails with a clear error."""
+    sc = c1
+    m = lib.NBVH(MAX_NET, sc.boxes, sc.lo, sc.side, precision="fp32")
+    m.set_params(configs.init_params(MAX_NET))
+    probes, _ = scene.leaf_probes(sc.boxes, 2, seed=35)
+    with pytest.raises(lib.NbvhError, match="LDS"):
+        m.forward(torch.from_numpy(probes).cuda())
