@@ -16,6 +16,13 @@ numbers below one, r and r_max are negative and that ratio inverts the
 order, so the rank is used through exp(r - r_max) = q^2 p / (q^2 p)_max,
 which is 1 for the leaf of largest error and monotone in r.
 
+Levels of detail (Sec. 5.4): with lod_interval > 0 the current cut is
+registered as a level of detail whenever that many training steps have run
+since the last one; each level is an N-BVH view over its cut that shares the
+one network. Every training step then picks one of the registered levels or
+the current cut uniformly at random and trains on its nodes, each level with
+the acceptance probabilities it had when registered.
+
 The driver runs on the host; every per-ray and per-segment step (traversal,
 first-hit selection, crossing counts, network, loss, per-leaf sums,
 training) is a library call. Labels come from the caller (classical
@@ -44,6 +51,7 @@ class Schedule:
     stats_rays: int = 1 << 18   # rays drawn to estimate q and p before an expansion
     min_accept: float = 0.005   # acceptance floor of the ray distribution
     inflate: float = 0.5        # the root box grows by this fraction of its extent for sampling
+    lod_interval: int = 0       # training steps between registered levels of detail (0: none)
 
 
 @dataclass
@@ -120,10 +128,12 @@ class Sampler:
 
 
 def construct(net, base, label_fn, schedule: Schedule, scene_lo, scene_side, params=None, precision="bf16",
-              seed: int = 11, log=None, **model_kw):
+              seed: int = 11, log=None, lods: list | None = None, **model_kw):
     """Grow a cut of `base` to schedule.target_leaves leaves while training
     the network; returns (model, cut, history). label_fn(probes [k][8]
-    float32 numpy) -> labels [k][8] float32 numpy."""
+    float32 numpy) -> labels [k][8] float32 numpy. If `lods` is a list, the
+    levels of detail are appended to it as (Cut, NBVH) pairs from coarse to
+    fine, the final cut and model last."""
     cut = Cut([0])
     model = NBVH(net, cut.boxes(base), scene_lo, scene_side, precision=precision, **model_kw)
     if params is not None:
@@ -132,17 +142,31 @@ def construct(net, base, label_fn, schedule: Schedule, scene_lo, scene_side, par
     sampler = Sampler(base, schedule.inflate, seed, model.device)
     accept = torch.ones(1, dtype=torch.float32, device=model.device)
     history = []
+    levels = []  # registered levels of detail: (Cut, view, acceptance)
+    pick = np.random.default_rng(seed)
+    done = [0, 0]  # training steps run, steps at the last registration
 
     def train(steps):
         losses = []
         for _ in range(steps):
+            k = int(pick.integers(len(levels) + 1)) if levels else len(levels)
+            tree, acc = (model, accept) if k == len(levels) else (levels[k][1], levels[k][2])
             rays, u = sampler.rays(schedule.rays_per_step)
-            probes, _ = model.first_hits(rays, u, accept)
+            probes, _ = tree.first_hits(rays, u, acc)
+            done[0] += 1
             if probes.shape[0] == 0:
                 continue
             lab = torch.from_numpy(label_fn(probes.cpu().numpy())).to(model.device)
-            losses.append(model.train_step(probes.contiguous(), lab))
+            losses.append(tree.train_step(probes.contiguous(), lab))
         return float(torch.stack(losses)[:, 0].mean()) if losses else float("nan")
+
+    def maybe_register():
+        if schedule.lod_interval > 0 and done[0] - done[1] >= schedule.lod_interval:
+            done[1] = done[0]
+            if not levels or levels[-1][0].nodes != cut.nodes:
+                levels.append((Cut(list(cut.nodes)), model.view(cut.boxes(base)), accept.clone()))
+                if log:
+                    log("level of detail %d: %d leaves" % (len(levels) - 1, len(cut.nodes)))
 
     def statistics():
         n_leaves = len(cut.nodes)
@@ -162,6 +186,7 @@ def construct(net, base, label_fn, schedule: Schedule, scene_lo, scene_side, par
         mean_loss = train(int(round(iters)))
         r = statistics()
         accept = torch.tensor(acceptance(r, schedule.min_accept), dtype=torch.float32, device=model.device)
+        maybe_register()
         k = min(int(round(splits)), schedule.target_leaves - len(cut.nodes))
         pos = choose_splits(cut, base, r, k)
         history.append(dict(leaves=len(cut.nodes), steps=int(round(iters)), loss=mean_loss, split=len(pos)))
@@ -183,4 +208,7 @@ def construct(net, base, label_fn, schedule: Schedule, scene_lo, scene_side, par
     history.append(dict(leaves=len(cut.nodes), steps=schedule.final_iters, loss=final, split=0))
     if log:
         log("final: %d leaves, %d steps, mean loss %.4f" % (len(cut.nodes), schedule.final_iters, final))
+    if lods is not None:
+        lods.extend((c, v) for c, v, _ in levels if c.nodes != cut.nodes)
+        lods.append((cut, model))
     return model, cut, history

@@ -51,14 +51,8 @@ class NBVH:
         self.device = torch.device(device)
         self.cfg = make_config(net, scene_lo, scene_side, precision, **kw)
         self.precision = self.cfg.precision
-        lb = np.ascontiguousarray(leaf_boxes, dtype=np.float32)
-        self.n_leaves = lb.shape[0]
-        nb = self.lib.nbvh_nodes_bytes(self.n_leaves)
-        self.nodes = torch.empty(nb, dtype=torch.uint8, device=self.device)
-        ctx = ctypes.c_void_p()
-        check(self.lib.nbvh_build(ctypes.byref(self.cfg), lb.ctypes.data_as(ctypes.c_void_p), self.n_leaves,
-                                  _ptr(self.nodes), nb, _stream(), ctypes.byref(ctx)))
-        self.ctx = ctx
+        self.ctx, self.nodes, self.n_leaves = self._build(leaf_boxes)
+        self._owner = None
         nt, nm = ctypes.c_uint64(), ctypes.c_uint64()
         check(self.lib.nbvh_param_count(ctypes.byref(self.cfg), ctypes.byref(nt), ctypes.byref(nm)))
         self.n_table, self.n_mlp = nt.value, nm.value
@@ -157,18 +151,47 @@ class NBVH:
         base BVH), keeping the network parameters, optimiser moments, device
         state and launch knobs. The hash-grid domain (scene_lo, scene_side)
         is unchanged, so the boxes must stay inside it."""
-        lb = np.ascontiguousarray(leaf_boxes, dtype=np.float32)
-        nb = self.lib.nbvh_nodes_bytes(lb.shape[0])
-        nodes = torch.empty(nb, dtype=torch.uint8, device=self.device)
         tuning = self.get_tuning()
-        ctx = ctypes.c_void_p()
-        check(self.lib.nbvh_build(ctypes.byref(self.cfg), lb.ctypes.data_as(ctypes.c_void_p), lb.shape[0],
-                                  _ptr(nodes), nb, _stream(), ctypes.byref(ctx)))
+        ctx, nodes, n_leaves = self._build(leaf_boxes)
         check(self.lib.nbvh_bind_params(ctx, ctypes.byref(self._p)))
         old, self.ctx = self.ctx, ctx
         self.lib.nbvh_destroy(old)
-        self.nodes, self.n_leaves = nodes, lb.shape[0]
+        self.nodes, self.n_leaves = nodes, n_leaves
         self.set_tuning(**tuning)
+
+    def view(self, leaf_boxes) -> "NBVH":
+        """Another N-BVH over `leaf_boxes` bound to this one's buffers: the
+        same hash grid, MLP, optimiser moments, gradient and device state
+        (step count, loss scale, flags). This is how several tree cuts share
+        one network (levels of detail, Sec. 5.4): a training step through any
+        view updates the one set of parameters. Launch knobs are copied. The
+        view keeps this object alive. FP8 models have no views: whether their
+        E4M3 weights match the parameters is tracked per tree, so a change
+        made through one tree could leave another's stale; build an FP8 model
+        per tree from the trained parameters instead."""
+        if self.cfg.precision == _abi.NBVH_FP8:
+            raise ValueError("FP8 models have no views; build one FP8 model per tree from the trained parameters")
+        v = NBVH.__new__(NBVH)
+        v.lib, v.net, v.device, v.cfg, v.precision = self.lib, self.net, self.device, self.cfg, self.precision
+        v.n_table, v.n_mlp, v.offsets, v.n_params = self.n_table, self.n_mlp, self.offsets, self.n_params
+        v.params, v.params_lp, v.adam_m, v.adam_v = self.params, self.params_lp, self.adam_m, self.adam_v
+        v.grad, v.state, v.aux, v._p = self.grad, self.state, self.aux, self._p
+        v._owner = self
+        v._ws = None
+        v.ctx, v.nodes, v.n_leaves = v._build(leaf_boxes)
+        check(v.lib.nbvh_bind_params(v.ctx, ctypes.byref(v._p)))
+        v.set_tuning(**self.get_tuning())
+        return v
+
+    def _build(self, leaf_boxes):
+        """(ctx, nodes, n_leaves) of a fresh N-BVH over leaf_boxes [n][6]."""
+        lb = np.ascontiguousarray(leaf_boxes, dtype=np.float32)
+        nb = self.lib.nbvh_nodes_bytes(lb.shape[0])
+        nodes = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        check(self.lib.nbvh_build(ctypes.byref(self.cfg), lb.ctypes.data_as(ctypes.c_void_p), lb.shape[0],
+                                  _ptr(nodes), nb, _stream(), ctypes.byref(ctx)))
+        return ctx, nodes, lb.shape[0]
 
     # -- calls --------------------------------------------------------------------
     def first_hits(self, rays: torch.Tensor, u: torch.Tensor, accept: torch.Tensor,

@@ -137,3 +137,68 @@ def test_construction_grows_cut_and_learns(lib, c1):
     box_acc = float(((off[1:] > off[:-1]) == gt["hit"]).mean())
     _say("construction: hit accuracy %.4f, boxes alone %.4f, history %s" % (acc, box_acc, hist))
     assert acc > box_acc and acc > 0.9
+
+
+def test_view_shares_the_network(lib, c1):
+    """A view over other leaves answers exactly like a separate model with
+    the same parameters on those leaves, and trains the one network."""
+    sc = c1
+    net = configs.C1_NET
+    params = configs.init_params(net, "uniform", 0.5, seed_features=76, seed_mlp=77)
+    coarse, _ = scene.median_split_leaves(sc.verts, sc.tris, 8)
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32")
+    m.set_params(params)
+    v = m.view(coarse)
+    ref = lib.NBVH(net, coarse, sc.lo, sc.side, precision="fp32")
+    ref.set_params(params)
+    rays = torch.from_numpy(scene.pinhole_rays(128, 128)).cuda()
+    _say("view query")
+    hv = v.query(rays).cpu().numpy()
+    hr = ref.query(rays).cpu().numpy()
+    assert np.array_equal(hv.view(np.uint32), hr.view(np.uint32))
+    probes, _ = scene.leaf_probes(coarse, 64, seed=78)
+    lab = scene.probe_labels(sc.mesh, probes)
+    _say("train through the view")
+    v.train_step(torch.from_numpy(probes).cuda(), torch.from_numpy(lab).cuda())
+    ref.train_step(torch.from_numpy(probes).cuda(), torch.from_numpy(lab).cuda())
+    torch.cuda.synchronize()
+    assert m.read_state()["step"] == 1 and v.read_state()["step"] == 1
+    got, want = m.get_params(), ref.get_params()
+    assert not np.array_equal(got, params)
+    assert np.abs(got - want).max() <= 1e-6
+    with pytest.raises(ValueError):
+        lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp8").view(coarse)
+
+
+def test_levels_of_detail(lib, c1):
+    """Construction with levels of detail (Sec. 5.4): several cuts of one
+    base BVH, coarse to fine, trained together on one network. Every level
+    is a cut, answers camera rays well, and the coarser levels cross fewer
+    leaves per ray."""
+    from paper_2405_16237_amd import construct as C
+    sc = c1
+    base = scene.base_bvh(sc.verts, sc.tris, leaf_tris=64)
+    net = configs.C1_NET
+    root = np.concatenate([base["lo"][0], base["hi"][0]])[None, :]
+    lo, side = scene.scene_cube(root)
+    sched = C.Schedule(target_leaves=48, iters=40, iters_growth=1.3, splits=2, splits_growth=1.6, final_iters=400,
+                       rays_per_step=1 << 15, stats_rays=1 << 15, lod_interval=100)
+    lods = []
+    C.construct(net, base, lambda p: scene.probe_labels(sc.mesh, p), sched, lo, side,
+                params=configs.init_params(net, "normal", 1e-2), log=_say, lods=lods)
+    sizes = [len(c.nodes) for c, _ in lods]
+    _say("level sizes", sizes)
+    assert len(lods) >= 3 and sizes == sorted(sizes) and len(set(sizes)) == len(sizes) and sizes[-1] == 48
+    rays_np = scene.pinhole_rays(192, 192)
+    gt = scene.ray_ground_truth(sc.mesh, rays_np)
+    rays = torch.from_numpy(rays_np).cuda()
+    segs, accs = [], []
+    for c, tree in lods:
+        assert base["n_tris"][c.nodes].sum() == sc.tris.shape[0]
+        h = tree.query(rays).cpu().numpy()
+        accs.append(float(((h[:, 7].view(np.uint32) != 0xFFFFFFFF) == gt["hit"]).mean()))
+        torch.cuda.synchronize()
+        segs.append(tree.read_state()["last_n_segments"])
+    _say("hit accuracy per level", accs, "segments", segs)
+    assert min(accs) > 0.85 and accs[-1] > 0.9
+    assert segs[0] < segs[-1]
