@@ -59,6 +59,22 @@ typedef enum { NBVH_FP32 = 0, NBVH_BF16 = 1, NBVH_FP8 = 2 } nbvh_precision;
 #define NBVH_MAX_LEVELS 32
 #define NBVH_MISS 0xFFFFFFFFu
 
+/* How a leaf that contains the ray origin (the ray's line enters the box
+ * before tmin and leaves it after) is queried; nbvh_config.inside_rule.
+ * CLIP   : the segment is the part of the box after tmin, [tmin, exit],
+ *          sampled and encoded in ray order like any other.
+ * REVERSE: the whole chord [entry, exit] of the box is queried in reverse,
+ *          as the ray (o, -d) crossing it from the exit point, so the
+ *          features are concatenated in the opposite order (the reversal
+ *          rule of Sec. 6, a commented-out "Depth estimation" passage, and
+ *          the convexity assumption of Sec. 9, "Limitations"). The reversed query
+ *          predicts the last surface crossing of the chord; the leaf is hit
+ *          only if that point lies in front of the origin (t > tmin). Such
+ *          segments carry NBVH_SEG_INSIDE in their leaf field and store the
+ *          chord [entry, exit] with entry < tmin. */
+typedef enum { NBVH_INSIDE_CLIP = 0, NBVH_INSIDE_REVERSE = 1 } nbvh_inside_rule;
+#define NBVH_SEG_INSIDE 0x80000000u
+
 /* A ray: origin, [tmin, tmax], direction (not necessarily unit length).
  * Direction components must be 0 or normal floats. 32 bytes. */
 typedef struct {
@@ -70,7 +86,9 @@ typedef struct {
 
 /* One ray/leaf crossing: [t0, t1] is the part of the ray's [tmin, tmax]
  * inside the leaf box (Sec. 5: inference queries the model on each leaf a
- * ray reaches). 16 bytes. */
+ * ray reaches). Under NBVH_INSIDE_REVERSE a leaf containing the origin has
+ * leaf = id | NBVH_SEG_INSIDE and [t0, t1] = the whole chord (t0 < tmin).
+ * Runs are sorted by (t0, leaf). 16 bytes. */
 typedef struct {
   uint32_t ray;
   uint32_t leaf;
@@ -135,6 +153,7 @@ typedef struct {
   float scene_side;
   float w_hit, w_t, w_normal, w_albedo; /* loss weights (Sec. 5.2: 2, 2, 1, 1); albedo only with n_out >= 8 */
   float lr, beta1, beta2, eps, loss_scale;
+  int32_t inside_rule; /* nbvh_inside_rule: queries and training-ray selection (NBVH_INSIDE_CLIP) */
 } nbvh_config;
 
 /* Caller-owned device buffers of the learnable state. All FP32 arrays have
@@ -289,14 +308,16 @@ nbvh_status nbvh_query_segments(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_
                                 const uint32_t* seg_offsets_dev, const nbvh_segment* segs_dev,
                                 nbvh_hit* hits_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
-/* Training-ray selection for the error-driven construction (Sec. 5.3, "Ray
+/* Training-ray selection for the error-driven construction (Sec. 5.2, "Ray
  * distribution" and "Node error"). For each of the n_rays rays (device,
  * typically sampled uniformly in the inflated root box) the N-BVH is
  * traversed as by nbvh_traverse; the first leaf crossed (smallest t0, ties
  * to the lower leaf id) is kept iff u_dev[r] < accept_dev[leaf] (u_dev:
  * [n_rays] caller-drawn uniforms in [0, 1); accept_dev: [n_leaves]
  * acceptance probabilities). Kept segments are written to probes_dev as
- * (o, t0, d, t1) with their leaf id in leaf_ids_dev, in an unspecified
+ * (o, t0, d, t1) (under NBVH_INSIDE_REVERSE a first leaf that contains the
+ * origin gives the reversed chord (o, -exit, -d, -entry), the probe such a
+ * leaf is queried with) with their leaf id in leaf_ids_dev, in an unspecified
  * order; both need room for n_rays entries. *n_out_dev (device) receives the
  * number kept (cleared by the call). If leaf_hits_dev is not NULL, every
  * leaf crossed by a ray has its counter incremented (the caller clears it),
@@ -305,7 +326,7 @@ nbvh_status nbvh_first_hits(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_
                             const float* accept_dev, nbvh_probe* probes_dev, uint32_t* leaf_ids_dev,
                             uint32_t* n_out_dev, uint32_t* leaf_hits_dev, void* stream);
 
-/* Per-leaf training loss (Sec. 5.3, "Node error"): runs the network on the n
+/* Per-leaf training loss (Sec. 5.1, "Node error"): runs the network on the n
  * segments probes_dev with labels_dev and adds each segment's combined loss
  * (weights w_hit, w_t, w_normal, w_albedo; not divided by the batch size) to
  * leaf_loss_dev[leaf_ids_dev[i]] (float, [n_leaves]) and one to

@@ -52,7 +52,7 @@ def _lib():
             L.oc_slab_one.argtypes = [P, P, P]
             L.oc_slab_one.restype = ctypes.c_int
             L.oc_traverse_count.argtypes = [P, I, P, I, P]
-            L.oc_traverse_fill.argtypes = [P, I, P, I, P, P, P, P, P]
+            L.oc_traverse_fill.argtypes = [P, I, P, I, P, P, P, P, P, ctypes.c_int]
             L.oc_sample_positions.argtypes = [P, P, I, P]
             L.oc_table_params.argtypes = [P]
             L.oc_table_params.restype = I
@@ -66,7 +66,7 @@ def _lib():
             L.oc_adam.argtypes = [I, P, P, P, P, I, D, D, D, D, D]
             L.oc_min_abs_preact.argtypes = [P, P, P, I, P]
             L.oc_layer_amax.argtypes = [P, P, P, I, P]
-            L.oc_resolve.argtypes = [I, P, P, P, P, P, ctypes.c_int, P]
+            L.oc_resolve.argtypes = [I, P, P, P, P, P, ctypes.c_int, P, P]
             L.oc_num_threads.restype = ctypes.c_int
             _LIB = L
     return _LIB
@@ -118,9 +118,14 @@ def slab(ray, box):
     return bool(h), out[0], out[1]
 
 
-def traverse(rays, boxes):
+INSIDE_TAG = 0x80000000
+
+
+def traverse(rays, boxes, reverse=False):
     """Every-leaf traversal. Returns (offsets uint64 [n+1], seg_ray, seg_leaf
-    uint32, seg_t0, seg_t1 float32), each ray's run sorted by (t0, leaf)."""
+    uint32, seg_t0, seg_t1 float32), each ray's run sorted by (t0, leaf).
+    reverse: a leaf around the ray origin gives its whole chord [entry, exit]
+    with INSIDE_TAG set in its leaf id (queried backwards)."""
     rays = _c(rays, np.float32)
     boxes = _c(boxes, np.float32)
     n, m = rays.shape[0], boxes.shape[0]
@@ -134,18 +139,26 @@ def traverse(rays, boxes):
     sl = np.zeros(tot, dtype=np.uint32)
     t0 = np.zeros(tot, dtype=np.float32)
     t1 = np.zeros(tot, dtype=np.float32)
-    L.oc_traverse_fill(_p(rays), n, _p(boxes), m, _p(offsets), _p(sr), _p(sl), _p(t0), _p(t1))
+    L.oc_traverse_fill(_p(rays), n, _p(boxes), m, _p(offsets), _p(sr), _p(sl), _p(t0), _p(t1), int(bool(reverse)))
     return offsets, sr, sl, t0, t1
 
 
-def segment_rows(rays, seg_ray, seg_t0, seg_t1):
-    """[n_seg][8] float32 rows (o, t0, d, t1) for the segments of a traversal."""
+def segment_rows(rays, seg_ray, seg_t0, seg_t1, seg_leaf=None):
+    """[n_seg][8] float32 rows (o, t0, d, t1) for the segments of a traversal.
+    A tagged (inside) segment is the chord crossed backwards from its exit:
+    the ray (o, -d) over [-t1, -t0], so its samples run from the exit to the
+    entry."""
     rays = np.asarray(rays, dtype=np.float32)
     out = np.zeros((seg_ray.shape[0], 8), dtype=np.float32)
     out[:, 0:3] = rays[seg_ray, 0:3]
     out[:, 3] = seg_t0
     out[:, 4:7] = rays[seg_ray, 4:7]
     out[:, 7] = seg_t1
+    if seg_leaf is not None:
+        inside = (np.asarray(seg_leaf, dtype=np.uint32) & INSIDE_TAG) != 0
+        out[inside, 3] = -np.asarray(seg_t1, dtype=np.float32)[inside]
+        out[inside, 4:7] = -out[inside, 4:7]
+        out[inside, 7] = -np.asarray(seg_t0, dtype=np.float32)[inside]
     return out
 
 
@@ -228,20 +241,35 @@ def segment_loss(cfg, z, labels, weights=LOSS_WEIGHTS):
     return out
 
 
-def first_hits(rays, boxes, u, accept):
-    """Training-ray selection (Sec. 5.3): for each ray its first crossed leaf
-    (smallest t0, ties to the lower id, from the every-leaf traversal), kept
-    iff u[r] < accept[leaf] in binary32. Returns (ray indices kept, their
-    leaf, t0, t1) in ray order and the number of rays crossing each leaf."""
-    off, sr, sl, t0, t1 = traverse(rays, boxes)
+def _first(rays, boxes, u, accept, reverse):
+    off, sr, sl, t0, t1 = traverse(rays, boxes, reverse)
     off = off.astype(np.int64)
     has = off[1:] > off[:-1]
     first = off[:-1][has]  # runs are sorted by (t0, leaf): the first entry is the first leaf
     ray = np.nonzero(has)[0]
-    leaf = sl[first].astype(np.int64)
+    tag = sl[first]
+    leaf = (tag & ~np.uint32(INSIDE_TAG)).astype(np.int64)
     keep = np.asarray(u, dtype=np.float32)[ray] < np.asarray(accept, dtype=np.float32)[leaf]
-    hits = np.bincount(sl.astype(np.int64), minlength=boxes.shape[0])
-    return ray[keep], leaf[keep], t0[first][keep], t1[first][keep], hits
+    hits = np.bincount((sl & ~np.uint32(INSIDE_TAG)).astype(np.int64), minlength=boxes.shape[0])
+    return ray[keep], leaf[keep], tag[keep], t0[first][keep], t1[first][keep], hits
+
+
+def first_hits(rays, boxes, u, accept, reverse=False):
+    """Training-ray selection (Sec. 5.2, "Ray distribution"): for each ray its first crossed leaf
+    (smallest t0, ties to the lower id, from the every-leaf traversal), kept
+    iff u[r] < accept[leaf] in binary32. Returns (ray indices kept, their
+    leaf, t0, t1) in ray order and the number of rays crossing each leaf.
+    With reverse, a leaf around the origin reports its chord [entry, exit]."""
+    ray, leaf, _, t0, t1, hits = _first(rays, boxes, u, accept, reverse)
+    return ray, leaf, t0, t1, hits
+
+
+def first_hit_probes(rays, boxes, u, accept, reverse=False):
+    """The training segments of first_hits as probe rows (o, t0, d, t1), a
+    leaf around the origin crossed backwards when reverse is set, and their
+    leaf ids, in ray order."""
+    ray, leaf, tag, t0, t1, _ = _first(rays, boxes, u, accept, reverse)
+    return segment_rows(rays, ray, t0, t1, tag), leaf
 
 
 def backward(cfg, params, segs, dz):
@@ -274,22 +302,26 @@ def train_step(cfg, params, m, v, step, segs, labels, lr=1e-2, beta1=0.9, beta2=
 
 
 # -- query -------------------------------------------------------------------------
-def resolve(offsets, seg_leaf, seg_t0, seg_t1, z, n_out):
-    """Per ray [t, n.xyz, leaf, seg, albedo.rgb]; leaf = seg = -1 on a miss."""
+def resolve(offsets, seg_leaf, seg_t0, seg_t1, z, n_out, ray_tmin=None):
+    """Per ray [t, n.xyz, leaf, seg, albedo.rgb]; leaf = seg = -1 on a miss.
+    ray_tmin [n] is needed when segments carry INSIDE_TAG (zeros otherwise)."""
     offsets = _c(offsets, np.uint64)
     z = _c(z, np.float64)
     n = offsets.shape[0] - 1
+    tmin = _c(np.zeros(n) if ray_tmin is None else ray_tmin, np.float32)
     out = np.zeros((n, 9), dtype=np.float64)
     _lib().oc_resolve(n, _p(offsets), _p(_c(seg_leaf, np.uint32)), _p(_c(seg_t0, np.float32)),
-                      _p(_c(seg_t1, np.float32)), _p(z), int(n_out), _p(out))
+                      _p(_c(seg_t1, np.float32)), _p(z), int(n_out), _p(tmin), _p(out))
     return out
 
 
-def query(cfg, params, rays, boxes):
+def query(cfg, params, rays, boxes, reverse=False):
     """Full neural ray query: traversal, encode, MLP, resolve. Returns
-    (hits [n][9], (offsets, seg_ray, seg_leaf, t0, t1), z)."""
-    tr = traverse(rays, boxes)
+    (hits [n][9], (offsets, seg_ray, seg_leaf, t0, t1), z). reverse: leaves
+    around the ray origin are queried backwards along their chord."""
+    tr = traverse(rays, boxes, reverse)
     offsets, sr, sl, t0, t1 = tr
-    segs = segment_rows(rays, sr, t0, t1)
+    segs = segment_rows(rays, sr, t0, t1, sl)
     z = forward(cfg, params, segs) if segs.shape[0] else np.zeros((0, cfg.n_out))
-    return resolve(offsets, sl, t0, t1, z, cfg.n_out), tr, z
+    tmin = np.asarray(rays, dtype=np.float32)[:, 3]
+    return resolve(offsets, sl, t0, t1, z, cfg.n_out, tmin), tr, z

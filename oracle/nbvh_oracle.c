@@ -44,9 +44,11 @@ typedef struct {
 /* the slab; otherwise the two plane distances use the correctly rounded      */
 /* reciprocal of the direction, the near/far pair is ordered by the sign of   */
 /* that reciprocal, and the interval shrinks by max/min. Hit iff tn <= tf.    */
+/* *entry (if not NULL) receives where the ray's line enters the box: the     */
+/* largest near-plane distance, without tmin (-inf if no axis constrains).    */
 /* ------------------------------------------------------------------------ */
-static int oc_slab(const float* ray, const float* box, float* t0, float* t1) {
-  float tn = ray[3], tf = ray[7];
+static int oc_slab_entry(const float* ray, const float* box, float* t0, float* t1, float* entry) {
+  float tn = ray[3], tf = ray[7], te = -INFINITY;
   for (int a = 0; a < 3; ++a) {
     float o = ray[a], d = ray[4 + a];
     float lo = box[a], hi = box[3 + a];
@@ -63,11 +65,17 @@ static int oc_slab(const float* ray, const float* box, float* t0, float* t1) {
       tb = s;
     }
     tn = fmaxf(tn, ta);
+    te = fmaxf(te, ta);
     tf = fminf(tf, tb);
   }
   *t0 = tn;
   *t1 = tf;
+  if (entry) *entry = te;
   return tn <= tf;
+}
+
+static int oc_slab(const float* ray, const float* box, float* t0, float* t1) {
+  return oc_slab_entry(ray, box, t0, t1, NULL);
 }
 
 int oc_slab_one(const float* ray, const float* box, float* t01) {
@@ -89,19 +97,29 @@ void oc_traverse_count(const float* rays, int64_t n_rays, const float* boxes, in
 }
 
 /* Segment list of each ray in front-to-back order: sorted by entry distance,
- * equal entries by leaf id. offsets = exclusive prefix sum of the counts. */
+ * equal entries by leaf id. offsets = exclusive prefix sum of the counts.
+ * reverse != 0 (queries from inside a leaf, the commented-out "Depth
+ * estimation" passage of Sec. 6): a box whose chord starts before tmin holds
+ * the ray origin; its segment is the whole chord [entry, t1] and its leaf id
+ * carries the tag bit 2^31, so that it is queried backwards. */
+#define OC_INSIDE_TAG 0x80000000u
 void oc_traverse_fill(const float* rays, int64_t n_rays, const float* boxes, int64_t n_boxes,
                       const uint64_t* offsets, uint32_t* seg_ray, uint32_t* seg_leaf,
-                      float* seg_t0, float* seg_t1) {
+                      float* seg_t0, float* seg_t1, int reverse) {
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t r = 0; r < n_rays; ++r) {
     uint64_t k = offsets[r];
     for (int64_t b = 0; b < n_boxes; ++b) {
-      float t0, t1;
-      if (!oc_slab(rays + 8 * r, boxes + 6 * b, &t0, &t1)) continue;
+      float t0, t1, entry;
+      if (!oc_slab_entry(rays + 8 * r, boxes + 6 * b, &t0, &t1, &entry)) continue;
+      uint32_t id = (uint32_t)b;
+      if (reverse && entry < rays[8 * r + 3]) {
+        t0 = entry;
+        id |= OC_INSIDE_TAG;
+      }
       /* insertion into the sorted run [offsets[r], k) */
       uint64_t j = k;
-      while (j > offsets[r] && (seg_t0[j - 1] > t0 || (seg_t0[j - 1] == t0 && seg_leaf[j - 1] > (uint32_t)b))) {
+      while (j > offsets[r] && (seg_t0[j - 1] > t0 || (seg_t0[j - 1] == t0 && seg_leaf[j - 1] > id))) {
         seg_ray[j] = seg_ray[j - 1];
         seg_leaf[j] = seg_leaf[j - 1];
         seg_t0[j] = seg_t0[j - 1];
@@ -109,7 +127,7 @@ void oc_traverse_fill(const float* rays, int64_t n_rays, const float* boxes, int
         --j;
       }
       seg_ray[j] = (uint32_t)r;
-      seg_leaf[j] = (uint32_t)b;
+      seg_leaf[j] = id;
       seg_t0[j] = t0;
       seg_t1[j] = t1;
       ++k;
@@ -449,7 +467,7 @@ void oc_loss(const oc_cfg* c, const double* z, const float* labels, int64_t n, d
   loss_out[0] = w_hit * loss_out[1] + w_t * loss_out[2] + w_n * loss_out[3] + w_a * s_a / B;
 }
 
-/* Combined loss of each segment on its own (Sec. 5.3, "Node error": the
+/* Combined loss of each segment on its own (Sec. 5.1, "Node error": the
  * training loss q of a node is taken over the segments that train it):
  * out[i] = w_hit BCE + h (w_t |sigma(z1) - tau| + w_n (1/3) sum |n_hat - n|
  * + w_a relative L2 of the albedo), not divided by the batch size. */
@@ -603,11 +621,14 @@ void oc_adam(int64_t n, double* params, const double* grad, double* m, double* v
 /* 5.2 "Visibility": the segment is hit when the sigmoid output exceeds 0.5, */
 /* i.e. z0 > 0; "Intersection point": distance local to the segment). The    */
 /* ray's hit is the smallest t0 + sigmoid(z1) (t1 - t0) over its hit         */
-/* segments; equal t keeps the earlier segment. out rows: [t, n.xyz, leaf    */
-/* (as double, -1 = miss), seg index (-1), albedo.rgb].                      */
+/* segments; equal t keeps the earlier segment. A tagged (inside) segment   */
+/* was queried backwards from t1, so its local distance counts from t1:      */
+/* t = t1 - sigmoid(z1) (t1 - t0), and it is a hit only in front of the      */
+/* origin, t > tmin. out rows: [t, n.xyz, leaf (untagged, as double, -1 =    */
+/* miss), seg index (-1), albedo.rgb].                                       */
 /* ------------------------------------------------------------------------ */
 void oc_resolve(int64_t n_rays, const uint64_t* offsets, const uint32_t* seg_leaf, const float* seg_t0,
-                const float* seg_t1, const double* z, int n_out, double* out) {
+                const float* seg_t1, const double* z, int n_out, const float* ray_tmin, double* out) {
 #pragma omp parallel for schedule(static)
   for (int64_t r = 0; r < n_rays; ++r) {
     double best = INFINITY;
@@ -615,7 +636,14 @@ void oc_resolve(int64_t n_rays, const uint64_t* offsets, const uint32_t* seg_lea
     for (uint64_t k = offsets[r]; k < offsets[r + 1]; ++k) {
       const double* zk = z + (int64_t)n_out * (int64_t)k;
       if (!(zk[0] > 0.0)) continue;
-      double t = (double)seg_t0[k] + oc_sigmoid(zk[1]) * ((double)seg_t1[k] - (double)seg_t0[k]);
+      const double a = (double)seg_t0[k], b = (double)seg_t1[k], tau = oc_sigmoid(zk[1]);
+      double t;
+      if (seg_leaf[k] & OC_INSIDE_TAG) {
+        t = b - tau * (b - a);
+        if (!(t > (double)ray_tmin[r])) continue;
+      } else {
+        t = a + tau * (b - a);
+      }
       if (t < best) {
         best = t;
         bs = (int64_t)k;
@@ -633,7 +661,7 @@ void oc_resolve(int64_t n_rays, const uint64_t* offsets, const uint32_t* seg_lea
     o[1] = zk[2];
     o[2] = zk[3];
     o[3] = zk[4];
-    o[4] = (double)seg_leaf[bs];
+    o[4] = (double)(seg_leaf[bs] & ~OC_INSIDE_TAG);
     o[5] = (double)bs;
     if (n_out >= 8)
       for (int a = 0; a < 3; ++a) o[6 + a] = oc_sigmoid(zk[5 + a]);

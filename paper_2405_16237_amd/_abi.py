@@ -17,6 +17,8 @@ NBVH_FP32, NBVH_BF16, NBVH_FP8 = 0, 1, 2
 NBVH_FLAG_CAPACITY, NBVH_FLAG_NONFINITE = 1, 2
 NBVH_MAX_LEVELS = 32
 NBVH_MISS = 0xFFFFFFFF
+NBVH_INSIDE_CLIP, NBVH_INSIDE_REVERSE = 0, 1
+NBVH_SEG_INSIDE = 0x80000000
 
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "CAPACITY", 3: "NOT_BOUND", 4: "HIP", 5: "UNSUPPORTED"}
 
@@ -29,7 +31,7 @@ class NbvhConfig(ctypes.Structure):
         ("precision", ctypes.c_int32), ("scene_lo", ctypes.c_float * 3), ("scene_side", ctypes.c_float),
         ("w_hit", ctypes.c_float), ("w_t", ctypes.c_float), ("w_normal", ctypes.c_float), ("w_albedo", ctypes.c_float),
         ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
-        ("loss_scale", ctypes.c_float),
+        ("loss_scale", ctypes.c_float), ("inside_rule", ctypes.c_int32),
     ]
 
 

@@ -1,4 +1,4 @@
-"""Error-driven N-BVH construction (Sec. 5.3, "Error-driven construction").
+"""Error-driven N-BVH construction (Sec. 5.1, "Error-driven construction").
 
 The leaves of the N-BVH are a cut through the base BVH of the input geometry.
 The cut starts at the root and grows: the network trains on the current
@@ -10,13 +10,13 @@ reached; a final, longer training round follows.
 
 Training rays are drawn uniformly in the inflated root box with uniform
 directions, and each trains only the first leaf it crosses, kept with a
-probability that grows with that leaf's rank (Sec. 5.3, "Ray distribution").
+probability that grows with that leaf's rank (Sec. 5.2, "Ray distribution").
 The paper states it as max(r / r_max, 0.005); with r a sum of logarithms of
 numbers below one, r and r_max are negative and that ratio inverts the
 order, so the rank is used through exp(r - r_max) = q^2 p / (q^2 p)_max,
 which is 1 for the leaf of largest error and monotone in r.
 
-Levels of detail (Sec. 5.4): with lod_interval > 0 the current cut is
+Levels of detail (Sec. 5.3): with lod_interval > 0 the current cut is
 registered as a level of detail whenever that many training steps have run
 since the last one; each level is an N-BVH view over its cut that shares the
 one network. Every training step then picks one of the registered levels or

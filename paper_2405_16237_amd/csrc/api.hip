@@ -76,6 +76,8 @@ static nbvh_status make_devcfg(const nbvh_config* c, DevCfg* d) {
   if (c->n_out < 5 || c->n_out > 16) return set_error("n_out %d not in [5, 16]", c->n_out), NBVH_ERR_INVALID_ARG;
   if (c->precision != NBVH_FP32 && c->precision != NBVH_BF16 && c->precision != NBVH_FP8)
     return set_error("precision %d unknown", c->precision), NBVH_ERR_INVALID_ARG;
+  if (c->inside_rule != NBVH_INSIDE_CLIP && c->inside_rule != NBVH_INSIDE_REVERSE)
+    return set_error("inside_rule %d unknown", c->inside_rule), NBVH_ERR_INVALID_ARG;
   if (!(c->scene_side > 0.0f) || !std::isfinite(c->scene_side))
     return set_error("scene_side must be positive and finite"), NBVH_ERR_INVALID_ARG;
   memset(d, 0, sizeof(*d));
@@ -87,6 +89,7 @@ static nbvh_status make_devcfg(const nbvh_config* c, DevCfg* d) {
   d->width = W;
   d->hidden = c->mlp_hidden;
   d->n_out = c->n_out;
+  d->inside_reverse = c->inside_rule == NBVH_INSIDE_REVERSE;
   const uint64_t T = 1ull << c->log2_T;
   uint64_t off = 0;
   for (int l = 0; l < L; ++l) {
@@ -613,7 +616,8 @@ struct nbvh_batch {
 
 static bool same_shape(const nbvh_config& a, const nbvh_config& b) {
   if (a.n_levels != b.n_levels || a.n_features != b.n_features || a.n_samples != b.n_samples ||
-      a.mlp_width != b.mlp_width || a.mlp_hidden != b.mlp_hidden || a.n_out != b.n_out || a.precision != b.precision)
+      a.mlp_width != b.mlp_width || a.mlp_hidden != b.mlp_hidden || a.n_out != b.n_out || a.precision != b.precision ||
+      a.inside_rule != b.inside_rule)
     return false;
   for (int l = 0; l < a.n_levels; ++l)
     if (a.level_res[l] != b.level_res[l]) return false;

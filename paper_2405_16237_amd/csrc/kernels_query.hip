@@ -64,7 +64,7 @@ __host__ __device__ inline size_t query_lds_bytes(int n_in, int width) {
   const int ld0 = (n_in > width ? n_in : width) + Pad<AT>::v;
   const int ld1 = width + Pad<AT>::v;
   return (size_t)kQM * (ld0 + ld1) * sizeof(AT) + (size_t)kQM * kOutPad * 4 + (size_t)kQM * 32 + kQM * 4 + 16 +
-         (size_t)kQM * 4 * 12;
+         (size_t)kQM * 4 * 13;
 }
 
 // One object's query inputs.
@@ -108,6 +108,7 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
   float* s_bt = (float*)(s_bleaf + kQM);
   float* s_bn = s_bt + kQM;       // [3][kQM]
   float* s_ba = s_bn + 3 * kQM;   // [3][kQM]
+  float* s_tmin = s_ba + 3 * kQM;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t n_active = *J.n_active;
@@ -147,8 +148,12 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
             const float4 ra = rp[0], rb = rp[1];
             const nbvh_segment sg = J.segs[cur];
             s_leaf[lane] = sg.leaf;
-            sA[lane] = make_float4(ra.x, ra.y, ra.z, sg.t0);
-            sB[lane] = make_float4(rb.x, rb.y, rb.z, sg.t1);
+            s_tmin[lane] = ra.w;
+            // a leaf around the origin (reversed inside rule) is queried as the
+            // chord crossed backwards: origin o, direction -d, [-t1, -t0]
+            const bool in = (sg.leaf & NBVH_SEG_INSIDE) != 0u;
+            sA[lane] = make_float4(ra.x, ra.y, ra.z, in ? -sg.t1 : sg.t0);
+            sB[lane] = in ? make_float4(-rb.x, -rb.y, -rb.z, -sg.t0) : make_float4(rb.x, rb.y, rb.z, sg.t1);
           }
         }
         if (r0 + base + nfree < r1) break;  // this eighth still has rays
@@ -196,12 +201,17 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
       const float t0 = sA[lane].w, t1 = sB[lane].w;
       float best_t = s_bt[lane];
       const float* zr = z + lane * kOutPad;
+      const uint32_t leaf = s_leaf[lane];
+      const bool in = (leaf & NBVH_SEG_INSIDE) != 0u;
       if (zr[0] > 0.0f) {
-        const float t = t0 + sigmoidf_(zr[1]) * (t1 - t0);
-        if (t < best_t) {
+        // distance along the queried direction; a reversed chord's point is
+        // mapped back to the ray and counts only in front of the origin
+        const float tq = t0 + sigmoidf_(zr[1]) * (t1 - t0);
+        const float t = in ? -tq : tq;
+        if (t < best_t && (!in || t > s_tmin[lane])) {
           best_t = t;
           s_bt[lane] = t;
-          s_bleaf[lane] = s_leaf[lane];
+          s_bleaf[lane] = leaf & ~NBVH_SEG_INSIDE;
           s_bn[lane] = zr[2];
           s_bn[kQM + lane] = zr[3];
           s_bn[2 * kQM + lane] = zr[4];
@@ -217,9 +227,15 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
       bool more = false;
       if (cur < s_end[lane] && nxt.t0 < best_t) {
         more = true;
+        const bool nin = (nxt.leaf & NBVH_SEG_INSIDE) != 0u;
         s_leaf[lane] = nxt.leaf;
-        sA[lane].w = nxt.t0;
-        sB[lane].w = nxt.t1;
+        if (nin != in) {
+          sB[lane].x = -sB[lane].x;
+          sB[lane].y = -sB[lane].y;
+          sB[lane].z = -sB[lane].z;
+        }
+        sA[lane].w = nin ? -nxt.t1 : nxt.t0;
+        sB[lane].w = nin ? -nxt.t0 : nxt.t1;
       }
       if (!more) {
         float4* h = (float4*)(J.hits + ray);

@@ -958,7 +958,7 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ z, const
   }
 }
 
-// Per-leaf sums of the segment loss (Sec. 5.3, "Node error": a node's
+// Per-leaf sums of the segment loss (Sec. 5.1, "Node error": a node's
 // training loss q): the combined loss of each segment, unscaled and with the
 // loss weights, added to leaf_loss[leaf] with one count in leaf_count[leaf].
 __global__ __launch_bounds__(256) void k_leaf_loss(const float* __restrict__ z, const nbvh_label* __restrict__ labels,

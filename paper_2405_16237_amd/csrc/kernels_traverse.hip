@@ -33,9 +33,15 @@ __device__ inline RayPre load_ray(const nbvh_ray* rays, uint32_t r) {
   return R;
 }
 
-// hit iff tn <= tf; axis with zero direction: origin must lie in the slab
-__device__ inline bool slab(const RayPre& R, const float lo[3], const float hi[3], float& t0, float& t1) {
-  float tn = R.tmin, tf = R.tmax;
+// hit iff tn <= tf; axis with zero direction: origin must lie in the slab.
+// REV (reversed inside queries): `inside` is set when the ray's line enters
+// the box before tmin (entry te = the largest near-plane distance) and the
+// box is hit, i.e. the origin lies in the box; the interval is then the chord
+// [te, tf] instead of [tmin, tf].
+template <bool REV>
+__device__ inline bool slab(const RayPre& R, const float lo[3], const float hi[3], float& t0, float& t1,
+                            bool& inside) {
+  float tn = R.tmin, tf = R.tmax, te = -INFINITY;
   bool ok = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -50,19 +56,27 @@ __device__ inline bool slab(const RayPre& R, const float lo[3], const float hi[3
         tb = s;
       }
       tn = fmaxf(tn, ta);
+      if (REV) te = fmaxf(te, ta);
       tf = fminf(tf, tb);
     }
   }
-  t0 = tn;
+  const bool hit = ok && (tn <= tf);
+  inside = REV && hit && te < R.tmin;
+  t0 = inside ? te : tn;
   t1 = tf;
-  return ok && (tn <= tf);
+  return hit;
 }
 
-// Walk the tree; Emit(leaf, t0, t1) is called for every leaf crossed. The
+// leaf field of a segment: the leaf id, with NBVH_SEG_INSIDE for a reversed chord
+__device__ inline uint32_t seg_leaf(int32_t leaf, bool inside) {
+  return (uint32_t)leaf | (inside ? NBVH_SEG_INSIDE : 0u);
+}
+
+// Walk the tree; Emit(leaf, t0, t1, inside) is called for every leaf crossed. The
 // per-lane stack lives in LDS, entry i of this lane at stk[i * stride]
 // (lane-contiguous, so a wave's pushes and pops touch consecutive words);
 // it needs as many entries as the tree has inner levels.
-template <typename Emit>
+template <bool REV, typename Emit>
 __device__ inline void walk(const Node* __restrict__ nodes, const RayPre& R, Emit emit, int32_t* stk,
                             uint32_t stride) {
   int sp = 0;
@@ -74,16 +88,17 @@ __device__ inline void walk(const Node* __restrict__ nodes, const RayPre& R, Emi
     const float lo1[3] = {q1.z, q1.w, q2.x}, hi1[3] = {q2.y, q2.z, q2.w};
     const int32_t c0 = __float_as_int(q3.x), c1 = __float_as_int(q3.y);
     float a0, a1, b0, b1;
-    bool h0 = slab(R, lo0, hi0, a0, a1);
-    bool h1 = (c1 != kEmptyChild) && slab(R, lo1, hi1, b0, b1);
+    bool ia = false, ib = false;
+    bool h0 = slab<REV>(R, lo0, hi0, a0, a1, ia);
+    bool h1 = (c1 != kEmptyChild) && slab<REV>(R, lo1, hi1, b0, b1, ib);
     int32_t next = -1;
     if (h0) {
-      if (c0 < 0) emit(~c0, a0, a1);
+      if (c0 < 0) emit(~c0, a0, a1, ia);
       else next = c0;
     }
     if (h1) {
       if (c1 < 0) {
-        emit(~c1, b0, b1);
+        emit(~c1, b0, b1, ib);
       } else if (next < 0) {
         next = c1;
       } else {
@@ -134,6 +149,7 @@ __device__ inline void insert_staged(float* st, size_t plane, uint32_t k, int32_
 // kStage segments of ray r are also kept there, sorted, so that the
 // compaction after the scan need not walk the tree again.
 constexpr uint32_t kStage = 12;
+template <bool REV>
 __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
                                                         uint32_t n_rays, uint32_t* __restrict__ counts,
                                                         nbvh_hit* __restrict__ hits, uint32_t* __restrict__ active,
@@ -144,10 +160,10 @@ __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__
   if (r < n_rays) {
     RayPre R = load_ray(rays, r);
     float* run = staging ? staging + r : nullptr;
-    walk(
+    walk<REV>(
         nodes, R,
-        [&](int32_t leaf, float t0, float t1) {
-          if (run && cnt < kStage) insert_staged(run, n_rays, cnt, leaf, t0, t1);
+        [&](int32_t leaf, float t0, float t1, bool inside) {
+          if (run && cnt < kStage) insert_staged(run, n_rays, cnt, (int32_t)seg_leaf(leaf, inside), t0, t1);
           ++cnt;
         },
         s_stack + threadIdx.x, blockDim.x);
@@ -175,6 +191,7 @@ __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__
   }
 }
 
+template <bool REV>
 __global__ __launch_bounds__(256) void k_traverse_fill(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
                                                        uint32_t n_rays, const uint32_t* __restrict__ offsets,
                                                        nbvh_segment* __restrict__ segs, uint64_t capacity) {
@@ -186,21 +203,22 @@ __global__ __launch_bounds__(256) void k_traverse_fill(const Node* __restrict__ 
   if (beg == end) return;
   RayPre R = load_ray(rays, r);
   uint32_t k = beg;
-  walk(
+  walk<REV>(
       nodes, R,
-      [&](int32_t leaf, float t0, float t1) {
+      [&](int32_t leaf, float t0, float t1, bool inside) {
         // insertion into the sorted run [beg, k)
+        const uint32_t tag = seg_leaf(leaf, inside);
         uint32_t j = k;
         while (j > beg) {
           nbvh_segment prev = segs[j - 1];
-          if (prev.t0 > t0 || (prev.t0 == t0 && prev.leaf > (uint32_t)leaf)) {
+          if (prev.t0 > t0 || (prev.t0 == t0 && prev.leaf > tag)) {
             segs[j] = prev;
             --j;
           } else {
             break;
           }
         }
-        segs[j] = nbvh_segment{r, (uint32_t)leaf, t0, t1};
+        segs[j] = nbvh_segment{r, tag, t0, t1};
         ++k;
       },
       s_stack + threadIdx.x, blockDim.x);
@@ -208,6 +226,7 @@ __global__ __launch_bounds__(256) void k_traverse_fill(const Node* __restrict__ 
 
 // Compaction from the staging runs (rays with more than kStage segments walk
 // the tree again, as k_traverse_fill does).
+template <bool REV>
 __global__ __launch_bounds__(256) void k_traverse_compact(const Node* __restrict__ nodes,
                                                           const nbvh_ray* __restrict__ rays, uint32_t n_rays,
                                                           const uint32_t* __restrict__ offsets,
@@ -229,30 +248,32 @@ __global__ __launch_bounds__(256) void k_traverse_compact(const Node* __restrict
   }
   RayPre R = load_ray(rays, r);
   uint32_t k = beg;
-  walk(
+  walk<REV>(
       nodes, R,
-      [&](int32_t leaf, float t0, float t1) {
+      [&](int32_t leaf, float t0, float t1, bool inside) {
+        const uint32_t tag = seg_leaf(leaf, inside);
         uint32_t j = k;
         while (j > beg) {
           nbvh_segment prev = segs[j - 1];
-          if (prev.t0 > t0 || (prev.t0 == t0 && prev.leaf > (uint32_t)leaf)) {
+          if (prev.t0 > t0 || (prev.t0 == t0 && prev.leaf > tag)) {
             segs[j] = prev;
             --j;
           } else {
             break;
           }
         }
-        segs[j] = nbvh_segment{r, (uint32_t)leaf, t0, t1};
+        segs[j] = nbvh_segment{r, tag, t0, t1};
         ++k;
       },
       s_stack + threadIdx.x, blockDim.x);
 }
 
-// Training-ray selection (Sec. 5.3, "Ray distribution"): each ray trains only
+// Training-ray selection (Sec. 5.2, "Ray distribution"): each ray trains only
 // the first leaf it crosses (smallest t0, ties to the lower leaf id), and that
 // leaf is kept with probability accept[leaf] (kept iff u[r] < accept[leaf]).
 // Every leaf a ray crosses also counts one hit towards its hit-probability
-// estimate (Sec. 5.3, "Node error"). Kept segments are appended in wave order.
+// estimate (Sec. 5.1, "Node error"). Kept segments are appended in wave order.
+template <bool REV>
 __global__ __launch_bounds__(256) void k_first_hits(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
                                                     uint32_t n, const float* __restrict__ u,
                                                     const float* __restrict__ accept, nbvh_probe* __restrict__ probes,
@@ -260,20 +281,21 @@ __global__ __launch_bounds__(256) void k_first_hits(const Node* __restrict__ nod
                                                     uint32_t* __restrict__ leaf_hits) {
   extern __shared__ int32_t s_stack[];
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  bool take = false;
+  bool take = false, b_in = false;
   int32_t best = -1;
   float b0 = 0.f, b1 = 0.f;
   RayPre R;
   if (r < n) {
     R = load_ray(rays, r);
-    walk(
+    walk<REV>(
         nodes, R,
-        [&](int32_t leaf, float t0, float t1) {
+        [&](int32_t leaf, float t0, float t1, bool inside) {
           if (leaf_hits) atomicAdd(&leaf_hits[leaf], 1u);
           if (best < 0 || t0 < b0 || (t0 == b0 && leaf < best)) {
             best = leaf;
             b0 = t0;
             b1 = t1;
+            b_in = inside;
           }
         },
         s_stack + threadIdx.x, blockDim.x);
@@ -289,8 +311,13 @@ __global__ __launch_bounds__(256) void k_first_hits(const Node* __restrict__ nod
     if (take) {
       const uint32_t k = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
       float4* p = (float4*)(probes + k);
-      p[0] = make_float4(R.o[0], R.o[1], R.o[2], b0);
-      p[1] = make_float4(R.d[0], R.d[1], R.d[2], b1);
+      if (b_in) {  // the chord crossed backwards from its exit point
+        p[0] = make_float4(R.o[0], R.o[1], R.o[2], -b1);
+        p[1] = make_float4(-R.d[0], -R.d[1], -R.d[2], -b0);
+      } else {
+        p[0] = make_float4(R.o[0], R.o[1], R.o[2], b0);
+        p[1] = make_float4(R.d[0], R.d[1], R.d[2], b1);
+      }
       leaf_out[k] = (uint32_t)best;
     }
   }
@@ -304,8 +331,8 @@ nbvh_status launch_first_hits(const LaunchCtx& L, const nbvh_ray* rays, uint32_t
                               uint32_t* leaf_hits) {
   k_zero_u32<<<1, 64, 0, L.stream>>>(n_out, 1);
   if (n > 0)
-    k_first_hits<<<(n + 255) / 256, 256, stack_lds(L), L.stream>>>(L.nodes, rays, n, u, accept, probes, leaf_out, n_out,
-                                                        leaf_hits);
+    (L.cfg.inside_reverse ? k_first_hits<true> : k_first_hits<false>)<<<(n + 255) / 256, 256, stack_lds(L), L.stream>>>(
+        L.nodes, rays, n, u, accept, probes, leaf_out, n_out, leaf_hits);
   return check_launch("first_hits");
 }
 
@@ -415,8 +442,8 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
     k_zero_u32<<<1, 64, 0, L.stream>>>(n_active, 9);  // n_active and the query's 8 ray-queue counters
   }
   if (n_rays > 0)
-    k_traverse_count<<<grid, 256, stack_lds(L), L.stream>>>(L.nodes, rays, n_rays, scratch_counts, hits, active, n_active,
-                                                 segs ? staging : nullptr);
+    (L.cfg.inside_reverse ? k_traverse_count<true> : k_traverse_count<false>)<<<grid, 256, stack_lds(L), L.stream>>>(
+        L.nodes, rays, n_rays, scratch_counts, hits, active, n_active, segs ? staging : nullptr);
   const uint32_t n_tiles = (n_rays + kScanTile - 1) / kScanTile;
   if (n_rays > 0) k_scan_tiles<<<n_tiles, 256, 0, L.stream>>>(scratch_counts, n_rays, offsets, scratch_sums);
   k_scan_sums<<<1, 1024, 0, L.stream>>>(scratch_sums, n_tiles, scratch_total);
@@ -424,9 +451,12 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
                                                         L.state);
   if (segs && n_rays > 0) {
     if (staging)
-      k_traverse_compact<<<grid, 256, stack_lds(L), L.stream>>>(L.nodes, rays, n_rays, offsets, staging, segs, capacity);
+      (L.cfg.inside_reverse ? k_traverse_compact<true> : k_traverse_compact<false>)<<<grid, 256, stack_lds(L),
+                                                                                       L.stream>>>(
+          L.nodes, rays, n_rays, offsets, staging, segs, capacity);
     else
-      k_traverse_fill<<<grid, 256, stack_lds(L), L.stream>>>(L.nodes, rays, n_rays, offsets, segs, capacity);
+      (L.cfg.inside_reverse ? k_traverse_fill<true> : k_traverse_fill<false>)<<<grid, 256, stack_lds(L), L.stream>>>(
+          L.nodes, rays, n_rays, offsets, segs, capacity);
   }
   return check_launch("traverse");
 }

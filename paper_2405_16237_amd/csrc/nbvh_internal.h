@@ -49,6 +49,7 @@ struct DevCfg {
   uint64_t w_off[kMaxLayers];
   uint64_t wt_off[kMaxLayers];  // same layer, transposed copy, offset inside the aux arrays
   int32_t fan_in[kMaxLayers], fan_out[kMaxLayers];
+  int32_t inside_reverse;  // leaves containing the ray origin are queried along the reversed chord
 };
 
 // FP8 block of the auxiliary buffer, after the transposed FP32 and BF16

@@ -11,6 +11,7 @@ from . import _abi
 from ._abi import check
 
 PRECISIONS = {"fp32": _abi.NBVH_FP32, "bf16": _abi.NBVH_BF16, "fp8": _abi.NBVH_FP8}
+INSIDE_RULES = {"clip": _abi.NBVH_INSIDE_CLIP, "reverse": _abi.NBVH_INSIDE_REVERSE}
 
 
 def _ptr(t: torch.Tensor | None):
@@ -22,9 +23,10 @@ def _stream():
 
 
 def make_config(net, scene_lo, scene_side, precision="bf16", loss_weights=(2.0, 2.0, 1.0, 1.0), lr=1e-2,
-                beta1=0.9, beta2=0.99, eps=1e-8, loss_scale=1024.0) -> _abi.NbvhConfig:
+                beta1=0.9, beta2=0.99, eps=1e-8, loss_scale=1024.0, inside="clip") -> _abi.NbvhConfig:
     """net: object with n_levels, n_features, log2_T, n_samples, level_res,
-    mlp_width, mlp_hidden, n_out."""
+    mlp_width, mlp_hidden, n_out. inside: "clip" or "reverse", how a leaf
+    around the ray origin is queried (nbvh_inside_rule)."""
     c = _abi.NbvhConfig()
     c.n_levels, c.n_features, c.log2_T, c.n_samples = net.n_levels, net.n_features, net.log2_T, net.n_samples
     for i, r in enumerate(net.level_res):
@@ -36,6 +38,7 @@ def make_config(net, scene_lo, scene_side, precision="bf16", loss_weights=(2.0, 
     c.scene_side = float(np.float32(scene_side))
     c.w_hit, c.w_t, c.w_normal, c.w_albedo = loss_weights
     c.lr, c.beta1, c.beta2, c.eps, c.loss_scale = lr, beta1, beta2, eps, loss_scale
+    c.inside_rule = INSIDE_RULES[inside] if isinstance(inside, str) else int(inside)
     return c
 
 
@@ -163,7 +166,7 @@ class NBVH:
         """Another N-BVH over `leaf_boxes` bound to this one's buffers: the
         same hash grid, MLP, optimiser moments, gradient and device state
         (step count, loss scale, flags). This is how several tree cuts share
-        one network (levels of detail, Sec. 5.4): a training step through any
+        one network (levels of detail, Sec. 5.3): a training step through any
         view updates the one set of parameters. Launch knobs are copied. The
         view keeps this object alive. FP8 models have no views: whether their
         E4M3 weights match the parameters is tracked per tree, so a change

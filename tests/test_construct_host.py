@@ -1,4 +1,4 @@
-"""Host logic of the error-driven construction (Sec. 5.3) and the base BVH
+"""Host logic of the error-driven construction (Sec. 5.1) and the base BVH
 it cuts: ranking, acceptance, split choice and cut expansion on hand cases.
 CPU only."""
 import math

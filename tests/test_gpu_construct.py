@@ -1,6 +1,6 @@
 """Error-driven construction through the C ABI: first-hit training-ray
 selection and per-leaf losses against the oracle, then a small construction
-run (Sec. 5.3) on the 20,480-triangle mesh."""
+run (Sec. 5.1) on the 20,480-triangle mesh."""
 import sys
 
 import numpy as np
@@ -171,7 +171,7 @@ def test_view_shares_the_network(lib, c1):
 
 
 def test_levels_of_detail(lib, c1):
-    """Construction with levels of detail (Sec. 5.4): several cuts of one
+    """Construction with levels of detail (Sec. 5.3): several cuts of one
     base BVH, coarse to fine, trained together on one network. Every level
     is a cut, answers camera rays well, and the coarser levels cross fewer
     leaves per ray."""

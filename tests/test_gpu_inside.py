@@ -1,0 +1,140 @@
+"""Queries from inside a leaf under the reverse rule (a leaf around the ray
+origin is queried backwards along its chord): traversal, first-hit training
+segments and full queries through the C ABI against the oracle, on bounce
+rays leaving the 20,480-triangle mesh mixed with camera rays."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from nbvh_synth import configs, scene
+
+pytestmark = pytest.mark.gpu
+TAG = oracle.INSIDE_TAG
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_16237_amd as P
+    P.load()
+    return P
+
+
+@pytest.fixture(scope="module")
+def c1():
+    sc = configs.make_scene(20480, 64)
+    primary = scene.pinhole_rays(160, 160)
+    g = scene.ray_ground_truth(sc.mesh, primary)
+    hit = g["hit"]
+    pts = primary[hit, 0:3].astype(np.float64) + g["t"][hit, None] * primary[hit, 4:7].astype(np.float64)
+    bounce = scene.cosine_bounces(pts, g["n"][hit], 30_000 + 37, seed=91, offset=1e-4 * sc.diagonal)
+    rays = np.concatenate([bounce, primary[:5000]])
+    return sc, rays
+
+
+def test_traverse_reverse_bit_exact(lib, c1):
+    sc, rays_np = c1
+    m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="fp32", inside="reverse")
+    off_o, sr, sl, t0, t1 = oracle.traverse(rays_np, sc.boxes, reverse=True)
+    assert ((sl & TAG) != 0).sum() > 20_000
+    _say("reverse traversal", rays_np.shape)
+    off_g, segs = m.traverse(torch.from_numpy(rays_np).cuda(), int(off_o[-1]) + 16)
+    torch.cuda.synchronize()
+    assert np.array_equal(off_g.cpu().numpy().astype(np.uint64), off_o)
+    sg = segs[: int(off_o[-1])].cpu().numpy()
+    assert np.array_equal(sg[:, 0].astype(np.uint32), sr)
+    assert np.array_equal(sg[:, 1].view(np.uint32), sl)
+    assert np.array_equal(sg[:, 2].view(np.float32), t0)
+    assert np.array_equal(sg[:, 3].view(np.float32), t1)
+
+
+def test_first_hits_reverse_bit_exact(lib, c1):
+    sc, rays_np = c1
+    m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="fp32", inside="reverse")
+    rng = np.random.default_rng(92)
+    u = rng.uniform(size=rays_np.shape[0]).astype(np.float32)
+    accept = rng.uniform(0.3, 1.0, size=sc.boxes.shape[0]).astype(np.float32)
+    _say("reverse first hits")
+    probes, leaf = m.first_hits(torch.from_numpy(rays_np).cuda(), torch.from_numpy(u).cuda(),
+                                torch.from_numpy(accept).cuda())
+    rows, oleaf = oracle.first_hit_probes(rays_np, sc.boxes, u, accept, reverse=True)
+    p = probes.cpu().numpy()
+    lf = leaf.cpu().numpy().astype(np.int64)
+    assert p.shape[0] == rows.shape[0] > 10_000
+    kg = np.lexsort(p.view(np.int32).T[::-1])
+    ko = np.lexsort(rows.view(np.int32).T[::-1])
+    assert np.array_equal(p[kg].view(np.int32), rows[ko].view(np.int32))
+    assert np.array_equal(lf[kg], oleaf[ko])
+    assert (rows[:, 3] < 0).sum() > 5000  # reversed chords start behind the origin
+
+
+def _compare(lib, c1, precision, params, band):
+    sc, rays_np = c1
+    net = configs.C1_NET
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision=precision, inside="reverse")
+    m.set_params(params)
+    _say("reverse query", precision, rays_np.shape)
+    h = m.query(torch.from_numpy(rays_np).cuda()).cpu().numpy()
+    pref = params if precision == "fp32" else torch.from_numpy(params).to(torch.bfloat16).float().numpy()
+    out, tr, z = oracle.query(oracle.make_cfg(net, sc.lo, sc.side), pref.astype(np.float64), rays_np, sc.boxes,
+                              reverse=True)
+    off, sr, sl, t0, t1 = tr
+    # unambiguous rays: every logit clear of 0 and every reversed hit clear of the origin
+    tau = 1.0 / (1.0 + np.exp(-z[:, 1]))
+    a, b = t0.astype(np.float64), t1.astype(np.float64)
+    t_rev = b - tau * (b - a)
+    tmin = rays_np[sr, 3].astype(np.float64)
+    bad = np.abs(z[:, 0]) <= band * np.maximum(1.0, np.abs(z[:, 0]))
+    bad |= ((sl & TAG) != 0) & (np.abs(t_rev - tmin) <= 10 * band * np.maximum(1.0, np.abs(b - a)))
+    clear = np.ones(rays_np.shape[0], bool)
+    clear[np.unique(sr[bad])] = False
+    leaf = h[:, 7].view(np.uint32).astype(np.int64)
+    leaf[leaf == 0xFFFFFFFF] = -1
+    agree = leaf[clear] == out[clear, 4].astype(np.int64)
+    return h, out, clear, agree
+
+
+def test_query_reverse_fp32(lib, c1):
+    net = configs.C1_NET
+    params = configs.init_params(net, "uniform", 1.0, seed_features=93, seed_mlp=94)
+    h, out, clear, agree = _compare(lib, c1, "fp32", params, 1e-4)
+    assert clear.mean() > 0.9 and agree.mean() >= 0.999, (clear.mean(), agree.mean())
+    same = clear & (out[:, 4] >= 0) & (h[:, 7].view(np.uint32).astype(np.int64) == out[:, 4].astype(np.int64))
+    assert same.sum() > 2000
+    dt = np.abs(h[same, 0] - out[same, 0]) / np.maximum(1.0, np.abs(out[same, 0]))
+    assert dt.max() <= 1e-5, dt.max()
+    # some reversed hits are in front of the origin, some behind it
+    assert (out[:, 4] >= 0).mean() > 0.05 and (out[:, 4] < 0).mean() > 0.05
+
+
+def test_query_reverse_bf16(lib, c1):
+    net = configs.C1_NET
+    params = configs.init_params(net, "uniform", 1.0, seed_features=95, seed_mlp=96)
+    sc = c1[0]
+    h, out, clear, agree = _compare(lib, c1, "bf16", params, 2e-2)
+    assert agree.mean() >= 0.995, agree.mean()
+    same = clear & (out[:, 4] >= 0) & (h[:, 7].view(np.uint32).astype(np.int64) == out[:, 4].astype(np.int64))
+    assert np.abs(h[same, 0] - out[same, 0]).mean() <= 1e-3 * sc.diagonal
+
+
+def test_clip_and_reverse_agree_on_camera_rays(lib, c1):
+    """Camera rays start outside every leaf: both rules give identical hits."""
+    sc, rays_np = c1
+    cam = torch.from_numpy(rays_np[-5000:].copy()).cuda()
+    params = configs.init_params(configs.C1_NET, "uniform", 1.0, seed_features=97, seed_mlp=98)
+    hs = []
+    for rule in ("clip", "reverse"):
+        m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="bf16", inside=rule)
+        m.set_params(params)
+        hs.append(m.query(cam).cpu().numpy())
+    assert np.array_equal(hs[0].view(np.uint32), hs[1].view(np.uint32))

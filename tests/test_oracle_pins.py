@@ -588,3 +588,128 @@ def test_labels_sphere_within_sagitta():
     assert r["t"].max() <= 1.0 + 1e-12 and r["t"].min() >= math.cos(rho) - 1e-12
     # normals point outward
     assert (np.einsum("ij,ij->i", r["n"], d) > 0).all()
+
+
+# ---------------------------------------------------------------- queries from inside a leaf (reversed chords)
+TAG = oracle.INSIDE_TAG
+
+
+def test_reverse_traversal_closed_form():
+    """+z ray from the centre of the unit cube: the clip rule gives [0, 0.5];
+    the reverse rule gives the whole chord [-0.5, 0.5], tagged. A ray from
+    outside gets [2, 3] under both rules."""
+    box = np.array([[0, 0, 0, 1, 1, 1]], dtype=np.float32)
+    rays = np.array([[0.5, 0.5, 0.5, 0, 0, 0, 1, np.inf],
+                     [0.5, 0.5, -2.0, 0, 0, 0, 1, np.inf]], dtype=np.float32)
+    off, sr, sl, t0, t1 = oracle.traverse(rays, box)
+    assert sl.tolist() == [0, 0] and t0.tolist() == [0.0, 2.0] and t1.tolist() == [0.5, 3.0]
+    off, sr, sl, t0, t1 = oracle.traverse(rays, box, reverse=True)
+    assert sl.tolist() == [TAG, 0] and t0.tolist() == [-0.5, 2.0] and t1.tolist() == [0.5, 3.0]
+    # tmin > 0 moves the origin along the ray: from z = 0.5 + 0.25 the chord is unchanged
+    r = rays[:1].copy()
+    r[0, 3] = 0.25
+    _, _, sl, t0, t1 = oracle.traverse(r, box, reverse=True)
+    assert sl.tolist() == [TAG] and t0.tolist() == [-0.5] and t1.tolist() == [0.5]
+
+
+def test_reverse_rule_changes_only_boxes_around_the_origin():
+    """Segments of boxes that do not contain the origin are the same under
+    both rules; boxes that do get the chord start (entry < tmin) and the tag,
+    and the run is still sorted by (t0, tagged id)."""
+    rng = np.random.default_rng(31)
+    rays, boxes = _random_rays_boxes(rng, 400, 40)
+    rays[:, 0:3] = rng.uniform(-0.5, 0.5, size=(400, 3))  # many origins inside boxes
+    a = oracle.traverse(rays, boxes)
+    b = oracle.traverse(rays, boxes, reverse=True)
+    assert np.array_equal(a[0], b[0])
+    n_in = 0
+    for i, r in enumerate(rays):
+        sa = {(int(l), float(x), float(y)) for l, x, y in zip(*(v[a[0][i]:a[0][i + 1]] for v in a[2:]))}
+        sb = list(zip(*(v[b[0][i]:b[0][i + 1]] for v in b[2:])))
+        assert sorted(sb, key=lambda s: (float(s[1]), int(s[0]))) == sb
+        for l, x, y in sb:
+            l = int(l)
+            if l & TAG:
+                n_in += 1
+                lo, hi = boxes[l & ~TAG, :3], boxes[l & ~TAG, 3:]
+                assert np.all(r[0:3] >= lo) and np.all(r[0:3] <= hi)  # origin in the box
+                assert x < r[3] and (l & ~TAG, float(r[3]), float(y)) in sa
+                # the chord's entry point lies on the box surface
+                p = r[0:3].astype(np.float64) + float(x) * r[4:7].astype(np.float64)
+                assert np.min(np.minimum(np.abs(p - lo), np.abs(p - hi))) < 1e-5
+            else:
+                assert (l, float(x), float(y)) in sa
+    assert n_in > 50
+
+
+def test_reversed_rows_sample_the_chord_backwards():
+    """A tagged segment's probe row is the ray (o, -d) over [-t1, -t0]: its
+    sample points are the forward chord's in the opposite order."""
+    net = Net(2, 2, 10, 4, [4, 8])
+    cfg = oracle.make_cfg(net, np.zeros(3, np.float32), np.float32(2.0))
+    rays = np.array([[0.7, 0.9, 1.1, 0, 0.3, 0.4, 0.5, np.inf]], dtype=np.float32)
+    fwd = oracle.segment_rows(rays, np.array([0]), np.array([-0.8], np.float32), np.array([0.6], np.float32))
+    rev = oracle.segment_rows(rays, np.array([0]), np.array([-0.8], np.float32), np.array([0.6], np.float32),
+                              np.array([TAG], np.uint32))
+    assert rev[0, 3] == np.float32(-0.6) and rev[0, 7] == np.float32(0.8)
+    assert np.array_equal(rev[0, 4:7], -rays[0, 4:7])
+    xf = oracle.sample_positions(cfg, fwd)[0]
+    xr = oracle.sample_positions(cfg, rev)[0]
+    assert np.abs(xr - xf[::-1]).max() < 1e-6
+
+
+def test_resolve_reversed_hand_cases():
+    """A tagged segment's hit lies at t1 - sigmoid(z1) (t1 - t0) and counts
+    only in front of the origin (t > tmin); the leaf is reported untagged."""
+    logit = lambda p: math.log(p / (1 - p))
+    offsets = np.array([0, 2, 3, 4], dtype=np.uint64)
+    leaf = np.array([5 | TAG, 6, 8 | TAG, 9 | TAG], dtype=np.uint32)
+    t0 = np.array([-1.0, 0.5, -1.0, -2.0], dtype=np.float32)
+    t1 = np.array([1.0, 3.0, 1.0, 2.0], dtype=np.float32)
+    z = np.zeros((4, 5))
+    z[:, 0] = 1.0
+    z[:, 1] = [logit(0.25), logit(0.5), logit(0.75), logit(0.5)]
+    tmin = np.array([0.0, 0.0, 0.0], dtype=np.float32)
+    out = oracle.resolve(offsets, leaf, t0, t1, z, 5, tmin)
+    # ray 0: tagged 1 - 0.25*2 = 0.5 ahead of 0; the untagged segment gives 1.75 -> 0.5, leaf 5
+    assert abs(out[0, 0] - 0.5) < 1e-15 and out[0, 4] == 5 and out[0, 5] == 0
+    # ray 1: 1 - 0.75*2 = -0.5 is behind the origin -> miss
+    assert out[1, 4] == -1
+    # ray 2: 2 - 0.5*4 = 0 is not in front of tmin = 0 -> miss
+    assert out[2, 4] == -1
+
+
+def test_reverse_rule_with_exact_outputs_matches_ground_truth():
+    """With network outputs read off the exact labels of each queried
+    segment, the reverse rule returns the first surface point in front of the
+    origin for secondary rays leaving a surface that crosses the leaf once:
+    a square (two triangles) in the middle of a unit box, rays starting just
+    above it. Rays pointing down hit it; rays pointing up miss it (the only
+    crossing of their chord lies behind the origin)."""
+    verts = np.array([[0.1, 0.1, 0.5], [0.9, 0.1, 0.5], [0.9, 0.9, 0.5], [0.1, 0.9, 0.5]])
+    tris = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    mesh = scene.TriangleMesh(verts, tris)
+    box = np.array([[0, 0, 0, 1, 1, 1]], dtype=np.float32)
+    rng = np.random.default_rng(33)
+    n = 400
+    rays = np.zeros((n, 8), dtype=np.float32)
+    rays[:, 0:2] = rng.uniform(0.3, 0.7, size=(n, 2))
+    rays[:, 2] = 0.5 + 1e-3
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rays[:, 4:7] = d
+    rays[:, 7] = np.inf
+    off, sr, sl, t0, t1 = oracle.traverse(rays, box, reverse=True)
+    assert np.all(sl == TAG)
+    rows = oracle.segment_rows(rays, sr, t0, t1, sl)
+    lab = scene.probe_labels(mesh, rows)
+    tau = np.clip(lab[:, 0].astype(np.float64), 1e-12, 1 - 1e-12)
+    z = np.zeros((rows.shape[0], 5))
+    z[:, 0] = np.where(lab[:, 4] > 0, 10.0, -10.0)
+    z[:, 1] = np.log(tau / (1 - tau))
+    z[:, 2:5] = lab[:, 1:4]
+    out = oracle.resolve(off, sl, t0, t1, z, 5, rays[:, 3])
+    gt = scene.ray_ground_truth(mesh, rays)
+    got_hit = out[:, 4] >= 0
+    assert np.array_equal(got_hit, gt["hit"]) and 0.2 < gt["hit"].mean() < 0.8
+    assert np.abs(out[got_hit, 0] - gt["t"][got_hit]).max() < 1e-6
