@@ -91,6 +91,7 @@ def build_frame(configs, scene):
     W.params0 = configs.init_params(W.net, "normal", 1e-2)
     W.per_leaf = 256
     W.inside_fraction = 0.0
+    W.inside = "clip"  # camera rays start outside every leaf
     W.seg_cap_per_ray = 16
     W.describe = ("1920x1080 primary rays on a 1,003,520-triangle displaced icosphere, 1,024 neural leaves; "
                   "hash grid L=16 F=2 T=2^19, 8 samples/segment, MLP 256-4x128-5; train batch 2^18 probes")
@@ -99,7 +100,7 @@ def build_frame(configs, scene):
     return W
 
 
-def build_secondary(configs, scene):
+def build_secondary(configs, scene, inside="reverse", offset=1e-4):
     W = Workload()
     W.name = "secondary"
     W.sc = configs.make_scene(3_996_180, 16384, albedo_seed=scene.SEED_ALBEDO)
@@ -108,19 +109,28 @@ def build_secondary(configs, scene):
     hit = g["hit"]
     pts = primary[hit, 0:3].astype(np.float64) + g["t"][hit, None] * primary[hit, 4:7].astype(np.float64)
     W.rays = scene.cosine_bounces(pts, g["n"][hit], 1 << 24, seed=scene.SEED_SECONDARY,
-                                  offset=1e-4 * W.sc.diagonal)
+                                  offset=offset * W.sc.diagonal)
     # ground truth on every 16th ray
     W.gt_idx = np.arange(0, W.rays.shape[0], 16)
     W.gt = scene.ray_ground_truth(W.sc.mesh, W.rays[W.gt_idx])
     W.net = configs.C5_NET
     W.params0 = configs.init_params(W.net, "normal", 1e-2)
     W.per_leaf = 16
-    W.inside_fraction = 0.5  # half the probes start inside their leaf, as the bounce rays do
+    W.inside = inside
     W.seg_cap_per_ray = 8
+    if inside == "reverse":
+        # the leaf around each bounce origin is queried backwards along its
+        # chord, so training needs only whole chords, as for camera rays
+        W.inside_fraction = 0.0
+        how = "leaves around the origin queried along the reversed chord; train batch 2^18 whole-chord probes"
+    else:
+        W.inside_fraction = 0.5  # half the probes start inside their leaf, as the bounce rays do
+        how = ("leaves around the origin queried from the origin on; train batch 2^18 probes, half of them "
+               "starting inside their leaf")
     W.describe = ("2^24 cosine-weighted bounce rays from the 1920x1080 frame's primary hits on a 3,996,180-triangle "
                   "displaced icosphere with per-vertex albedo, 16,384 neural leaves; hash grid L=16 F=4 T=2^22, "
-                  "4 samples/segment, MLP 256-4x256-8 (hit, t, normal, albedo); train batch 2^18 probes, half of "
-                  "them starting inside their leaf")
+                  "4 samples/segment, MLP 256-4x256-8 (hit, t, normal, albedo); origins offset by %g of the scene "
+                  "diagonal along the normal; " % offset + how)
     W.cpu_sample = lambda stride: (W.rays[::stride * stride * 16], "every %dth ray" % (stride * stride * 16))
     return W
 
@@ -169,7 +179,7 @@ def run_single(args, W, P, torch, configs, scene):
         h = hits.cpu().numpy()
         return hit_error(h if W.gt_idx is None else h[W.gt_idx], W.gt, sc.diagonal)
 
-    bf = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", loss_scale=1024.0)
+    bf = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", loss_scale=1024.0, inside=W.inside)
     bf.set_params(W.params0)
     bf.workspace(R, seg_cap, B)
     # pre-training (untimed): the trained network of the training workload
@@ -220,7 +230,7 @@ def run_single(args, W, P, torch, configs, scene):
     # FP32 path with the same trained parameters
     fp32 = None
     if not args.no_fp32:
-        fp = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32", loss_scale=1024.0)
+        fp = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32", loss_scale=1024.0, inside=W.inside)
         fp.set_params(trained)
         fp.workspace(R, seg_cap, B)
         hits_fp = torch.empty((R, 8), dtype=torch.float32, device="cuda")
@@ -238,7 +248,7 @@ def run_single(args, W, P, torch, configs, scene):
     # calibrated on 2^16 seeded probe segments
     fp8 = None
     if not args.no_fp8:
-        f8 = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp8")
+        f8 = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp8", inside=W.inside)
         f8.set_params(trained)
         f8.calibrate_fp8(batches[0][0][: 1 << 16].contiguous())
         f8.workspace(R, seg_cap, 0)
@@ -263,14 +273,14 @@ def run_single(args, W, P, torch, configs, scene):
         stride = 16
         sample, what = W.cpu_sample(stride)
         t2 = time.time()
-        oracle.query(cfg, params, sample, sc.boxes)
+        oracle.query(cfg, params, sample, sc.boxes, W.inside == "reverse")
         dt = time.time() - t2
         # grow the sample towards the target time
         if dt < args.cpu_seconds / 2 and stride > 1:
             stride = max(1, int(stride / np.sqrt(args.cpu_seconds / max(dt, 1e-3))))
             sample, what = W.cpu_sample(stride)
             t2 = time.time()
-            oracle.query(cfg, params, sample, sc.boxes)
+            oracle.query(cfg, params, sample, sc.boxes, W.inside == "reverse")
             dt = time.time() - t2
         cpu = dict(value=sample.shape[0] / dt, unit="rays/s", cores=oracle.num_threads(), kind="oracle",
                    sample="%s (%d rays), full query in FP64 (every-leaf traversal, encode, MLP, resolve), %.1f s"
@@ -470,6 +480,10 @@ def main():
     ap.add_argument("--pretrain", type=int, default=600, help="untimed BF16 training steps before timing")
     ap.add_argument("--batches", type=int, default=4, help="distinct 2^18-probe batches cycled in training")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--inside", choices=("reverse", "clip"), default="reverse",
+                    help="secondary workload: how a leaf around a bounce origin is queried")
+    ap.add_argument("--bounce-offset", type=float, default=1e-4,
+                    help="secondary workload: origin offset along the normal, in scene diagonals")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true")
@@ -495,7 +509,8 @@ def main():
     if args.workload == "batched":
         out = run_batched(args, P, torch, configs, scene)
     else:
-        W = build_frame(configs, scene) if args.workload == "frame" else build_secondary(configs, scene)
+        W = build_frame(configs, scene) if args.workload == "frame" else build_secondary(configs, scene, args.inside,
+                                                                                           args.bounce_offset)
         out = run_single(args, W, P, torch, configs, scene)
     print(json.dumps(out), flush=True)
 
