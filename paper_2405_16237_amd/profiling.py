@@ -6,6 +6,7 @@ readings can be matched with the code they were taken on.
     python -m paper_2405_16237_amd.profiling stats --trace DIR --out FILE --command CMD
     python -m paper_2405_16237_amd.profiling traffic --fetch DIR --write DIR --copy-mib N \
         --out FILE --command-fetch CMD --command-write CMD
+    python -m paper_2405_16237_amd.profiling counters --pmc DIR [DIR ...] --out FILE --command CMD ...
 
 FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch; what one KiB of
 a counter means in bytes moved is taken from the copy kernel (an elementwise
@@ -157,6 +158,50 @@ def write_stats(path: str, stats, command: str, top: int = 40):
             f.write("| `%s` | %d | %.1f | %.2f |\n" % (name.replace("|", "/"), calls, total, avg))
 
 
+def pmc_all(pmc_dir: str) -> dict:
+    """{kernel: {counter: (dispatches, mean value)}} of every counter of a --pmc run."""
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for f in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            vals[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return {k: {c: (len(v), sum(v) / len(v)) for c, v in cs.items()} for k, cs in vals.items()}
+
+
+def write_counters(path: str, dirs: list, commands: list, n_cu: int = 256):
+    """Per-kernel means of the counters of several --pmc runs, with the
+    per-compute-unit busy fractions that say what bounds a kernel: TA/TD busy
+    cycles and stalls are summed over the compute units, GRBM_GUI_ACTIVE over
+    the 8 accelerator dies."""
+    merged = collections.defaultdict(dict)
+    for d in dirs:
+        for k, cs in pmc_all(d).items():
+            merged[k].update(cs)
+    with open(path, "w") as f:
+        f.write("# rocprofv3 --pmc: per-dispatch means of hardware counters\n")
+        for c in commands:
+            f.write("command: %s\n" % c)
+        f.write("source_digest: %s\n\n" % source_digest())
+        for k in sorted(merged):
+            cs = merged[k]
+            f.write("## `%s`\n\n| counter | dispatches | mean per dispatch |\n|---|---|---|\n" % k)
+            for c in sorted(cs):
+                f.write("| %s | %d | %.4g |\n" % (c, cs[c][0], cs[c][1]))
+            if "GRBM_GUI_ACTIVE" in cs:
+                cyc = cs["GRBM_GUI_ACTIVE"][1] / 8.0
+                f.write("\nkernel cycles per die: %.4g\n" % cyc)
+                for c in ("TD_TD_BUSY_sum", "TA_TA_BUSY_sum", "TA_ADDR_STALLED_BY_TC_CYCLES_sum", "TD_TC_STALL_sum",
+                          "TCP_PENDING_STALL_CYCLES_sum"):
+                    if c in cs:
+                        f.write("%s per compute unit: %.2f of the kernel's cycles\n" % (c, cs[c][1] / n_cu / cyc))
+            if "TCP_TOTAL_CACHE_ACCESSES_sum" in cs and "TCP_TCC_READ_REQ_sum" in cs:
+                f.write("L1 miss fraction (TCP_TCC_READ_REQ / TCP_TOTAL_CACHE_ACCESSES): %.3f\n"
+                        % (cs["TCP_TCC_READ_REQ_sum"][1] / cs["TCP_TOTAL_CACHE_ACCESSES_sum"][1]))
+            if "TCC_HIT_sum" in cs and "TCC_MISS_sum" in cs:
+                h, m = cs["TCC_HIT_sum"][1], cs["TCC_MISS_sum"][1]
+                f.write("L2 hit fraction: %.3f\n" % (h / (h + m)))
+            f.write("\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -171,7 +216,14 @@ def main():
     t.add_argument("--out", required=True)
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--pmc", nargs="+", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", action="append", required=True)
     a = ap.parse_args()
+    if a.cmd == "counters":
+        write_counters(a.out, a.pmc, a.command)
+        return
     if a.cmd == "stats":
         write_stats(a.out, kernel_stats(a.trace), a.command)
     else:
