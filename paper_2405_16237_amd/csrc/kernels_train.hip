@@ -398,6 +398,93 @@ __global__ __launch_bounds__(256) void k_wgrad(DevCfg c, WTiles tiles, TrainPtrs
   }
 }
 
+// BF16 weight gradient, one workgroup per (layer, 128-column input slice,
+// split): 8 waves own all output rows (wave w: row tiles w and w + 8), the
+// split's h_k^T rows of the slice are staged in LDS 32 batch entries at a time
+// (double-buffered) and shared by the waves, so every h_k^T and g_k^T element
+// is read from memory once per slice.
+constexpr int kWgCols = 128;       // input columns per workgroup
+constexpr int kWgLd = 40;          // LDS row stride (bf16): 80 B keeps 16-lane phases conflict-free
+struct WSlices {
+  int16_t layer[64], i0[64];
+  int n;
+};
+
+__global__ __launch_bounds__(512) void k_wgrad_rows(DevCfg c, WSlices sl, TrainPtrs P, uint32_t kb, int nsplit,
+                                                    float* __restrict__ wpart) {
+  __shared__ __align__(16) bf16 stage[2][kWgCols * kWgLd];
+  const int k = sl.layer[blockIdx.x], i0 = sl.i0[blockIdx.x];
+  const int split = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int fo_pad = fan_out_pad(c, k), fi = c.fan_in[k];
+  const int ncols = min(kWgCols, fi - i0);
+  const uint64_t ldb = P.ldb;
+  const uint32_t chunk = (kb / nsplit + 31) / 32 * 32;
+  const uint32_t b_beg = min(kb, split * chunk);
+  const uint32_t b_end = min(kb, b_beg + chunk);
+  const int n_it = (int)((b_end - b_beg) / 32);
+  const bf16* gT = (const bf16*)P.gT[k];
+  const bf16* hT = (const bf16*)P.hT[k];
+  // staging role: row sr of the slice, 8 batch entries at 8 * sp
+  const int sr = tid >> 2, sp = tid & 3;
+  const bool s_ok = sr < ncols;
+  const bf16* s_src = hT + (size_t)(i0 + (s_ok ? sr : 0)) * ldb + 8 * sp;
+  bf16* s_dst0 = &stage[0][sr * kWgLd + 8 * sp];
+  bf16* s_dst1 = &stage[1][sr * kWgLd + 8 * sp];
+  // compute role: row tiles wave and wave + 8
+  const bool rt0 = 16 * wave < fo_pad, rt1 = 16 * (wave + 8) < fo_pad;
+  const bf16* a_src0 = gT + (size_t)(16 * wave + r16) * ldb + 8 * q;
+  const bf16* a_src1 = gT + (size_t)(16 * (wave + 8) + r16) * ldb + 8 * q;
+  f32x4 acc0[8], acc1[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc0[j] = acc1[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (n_it > 0) {
+    const bf16x8 h = s_ok ? *(const bf16x8*)(s_src + b_beg) : zero_bf16x8();
+    if (sr < kWgCols) *(bf16x8*)s_dst0 = h;
+  }
+  bf16x8 a0 = (n_it > 0 && rt0) ? *(const bf16x8*)(a_src0 + b_beg) : zero_bf16x8();
+  bf16x8 a1 = (n_it > 0 && rt1) ? *(const bf16x8*)(a_src1 + b_beg) : zero_bf16x8();
+  __syncthreads();
+  for (int it = 0; it < n_it; ++it) {
+    const uint32_t b = b_beg + 32u * (uint32_t)it;
+    const bool more = it + 1 < n_it;
+    // the next slice of h^T and g^T travels while this one multiplies
+    bf16x8 hn = zero_bf16x8(), an0 = zero_bf16x8(), an1 = zero_bf16x8();
+    if (more && s_ok) hn = *(const bf16x8*)(s_src + b + 32);
+    if (more && rt0) an0 = *(const bf16x8*)(a_src0 + b + 32);
+    if (more && rt1) an1 = *(const bf16x8*)(a_src1 + b + 32);
+    const bf16* cur = stage[it & 1];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (16 * j < ncols) {
+        const bf16x8 bv = *(const bf16x8*)(cur + (16 * j + r16) * kWgLd + 8 * q);
+        if (rt0) acc0[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc0[j], 0, 0, 0);
+        if (rt1) acc1[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv, acc1[j], 0, 0, 0);
+      }
+    }
+    if (more) *(bf16x8*)((it & 1) ? s_dst0 : s_dst1) = hn;
+    a0 = an0;
+    a1 = an1;
+    __syncthreads();
+  }
+  const uint64_t span = c.n_params - c.w_off[0];
+  float* dst = wpart + (size_t)split * span + (c.w_off[k] - c.w_off[0]);
+  const int fo = c.fan_out[k];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int i = i0 + 16 * j + r16;
+    if (16 * j >= ncols || i >= fi) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int o = 16 * wave + 4 * q + e;
+      if (rt0 && o < fo) dst[(size_t)o * fi + i] = acc0[j][e];
+      const int o1 = o + 128;
+      if (rt1 && o1 < fo) dst[(size_t)o1 * fi + i] = acc1[j][e];
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_wgrad_reduce(DevCfg c, const float* __restrict__ wpart, int nsplit,
                                                       float* __restrict__ grad, DevState* __restrict__ state) {
   const uint64_t span = c.n_params - c.w_off[0];
@@ -1083,6 +1170,18 @@ static void set_lds(K kernel, size_t bytes) {
   (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+static WSlices make_slices(const DevCfg& c) {
+  WSlices S;
+  S.n = 0;
+  for (int k = 0; k <= c.hidden; ++k)
+    for (int i0 = 0; i0 < c.fan_in[k]; i0 += kWgCols) {
+      S.layer[S.n] = (int16_t)k;
+      S.i0[S.n] = (int16_t)i0;
+      ++S.n;
+    }
+  return S;
+}
+
 static WTiles make_tiles(const DevCfg& c) {
   WTiles T;
   T.n = 0;
@@ -1145,9 +1244,14 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
     if (labels)
       k_loss_finalize<<<1, 256, 0, L.stream>>>(P.loss_part, T.n_tiles, n, L.w_hit, L.w_t, L.w_normal, L.w_albedo,
                                                loss_dev, L.state);
-    const WTiles tiles = make_tiles(c);
     float* wpart = (float*)(w + T.wpart);
-    k_wgrad<AT><<<dim3(tiles.n, T.nsplit), 256, 0, L.stream>>>(c, tiles, P, kb, T.nsplit, wpart);
+    if constexpr (sizeof(AT) == 2) {
+      const WSlices slices = make_slices(c);
+      k_wgrad_rows<<<dim3(slices.n, T.nsplit), 512, 0, L.stream>>>(c, slices, P, kb, T.nsplit, wpart);
+    } else {
+      const WTiles tiles = make_tiles(c);
+      k_wgrad<AT><<<dim3(tiles.n, T.nsplit), 256, 0, L.stream>>>(c, tiles, P, kb, T.nsplit, wpart);
+    }
     const uint64_t span = c.n_params - c.w_off[0];
     k_wgrad_reduce<<<(uint32_t)((span + 255) / 256), 256, 0, L.stream>>>(c, wpart, T.nsplit, L.grad, L.state);
   }

@@ -364,7 +364,7 @@ def test_table_gradient_scatter_paths(lib, c1, path, order):
     assert np.abs(g - ref).max() <= 1e-5 * np.abs(ref).max(), np.abs(g - ref).max() / np.abs(ref).max()
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "f4", "c5"])
 def test_backward_bf16(lib, c1, name):
     sc, _ = c1
     net = NETS[name]
