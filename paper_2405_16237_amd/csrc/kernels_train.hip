@@ -91,10 +91,10 @@ static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_bat
     off = align256(off + (cells + 1) * 4);
     T.scan_sums = off;
     off = align256(off + (cells / 1024 + 4) * 4);
-    T.rec_idx = off;
-    off = align256(off + T.max_records * 2);
+    T.rec_idx = off;  // F = 2 keeps the entry inside its 12-byte record
+    if (c.n_features != 2) off = align256(off + T.max_records * 2);
     T.rec_val = off;
-    off = align256(off + T.max_records * c.n_features * 4);
+    off = align256(off + T.max_records * (c.n_features == 2 ? 12 : c.n_features * 4));
   }
   T.total = off;
   return T;
@@ -849,9 +849,14 @@ __global__ __launch_bounds__(256) void k_bin_write(DevCfg c, BinArgs A, const nb
     level_runs<F>(c, A.l_begin + (int)li, probes, p, duT, ldb, [&](uint32_t idx, const float* v) {
       const uint32_t rel = idx - A.off0;
       const uint32_t slot = atomicAdd(&cursor[rel / kBinChunk], 1u);
-      rec_idx[slot] = (uint16_t)(rel % kBinChunk);
+      if constexpr (F == 2) {
+        // one 12-byte record (entry, value pair): one store per contribution
+        ((uint3*)rec_val)[slot] = uint3{rel % kBinChunk, __float_as_uint(v[0]), __float_as_uint(v[1])};
+      } else {
+        rec_idx[slot] = (uint16_t)(rel % kBinChunk);
 #pragma unroll
-      for (int f = 0; f < F; ++f) rec_val[(size_t)slot * F + f] = v[f];
+        for (int f = 0; f < F; ++f) rec_val[(size_t)slot * F + f] = v[f];
+      }
     });
   }
 }
@@ -881,9 +886,16 @@ __global__ __launch_bounds__(1024) void k_bin_reduce(BinArgs A, const uint32_t* 
     for (int u = 0; u < kUnroll; ++u) {
       const uint32_t rr = r + u * blockDim.x;
       const bool ok = rr < r1;
-      ix[u] = ok ? (uint32_t)rec_idx[rr] : 0xffffffffu;
+      if constexpr (F == 2) {
+        const uint3 rec = ok ? ((const uint3*)rec_val)[rr] : uint3{0xffffffffu, 0u, 0u};
+        ix[u] = rec.x;
+        v[u][0] = __uint_as_float(rec.y);
+        v[u][1] = __uint_as_float(rec.z);
+      } else {
+        ix[u] = ok ? (uint32_t)rec_idx[rr] : 0xffffffffu;
 #pragma unroll
-      for (int f = 0; f < F; ++f) v[u][f] = ok ? rec_val[(size_t)rr * F + f] : 0.0f;
+        for (int f = 0; f < F; ++f) v[u][f] = ok ? rec_val[(size_t)rr * F + f] : 0.0f;
+      }
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
