@@ -493,7 +493,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the query shards by rays and the "
-              "training step by probes; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+              "training step by probes, but only one GPU is measured here). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
