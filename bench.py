@@ -492,7 +492,7 @@ def main():
                          "dispatch that scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the query shards by rays and the "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the query shards by rays and the "
               "training step by probes, but only one GPU is measured here). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
