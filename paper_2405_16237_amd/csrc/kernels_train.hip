@@ -861,6 +861,146 @@ __global__ __launch_bounds__(256) void k_bin_write(DevCfg c, BinArgs A, const nb
   }
 }
 
+// pass 2 for two-feature tables with at most kStagedBins bins: the same
+// records, grouped in LDS before they are stored. Each round every thread
+// advances its task by one sample (as level_runs does) and holds the 0 or 8
+// records that step closes; the round's records are counted per bin, placed in
+// an LDS stage in bin order and then stored in that order, so that the lanes
+// of a store instruction write runs of consecutive slots of one bin instead of
+// 64 scattered records.
+constexpr int kStagedBins = 1024;
+constexpr int kStageCap = 256 * 8;
+
+__global__ __launch_bounds__(256) void k_bin_write_staged(DevCfg c, BinArgs A, const nbvh_probe* __restrict__ probes,
+                                                          uint32_t n, const float* __restrict__ duT, uint64_t ldb,
+                                                          const uint32_t* __restrict__ offsets,
+                                                          uint3* __restrict__ rec) {
+  constexpr int F = 2;
+  __shared__ uint32_t cursor[kStagedBins];  // next slot of each bin for this workgroup
+  __shared__ uint32_t cnt[kStagedBins];     // the round's records per bin
+  __shared__ uint32_t off[kStagedBins];     // their exclusive offsets in the stage
+  __shared__ uint32_t sbase[kStagedBins];   // slot of the round's first record of each bin
+  __shared__ uint3 stage[kStageCap];
+  __shared__ uint32_t slot_of[kStageCap];
+  __shared__ uint32_t wtot[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (uint32_t i = tid; i < kStagedBins; i += 256) {
+    cursor[i] = i < A.n_bins ? offsets[(size_t)i * gridDim.x + blockIdx.x] : 0u;
+    cnt[i] = 0u;
+  }
+  __syncthreads();
+  const uint32_t t0 = blockIdx.x * A.per_wg, t1 = min(A.n_tasks, t0 + A.per_wg);
+  const uint32_t rounds_per_task = (uint32_t)c.n_samples + 1u;
+  const uint32_t n_tasks_thread = t1 > t0 ? (t1 - t0 + 255u) / 256u : 0u;
+  for (uint32_t j = 0; j < n_tasks_thread; ++j) {
+    const uint32_t t = t0 + j * 256u + (uint32_t)tid;
+    const bool have = t < t1;
+    const uint32_t li = have ? t / n : 0u, p = have ? t - li * n : 0u;
+    const int l = A.l_begin + (int)li;
+    const int N = c.level_res[l];
+    const bool dense = (c.dense_mask >> l) & 1u;
+    const uint32_t mask = (1u << c.log2_T) - 1u;
+    const uint32_t base = c.level_off[l];
+    const float4* pp = (const float4*)(probes + p);
+    const float4 a = pp[0], b = pp[1];
+    const float o[3] = {a.x, a.y, a.z}, d[3] = {b.x, b.y, b.z};
+    int ccx = -1, ccy = -1, ccz = -1;
+    float acc[8][F];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k][0] = acc[k][1] = 0.0f;
+    for (uint32_t s = 0; s < rounds_per_task; ++s) {
+      // one step of the run walk: the records of the run this sample closes
+      bool emit = false;
+      uint32_t rel[8];
+      float v0[8], v1[8];
+      int cx = -1, cy = -1, cz = -1;
+      float wx = 0.f, wy = 0.f, wz = 0.f, g0 = 0.f, g1 = 0.f;
+      const bool last = s == (uint32_t)c.n_samples;
+      if (have && !last) {
+        g0 = duT[(size_t)((s * c.n_levels + l) * F + 0) * ldb + p];
+        g1 = duT[(size_t)((s * c.n_levels + l) * F + 1) * ldb + p];
+        float x[3];
+        sample_position(c, o, d, a.w, b.w, (int)s, x);
+        cell_weight(x[0], N, cx, wx);
+        cell_weight(x[1], N, cy, wy);
+        cell_weight(x[2], N, cz, wz);
+      }
+      if (have && ccx >= 0 && (last || cx != ccx || cy != ccy || cz != ccz)) {
+        emit = true;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          rel[k] = base + corner_index(dense, N, mask, ccx + (k & 1), ccy + ((k >> 1) & 1), ccz + ((k >> 2) & 1)) * F -
+                   A.off0;
+          v0[k] = acc[k][0];
+          v1[k] = acc[k][1];
+        }
+      }
+      if (have && !last) {
+        if (cx != ccx || cy != ccy || cz != ccz) {
+          ccx = cx;
+          ccy = cy;
+          ccz = cz;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) acc[k][0] = acc[k][1] = 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float w = ((k & 1) ? wx : 1.0f - wx) * (((k >> 1) & 1) ? wy : 1.0f - wy) *
+                          (((k >> 2) & 1) ? wz : 1.0f - wz);
+          acc[k][0] = __builtin_fmaf(w, g0, acc[k][0]);
+          acc[k][1] = __builtin_fmaf(w, g1, acc[k][1]);
+        }
+      }
+      // round: rank within bin, exclusive scan over bins, stage, store
+      uint32_t rank[8];
+      if (emit) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) rank[k] = atomicAdd(&cnt[rel[k] / kBinChunk], 1u);
+      }
+      __syncthreads();
+      uint32_t c4[4], sum = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c4[q] = cnt[4 * tid + q];
+        sum += c4[q];
+      }
+      uint32_t incl = sum;  // inclusive scan of the per-thread sums within the wave
+#pragma unroll
+      for (int dd = 1; dd < 64; dd <<= 1) {
+        const uint32_t y = __shfl_up(incl, dd);
+        if (lane >= dd) incl += y;
+      }
+      if (lane == 63) wtot[wave] = incl;
+      __syncthreads();
+      uint32_t before = incl - sum;
+      for (int w2 = 0; w2 < wave; ++w2) before += wtot[w2];
+      const uint32_t total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int bi = 4 * tid + q;
+        off[bi] = before;
+        sbase[bi] = cursor[bi];
+        cursor[bi] += c4[q];
+        cnt[bi] = 0u;
+        before += c4[q];
+      }
+      __syncthreads();
+      if (emit) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t bin = rel[k] / kBinChunk;
+          const uint32_t i = off[bin] + rank[k];
+          stage[i] = uint3{rel[k] % kBinChunk, __float_as_uint(v0[k]), __float_as_uint(v1[k])};
+          slot_of[i] = sbase[bin] + rank[k];
+        }
+      }
+      __syncthreads();
+      for (uint32_t i = tid; i < total; i += 256) rec[slot_of[i]] = stage[i];
+      __syncthreads();
+    }
+  }
+}
+
 // pass 3: one workgroup per bin accumulates in LDS (64-bit fixed point) and
 // updates its chunk with plain read-modify-writes
 template <int F>
@@ -955,8 +1095,11 @@ static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char
     const uint32_t cells = T.n_bins * (uint32_t)kBinWgs;
     nbvh_status s = launch_exclusive_scan(L.stream, counts, cells, offsets, sums, sums + cells / 1024 + 3);
     if (s != NBVH_OK) return s;
-    k_bin_write<F><<<kBinWgs, 256, hist_lds, L.stream>>>(c, A, probes, n, duT, ldb, offsets,
-                                                        (uint16_t*)(w + T.rec_idx), (float*)(w + T.rec_val));
+    if (F == 2 && T.n_bins <= (uint32_t)kStagedBins)
+      k_bin_write_staged<<<kBinWgs, 256, 0, L.stream>>>(c, A, probes, n, duT, ldb, offsets, (uint3*)(w + T.rec_val));
+    else
+      k_bin_write<F><<<kBinWgs, 256, hist_lds, L.stream>>>(c, A, probes, n, duT, ldb, offsets,
+                                                          (uint16_t*)(w + T.rec_idx), (float*)(w + T.rec_val));
   }
   {
     ProfScope ps(L.prof, NBVH_K_SCATTER_REDUCE, L.stream);
