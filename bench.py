@@ -182,10 +182,26 @@ def run_single(args, W, P, torch, configs, scene):
     bf = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", loss_scale=1024.0, inside=W.inside)
     bf.set_params(W.params0)
     bf.workspace(R, seg_cap, B)
+    # levels of detail (Sec. 5.3): a coarser cut of the same median-split
+    # hierarchy over the same network, trained on a randomly chosen cut per step
+    coarse, coarse_batches, pick = None, [], None
+    if args.lod > 0:
+        cboxes, _ = scene.median_split_leaves(sc.verts, sc.tris, args.lod)
+        coarse = bf.view(cboxes)
+        coarse.workspace(R, seg_cap, B)
+        for i in range(args.batches):
+            pr, _ = scene.leaf_probes(cboxes, max(1, B // args.lod), seed=scene.SEED_PROBES + 50 + i,
+                                      inside_fraction=W.inside_fraction)
+            coarse_batches.append((torch.from_numpy(pr).cuda(),
+                                   torch.from_numpy(scene.probe_labels(sc.mesh, pr)).cuda()))
+        pick = np.random.default_rng(12)
     # pre-training (untimed): the trained network of the training workload
     t1 = time.time()
     loss = None
     for i in range(args.pretrain):
+        if coarse is not None and pick.integers(2):
+            loss = coarse.train_step(*coarse_batches[i % len(coarse_batches)])
+            continue
         p, l = batches[i % len(batches)]
         loss = bf.train_step(p, l)
     torch.cuda.synchronize()
@@ -264,6 +280,22 @@ def run_single(args, W, P, torch, configs, scene):
 
     roofline = rooflines(prof, net, bf.get_tuning(), evaluated, B, R, n_segments, W.name)
 
+    lod = None
+    if coarse is not None:
+        hits_c = torch.empty((R, 8), dtype=torch.float32, device="cuda")
+        c0 = coarse.read_state()
+        coarse.query(rays, seg_cap, hits_c)
+        torch.cuda.synchronize()
+        c1 = coarse.read_state()
+        acc_c = accuracy(hits_c)
+        cq_ms = time_loop(lambda i: coarse.query(rays, seg_cap, hits_c), args.steps)
+        lod = dict(coarse_leaves=args.lod, fine_leaves=int(sc.boxes.shape[0]), query_ms=cq_ms,
+                   rays_per_s=R / (cq_ms * 1e-3), speedup_vs_fine=q_ms / cq_ms,
+                   segments=int(c1["last_n_segments"]), segments_evaluated=int(c1["n_evaluated"] - c0["n_evaluated"]),
+                   accuracy=acc_c)
+        log("lod: %d leaves, query %.3f ms (%.2fx the %d-leaf cut), hit acc %.4f" %
+            (args.lod, cq_ms, q_ms / cq_ms, sc.boxes.shape[0], acc_c["hit_accuracy"]))
+
     # CPU baseline: the oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
@@ -301,7 +333,8 @@ def run_single(args, W, P, torch, configs, scene):
         "dtype": "bf16",
         "data": "synthetic",
         "config": {
-            "workload": W.describe,
+            "workload": W.describe + ("; the network is also trained on a %d-leaf cut of the same hierarchy, a "
+                                      "random cut per step" % args.lod if args.lod else ""),
             "rays": R, "segments": int(n_segments), "segments_evaluated": int(evaluated), "train_batch": B,
             "step": "one full query + one training step (forward, loss, backward, Adam)",
         },
@@ -314,6 +347,7 @@ def run_single(args, W, P, torch, configs, scene):
         "fp8": fp8,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        **({"lod": lod} if lod is not None else {}),
     }
 
 
@@ -480,6 +514,9 @@ def main():
     ap.add_argument("--pretrain", type=int, default=600, help="untimed BF16 training steps before timing")
     ap.add_argument("--batches", type=int, default=4, help="distinct 2^18-probe batches cycled in training")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--lod", type=int, default=0,
+                    help="also train and time a coarser cut of this many leaves over the same network (levels of "
+                         "detail); 0 = off")
     ap.add_argument("--inside", choices=("reverse", "clip"), default="reverse",
                     help="secondary workload: how a leaf around a bounce origin is queried")
     ap.add_argument("--bounce-offset", type=float, default=1e-4,
