@@ -357,7 +357,10 @@ def rooflines(prof, net, tune, evaluated, B, R, n_segments, workload):
       query_eval / train_tile: table bytes gathered, S*L*8 corners x F x 2 B;
       scatter routes: one 4-byte read-modify-write per corner and feature of
         the levels each route handles;
-      wgrad: 2 FLOPs per weight and probe; optimizer: 34 B per parameter;
+      wgrad: the stored BF16 activations and gradients read once (the thin
+        GEMMs over the batch stream them; 2 FLOPs per weight and probe are far
+        below the matrix cores' rate) plus the split partials written and read;
+      optimizer: 34 B per parameter;
       traverse: rays, two passes over the segment queue and the counts."""
     per = {k: (v[0] / max(1, v[1]), v[1], v[0]) for k, v in prof.items() if v[1] > 0}
     c = net
@@ -378,7 +381,9 @@ def rooflines(prof, net, tune, evaluated, B, R, n_segments, workload):
         "scatter": ("hbm", B * S * (L - sorted_levels) * 8 * F * 4, "GB/s"),
         "scatter_sort": ("hbm", B * S * sorted_levels * 8 * F * 4, "GB/s"),
         "scatter_reduce": ("hbm", B * S * sorted_levels * 8 * F * 4, "GB/s"),
-        "wgrad": ("mfma", B * 2 * c.n_mlp_params, "TFLOP/s"),
+        "wgrad": ("hbm", B * 2 * sum(fi + (32 if k == len(c.layer_dims()) - 1 else fo)
+                                     for k, (fi, fo) in enumerate(c.layer_dims()))
+                  + 2 * tune["wgrad_splits"] * c.n_mlp_params * 4, "GB/s"),
         "optimizer": ("hbm", (c.n_table_params + c.n_mlp_params) * 34, "GB/s"),
         "traverse": ("hbm", R * 32 + n_segments * 16 * 2 + R * 12, "GB/s"),
     }
