@@ -80,21 +80,22 @@ class Workload:
     """Inputs of one benchmark workload (all host arrays, seeded)."""
 
 
-def build_frame(configs, scene):
+def build_frame(configs, scene, samples=8):
     W = Workload()
     W.name = "frame"
     W.sc = configs.make_scene(1_003_520, 1024)
     W.rays = scene.pinhole_rays(1920, 1080)
     W.gt_idx = None
     W.gt = scene.ray_ground_truth(W.sc.mesh, W.rays)
-    W.net = configs.C2_NET
+    W.net = configs.C2_NET if samples == 8 else configs.C2_NET_S4
     W.params0 = configs.init_params(W.net, "normal", 1e-2)
     W.per_leaf = 256
     W.inside_fraction = 0.0
     W.inside = "clip"  # camera rays start outside every leaf
     W.seg_cap_per_ray = 16
     W.describe = ("1920x1080 primary rays on a 1,003,520-triangle displaced icosphere, 1,024 neural leaves; "
-                  "hash grid L=16 F=2 T=2^19, 8 samples/segment, MLP 256-4x128-5; train batch 2^18 probes")
+                  "hash grid L=16 F=2 T=2^19, %d samples/segment, MLP %d-4x128-5; train batch 2^18 probes"
+                  % (samples, samples * 32))
     W.cpu_sample = lambda stride: (W.rays.reshape(1080, 1920, 8)[::stride, ::stride].reshape(-1, 8),
                                    ("every %dth row and column of the 1920x1080 frame" % stride) if stride > 1 else "the whole 1920x1080 frame")
     return W
@@ -519,6 +520,8 @@ def main():
     ap.add_argument("--pretrain", type=int, default=600, help="untimed BF16 training steps before timing")
     ap.add_argument("--batches", type=int, default=4, help="distinct 2^18-probe batches cycled in training")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--samples", type=int, choices=(8, 4), default=8,
+                    help="frame workload: samples per segment (8, n_in = 256; or 4, the literal 128-input MLP)")
     ap.add_argument("--lod", type=int, default=0,
                     help="also train and time a coarser cut of this many leaves over the same network (levels of "
                          "detail); 0 = off")
@@ -551,7 +554,7 @@ def main():
     if args.workload == "batched":
         out = run_batched(args, P, torch, configs, scene)
     else:
-        W = build_frame(configs, scene) if args.workload == "frame" else build_secondary(configs, scene, args.inside,
+        W = build_frame(configs, scene, args.samples) if args.workload == "frame" else build_secondary(configs, scene, args.inside,
                                                                                            args.bounce_offset)
         out = run_single(args, W, P, torch, configs, scene)
     print(json.dumps(out), flush=True)
