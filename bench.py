@@ -520,6 +520,9 @@ def main():
     ap.add_argument("--pretrain", type=int, default=600, help="untimed BF16 training steps before timing")
     ap.add_argument("--batches", type=int, default=4, help="distinct 2^18-probe batches cycled in training")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--per-leaf", type=int, default=0,
+                    help="training probes per leaf (0: the workload's; 32 on the frame workload gives 2^15, one "
+                         "GPU's share of a 2^18 batch split over eight)")
     ap.add_argument("--samples", type=int, choices=(8, 4), default=8,
                     help="frame workload: samples per segment (8, n_in = 256; or 4, the literal 128-input MLP)")
     ap.add_argument("--lod", type=int, default=0,
@@ -556,6 +559,9 @@ def main():
     else:
         W = build_frame(configs, scene, args.samples) if args.workload == "frame" else build_secondary(configs, scene, args.inside,
                                                                                            args.bounce_offset)
+        if args.per_leaf > 0:
+            W.per_leaf = args.per_leaf
+            W.describe = W.describe.replace("train batch 2^18 probes", "train batch %d probes" % (args.per_leaf * W.sc.boxes.shape[0]))
         out = run_single(args, W, P, torch, configs, scene)
     print(json.dumps(out), flush=True)
 

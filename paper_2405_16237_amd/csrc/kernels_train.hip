@@ -702,7 +702,8 @@ __global__ __launch_bounds__(kHashTile) void k_scatter_hash(DevCfg c, int l_begi
   }
   __syncthreads();
   const uint32_t p = blockIdx.x * kHashTile + threadIdx.x;
-  for (int l = l_begin; l < l_end; ++l) {
+  // workgroups (tile, y) take levels l_begin + y, + gridDim.y, ...
+  for (int l = l_begin + (int)blockIdx.y; l < l_end; l += (int)gridDim.y) {
     if (p < n) {
       level_runs<F>(c, l, probes, p, duT, ldb, [&](uint32_t idx, const float* v) {
         bool any = false;
@@ -1066,10 +1067,13 @@ static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char
       (void)hipFuncSetAttribute((const void*)k_scatter_lds<F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       k_scatter_lds<F><<<L.n_cu, 1024, lds, L.stream>>>(c, T.n_lds, T.lds_floats, probes, n, duT, ldb, L.grad);
     }
-    if (T.hash_end > T.n_lds)
-      k_scatter_hash<F><<<(n + kHashTile - 1) / kHashTile, kHashTile, 0, L.stream>>>(c, T.n_lds, T.hash_end, probes,
-                                                                                   n, duT, ldb, gmax, L.state,
-                                                                                   L.grad);
+    if (T.hash_end > T.n_lds) {
+      // small batches: one workgroup per (tile, level), so that the chip fills
+      const uint32_t tiles = (n + kHashTile - 1) / kHashTile;
+      const uint32_t split = tiles < 4u * (uint32_t)L.n_cu ? (uint32_t)(T.hash_end - T.n_lds) : 1u;
+      k_scatter_hash<F><<<dim3(tiles, split), kHashTile, 0, L.stream>>>(c, T.n_lds, T.hash_end, probes, n, duT, ldb,
+                                                                        gmax, L.state, L.grad);
+    }
     if (T.hash_end >= c.n_levels) return check_launch("scatter");
     if (T.n_bins == 0) {
       const uint64_t threads = (uint64_t)n * (c.n_levels - T.hash_end) * 2 * F;
