@@ -7,13 +7,17 @@
 //                 scale) -> dgrad back through the layers on the matrix
 //                 cores. It stores the weight-gradient operands h_k^T and
 //                 g_k^T (feature-major, batch-minor) and dL/du^T.
-//  k_wgrad        dL/dW_k = sum_b g_k[b] h_k[b]^T as split-K MFMA GEMMs into
-//                 per-split partials; k_wgrad_reduce adds them into grad in
-//                 a fixed order.
-//  k_scatter_*    recompute every sample's cell corners and weights (no
-//                 stored encodings) and add w * dL/du into the table
-//                 gradient (LDS for the coarsest levels, coalesced FP32
-//                 atomics for the rest).
+//  k_wgrad_rows / k_wgrad   dL/dW_k = sum_b g_k[b] h_k[b]^T as split-K MFMA
+//                 GEMMs into per-split partials (BF16: every output row per
+//                 workgroup, activation slices shared through LDS);
+//                 k_wgrad_reduce adds them into grad in a fixed order.
+//  k_scatter_* / k_bin_*   recompute every sample's cell corners and weights
+//                 (no stored encodings) and add w * dL/du into the table
+//                 gradient: mid levels summed per probe tile in an LDS hash
+//                 (64-bit fixed point) then flushed with FP32 atomics, fine
+//                 levels counting-sorted into 64 KiB table chunks and summed
+//                 per chunk in LDS with no global atomics; coarse dense levels
+//                 held whole in LDS and coalesced atomics are tunable routes.
 //  k_check_finite / k_adam / k_adam_finalize   dense Adam with loss-scale
 //                 removal and non-finite skip; writes the BF16 shadow and the
 //                 transposed weight copies the dgrad reads.
