@@ -165,7 +165,8 @@ typedef struct {
  * the same layout (written by nbvh_sync_shadow and by every Adam step);
  * it may be NULL only if precision is FP32. grad accumulates dL/dparams
  * (times loss_scale) and is cleared by each optimiser step. state_dev is
- * nbvh_state_bytes() bytes. */
+ * nbvh_state_bytes() bytes. Every buffer must be 16-byte aligned
+ * (nbvh_bind_params returns NBVH_ERR_INVALID_ARG otherwise). */
 typedef struct {
   float* params_dev;
   void* params_lp_dev;

@@ -375,7 +375,8 @@ nbvh_status nbvh_bind_params(nbvh_ctx* ctx, const nbvh_params* p) {
     return set_error("a parameter buffer is NULL"), NBVH_ERR_INVALID_ARG;
   if (ctx->cfg.precision != NBVH_FP32 && !p->params_lp_dev)
     return set_error("params_lp_dev is required for BF16/FP8 precision"), NBVH_ERR_INVALID_ARG;
-  if (((uintptr_t)p->params_dev | (uintptr_t)p->params_lp_dev | (uintptr_t)p->aux_dev) & 15)
+  if (((uintptr_t)p->params_dev | (uintptr_t)p->params_lp_dev | (uintptr_t)p->aux_dev | (uintptr_t)p->adam_m_dev |
+       (uintptr_t)p->adam_v_dev | (uintptr_t)p->grad_dev) & 15)
     return set_error("parameter buffers must be 16-byte aligned"), NBVH_ERR_INVALID_ARG;
   ctx->p = *p;
   ctx->bound = true;

@@ -1246,8 +1246,12 @@ nbvh_status launch_leaf_loss(const LaunchCtx& L, const nbvh_probe* probes, const
 __global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ g, uint64_t n,
                                                       DevState* __restrict__ state) {
   bool bad = false;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    bad = bad || !isfinite(g[i]);
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t j = tid; j < n / 4; j += stride) {
+    const float4 x = ((const float4*)g)[j];
+    bad = bad || !isfinite(x.x) || !isfinite(x.y) || !isfinite(x.z) || !isfinite(x.w);
+  }
+  for (uint64_t i = (n / 4) * 4 + tid; i < n; i += stride) bad = bad || !isfinite(g[i]);
   if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&state->nonfinite_pending, 1u);
 }
 
@@ -1277,8 +1281,40 @@ __global__ __launch_bounds__(256) void k_adam(DevCfg c, float* __restrict__ para
   const float step = (float)(state->step + 1);
   const float inv_scale = 1.0f / state->loss_scale;
   const float c1 = 1.0f - powf(beta1, step), c2 = 1.0f - powf(beta2, step);
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.n_params;
-       i += (uint64_t)gridDim.x * blockDim.x) {
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
+  // the hash table (and its padding up to the first weight): four parameters
+  // per thread with 16-byte loads and stores (w_off[0] is a multiple of 64)
+  const uint64_t n4 = c.w_off[0] / 4;
+  for (uint64_t j = tid; j < n4; j += stride) {
+    float4 p = ((const float4*)params)[j];
+    if (mode == 0) {
+      const float4 g = ((const float4*)grad)[j];
+      ((float4*)grad)[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (!skip) {
+        float4 mi = ((const float4*)m)[j], vi = ((const float4*)v)[j];
+        float* pp = (float*)&p;
+        float* mm = (float*)&mi;
+        float* vv = (float*)&vi;
+        const float* gg = (const float*)&g;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float gs = gg[e] * inv_scale;
+          mm[e] = beta1 * mm[e] + (1.0f - beta1) * gs;
+          vv[e] = beta2 * vv[e] + (1.0f - beta2) * gs * gs;
+          const float mh = mm[e] / c1, vh = vv[e] / c2;
+          pp[e] -= lr * mh / (sqrtf(vh) + eps);
+        }
+        ((float4*)m)[j] = mi;
+        ((float4*)v)[j] = vi;
+        ((float4*)params)[j] = p;
+      }
+    }
+    if (lp)
+      ((uint2*)lp)[j] = uint2{(uint32_t)f32_to_bf16_bits(p.x) | ((uint32_t)f32_to_bf16_bits(p.y) << 16),
+                              (uint32_t)f32_to_bf16_bits(p.z) | ((uint32_t)f32_to_bf16_bits(p.w) << 16)};
+  }
+  // the MLP weights: one parameter per thread, with their transposed copies
+  for (uint64_t i = 4 * n4 + tid; i < c.n_params; i += stride) {
     float p = params[i];
     if (mode == 0) {
       const float g = grad[i];
