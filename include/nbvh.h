@@ -212,6 +212,10 @@ typedef struct {
                                   an LDS hash table before the global atomics: 0..32 (8) */
   int32_t query_pairs;      /* 1 = fetch the x-neighbour corners of a cell with one load where they are
                                adjacent in the table; 0 = one load per corner (0) */
+  int32_t query_lds_kb;     /* LDS per query workgroup for the table's leading (coarse) levels, copied
+                               there whole once per workgroup and gathered from LDS; as many leading
+                               levels as fit, none if the first does not; ignored with query_pairs
+                               and by grouped queries: 0..64 (0) */
 } nbvh_tuning;
 
 /* Read / replace the context's launch knobs (validated). */
@@ -368,7 +372,10 @@ nbvh_status nbvh_optimizer_step(nbvh_ctx* ctx, void* stream);
  * with a_c = sigmoid(z_{5+c}) (the relative-L2 albedo term only when
  * n_out >= 8), back-propagation into grad and an optimiser step. loss_dev
  * (nullable) receives [total, bce, dist, normal] as FP32 (unweighted terms;
- * total weighted, albedo included). */
+ * total weighted, albedo included). Here and in nbvh_backward, a batch
+ * whose binned table-gradient pass would need more than 2^32 records
+ * (n * binned levels * n_samples * 8) returns NBVH_ERR_UNSUPPORTED before
+ * any launch; split such batches. */
 nbvh_status nbvh_train_step(nbvh_ctx* ctx, const nbvh_probe* probes_dev, const nbvh_label* labels_dev,
                             uint64_t n, float* loss_dev, void* ws_dev, size_t ws_bytes, void* stream);
 

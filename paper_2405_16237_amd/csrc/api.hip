@@ -364,7 +364,7 @@ nbvh_status nbvh_build(const nbvh_config* cfg, const float* leaf_boxes_host, uin
   hipDeviceProp_t prop;
   ctx->n_cu = (hipGetDeviceProperties(&prop, dev) == hipSuccess) ? prop.multiProcessorCount : 256;
   if (ctx->n_cu <= 0) ctx->n_cu = 256;
-  ctx->tune = nbvh_tuning{8, 0, 0, 8, 64, 0, 1, 8, 0};
+  ctx->tune = nbvh_tuning{8, 0, 0, 8, 64, 0, 1, 8, 0, 0};
   *out = ctx;
   return NBVH_OK;
 }
@@ -646,6 +646,7 @@ nbvh_status nbvh_set_tuning(nbvh_ctx* ctx, const nbvh_tuning* t) {
   if (t->scatter_hash_levels < 0 || t->scatter_hash_levels > NBVH_MAX_LEVELS)
     return set_error("scatter_hash_levels in 0..32"), NBVH_ERR_INVALID_ARG;
   if (t->query_pairs != 0 && t->query_pairs != 1) return set_error("query_pairs must be 0 or 1"), NBVH_ERR_INVALID_ARG;
+  if (t->query_lds_kb < 0 || t->query_lds_kb > 64) return set_error("query_lds_kb in 0..64"), NBVH_ERR_INVALID_ARG;
   ctx->tune = *t;
   return NBVH_OK;
 }

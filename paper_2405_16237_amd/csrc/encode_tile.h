@@ -87,6 +87,14 @@ __device__ inline void unpack_raw(const typename RawEntry<F, LP>::T& r, float v[
   }
 }
 
+// The same entry from the workgroup's LDS copy of the table's leading levels
+// (same parameter indices: the copy starts at parameter 0).
+template <int F, bool LP>
+__device__ inline typename RawEntry<F, LP>::T load_raw_lds(const unsigned char* ltab, uint32_t param_index) {
+  typedef typename RawEntry<F, LP>::T T;
+  return *(const T*)(ltab + param_index * (LP ? 2u : 4u));
+}
+
 // Two adjacent table entries (an x-neighbour pair) as loaded.
 template <int F, bool LP>
 struct RawPair;
@@ -124,13 +132,16 @@ __device__ inline typename RawEntry<F, LP>::T pair_half(const typename RawPair<F
 // all U levels before consuming any. Consecutive samples of a segment often
 // fall into the same cell at the coarser levels: such a lane keeps the
 // corner values it already holds and is masked out of the gathers.
+// Levels below lds_levels are gathered from ltab, the workgroup's LDS copy of
+// the table's leading levels (not with PAIRS).
 // With PAIRS, corners are fetched as x-neighbour pairs: on dense levels
 // (x, x+1) are adjacent entries; on hashed levels they are the two halves of
 // an aligned pair whenever x is even (the hash keeps x's low bit), so one
 // load serves both and lanes with odd x add one masked load.
 template <typename AT, int F, bool LP, int NWAVES, int UNROLL = 0, bool PAIRS = false>
 __device__ inline void encode_tile(const DevCfg& c, const void* table, const float4* sA, const float4* sB,
-                                   const int* s_valid, AT* act0, int ld0, int M, float qscale = 1.0f) {
+                                   const int* s_valid, AT* act0, int ld0, int M, float qscale = 1.0f,
+                                   const unsigned char* ltab = nullptr, int lds_levels = 0) {
   typedef typename RawEntry<F, LP>::T Raw;
   constexpr bool kPairs = PAIRS && !(F == 4 && !LP);  // a 32-byte fp32 pair has no single load
   constexpr int U = UNROLL > 0 ? UNROLL : 2;
@@ -192,6 +203,13 @@ __device__ inline void encode_tile(const DevCfg& c, const void* table, const flo
                   raw[u][2 * j] = pair_half<F, LP>(p, (h0 & 1u) != 0u);
                   raw[u][2 * j + 1] = even ? pair_half<F, LP>(p, (h1 & 1u) != 0u) : load_raw<F, LP>(table, base + h1 * F);
                 }
+              }
+            } else if (l < lds_levels) {  // wave-uniform
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                const uint32_t idx = base + corner_index(dense, N, hmask, cx + (k & 1), cy + ((k >> 1) & 1),
+                                                         cz + ((k >> 2) & 1)) * F;
+                raw[u][k] = load_raw_lds<F, LP>(ltab, idx);
               }
             } else {
 #pragma unroll

@@ -82,7 +82,15 @@ struct QueryJob {
   const uint32_t* total_segs;
   uint64_t capacity;
   DevState* state;
+  uint32_t lds_words;  // 4-byte words of the table's leading levels copied to LDS (0: none)
+  int lds_levels;      // levels gathered from that copy
 };
+
+// LDS bytes of the slot state and tiles, before the staged table levels
+template <typename AT>
+__host__ __device__ inline size_t query_ltab_offset(int n_in, int width) {
+  return (query_lds_bytes<AT>(n_in, width) + 15) & ~(size_t)15;
+}
 
 // The persistent slot loop over one object's ray queue (see the file comment).
 // Returns with every slot drained, so a workgroup can move on to another
@@ -109,6 +117,14 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
   float* s_bn = s_bt + kQM;       // [3][kQM]
   float* s_ba = s_bn + 3 * kQM;   // [3][kQM]
   float* s_tmin = s_ba + 3 * kQM;
+  // the table's leading levels, copied once; the slot loop's first barrier
+  // orders the copy before any gather from it
+  const unsigned char* ltab = smem + query_ltab_offset<AT>(c.n_in, c.width);
+  {
+    const uint32_t* src = (const uint32_t*)J.table;
+    uint32_t* dst = (uint32_t*)(smem + query_ltab_offset<AT>(c.n_in, c.width));
+    for (uint32_t i = threadIdx.x; i < J.lds_words; i += blockDim.x) dst[i] = src[i];
+  }
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t n_active = *J.n_active;
@@ -179,18 +195,19 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
       if (c1 < s_end[lane]) nxt = J.segs[c1];
     }
     if constexpr (sizeof(AT) == 1) {
-      encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM, J.scales[kMaxLayers]);
+      encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM, J.scales[kMaxLayers], ltab,
+                                        J.lds_levels);
       __syncthreads();
       mlp_forward_tile_fp8<kQM, NW>(c, (const uint8_t*)J.W, J.scales, (uint8_t*)act0, ld0, (uint8_t*)act1, ld1, z,
                                     kOutPad);
     } else if constexpr (sizeof(AT) == 2) {
       // layer 0's first weight fragments travel while the table is gathered
       const PreBf16 pre0 = prefetch_bf16<NW>((const bf16*)J.W + c.w_off[0], c.fan_in[0], c.fan_in[0], c.fan_out[0]);
-      encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM);
+      encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM, 1.0f, ltab, J.lds_levels);
       __syncthreads();
       mlp_forward_tile<kQM, NW, AT>(c, (const AT*)J.W, act0, ld0, act1, ld1, z, kOutPad, &pre0);
     } else {
-      encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM);
+      encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM, 1.0f, ltab, J.lds_levels);
       __syncthreads();
       mlp_forward_tile<kQM, NW, AT>(c, (const AT*)J.W, act0, ld0, act1, ld1, z, kOutPad);
     }
@@ -470,6 +487,8 @@ nbvh_status launch_query_eval_batch(const LaunchCtx* Ls, int n_obj, const DevCfg
     J.total_segs = offsets[k] + n_rays;
     J.capacity = capacity;
     J.state = Lk.state;
+    J.lds_words = 0;  // objects differ in their tables: nothing staged
+    J.lds_levels = 0;
   }
 #define NBVH_QB(AT, F, LP, NW, U, PR) \
   return query_batch_t<AT, F, LP, NW, U, PR>(Ls, n_obj, cfgs_dev, jobs, per_obj, hits, n_rays)
@@ -482,7 +501,19 @@ static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const 
                                 const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
                                 uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity) {
   const DevCfg& c = L.cfg;
-  const size_t lds = query_lds_bytes<AT>(c.n_in, c.width);
+  // leading levels staged in LDS: as many whole levels as the budget holds
+  int lds_levels = 0;
+  size_t staged = 0;
+  if (!PR && L.tune.query_lds_kb > 0) {
+    const size_t budget = (size_t)L.tune.query_lds_kb * 1024, pb = LP ? 2 : 4;
+    while (lds_levels < c.n_levels) {
+      const size_t end = lds_levels + 1 < c.n_levels ? c.level_off[lds_levels + 1] : c.n_table;
+      if (end * pb > budget) break;
+      ++lds_levels;
+      staged = end * pb;
+    }
+  }
+  const size_t lds = staged ? query_ltab_offset<AT>(c.n_in, c.width) + staged : query_lds_bytes<AT>(c.n_in, c.width);
   if (lds_fits(lds, "the query") != NBVH_OK) return NBVH_ERR_UNSUPPORTED;
   auto kern = k_query_eval<AT, F, LP, NW, U, PR>;
   set_lds(kern, lds);
@@ -505,6 +536,8 @@ static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const 
   J.total_segs = offsets + n_rays_bound;
   J.capacity = capacity;
   J.state = L.state;
+  J.lds_words = (uint32_t)(staged / 4);
+  J.lds_levels = lds_levels;
   ProfScope ps(L.prof, NBVH_K_QUERY_EVAL, L.stream);
   kern<<<grid, 64 * NW, lds, L.stream>>>(c, J);
   return check_launch("query_eval");

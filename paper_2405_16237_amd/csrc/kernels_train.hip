@@ -1395,6 +1395,13 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
                            uint32_t n, float* loss_dev, void* ws, size_t ws_bytes) {
   const DevCfg& c = L.cfg;
   const TrainLayout T = train_layout(c, L.precision, n, L.tune);
+  // the binned gradient pass counts, scans and places its records with 32-bit
+  // indices
+  if (T.max_records > 0xffffffffull) {
+    set_error("batch of %u probes needs %llu gradient records, more than 2^32: split the batch", n,
+              (unsigned long long)T.max_records);
+    return NBVH_ERR_UNSUPPORTED;
+  }
   if (ws_bytes < T.total) {
     set_error("workspace too small for a batch of %u: need %zu bytes, got %zu", n, T.total, ws_bytes);
     return NBVH_ERR_CAPACITY;

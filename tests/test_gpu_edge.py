@@ -134,3 +134,62 @@ def test_largest_network_fp32_is_refused(lib, c1):
     probes, _ = scene.leaf_probes(sc.boxes, 2, seed=35)
     with pytest.raises(lib.NbvhError, match="LDS"):
         m.forward(torch.from_numpy(probes).cuda())
+
+
+def test_batch_beyond_record_indices_is_refused(lib, c1):
+    """The binned table-gradient pass places its records with 32-bit indices:
+    a batch that would need more than 2^32 of them is refused before any
+    launch, by the training step and by the plain backward pass."""
+    from paper_2405_16237_amd import _abi
+    sc = c1
+    net = configs.C1_NET
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16")
+    m.set_params(configs.init_params(net))
+    m.set_tuning(scatter_lds_kb=0, scatter_hash_levels=1, scatter_binned=1)
+    n = 1 << 25  # x (L - 1) binned levels x S samples x 8 corners > 2^32
+    assert n * (net.n_levels - 1) * net.n_samples * 8 > (1 << 32)
+    probes = torch.zeros((64, 10), dtype=torch.float32, device="cuda")  # never read
+    labels = torch.zeros((64, 5), dtype=torch.float32, device="cuda")
+    dz = torch.zeros((64, net.n_out), dtype=torch.float32, device="cuda")
+    ws = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    _say("record-index limit", n)
+    st = m.lib.nbvh_train_step(m.ctx, probes.data_ptr(), labels.data_ptr(), n, None, ws.data_ptr(), ws.numel(), None)
+    assert st == _abi.NBVH_ERR_UNSUPPORTED and "2^32" in m.lib.nbvh_last_error().decode()
+    st = m.lib.nbvh_backward(m.ctx, probes.data_ptr(), n, dz.data_ptr(), ws.data_ptr(), ws.numel(), None)
+    assert st == _abi.NBVH_ERR_UNSUPPORTED and "2^32" in m.lib.nbvh_last_error().decode()
+    torch.cuda.synchronize()
+    st = m.read_state()
+    assert st["step"] == 0 and st["flags"] == 0
+
+
+@pytest.mark.parametrize("precision,log2_T,kb", [("bf16", 14, 24), ("fp32", 14, 64), ("fp8", 14, 24),
+                                                 ("bf16", 10, 64), ("fp32", 10, 64)])
+def test_query_with_levels_staged_in_lds(lib, c1, precision, log2_T, kb):
+    """Gathering the table's leading levels from a workgroup's LDS copy gives
+    the same hit records, bit for bit, as gathering them from global memory:
+    the first (dense) level of a 2^14 table, and every level of a 2^10 table
+    (all hashed, the copy ending at the table's end)."""
+    sc = c1
+    net = configs.NetConfig(8, 2, log2_T, 4, 16, 1.5, 64, 3, 5)
+    pb = 4 if precision == "fp32" else 2
+    ends = np.cumsum(net.level_sizes()) * net.n_features * pb
+    staged = int((ends <= kb * 1024).sum())
+    assert staged == (1 if log2_T == 14 else net.n_levels)
+    params = configs.init_params(net, "uniform", 1.0, seed_features=36, seed_mlp=37)
+    w_out = params.size - net.n_out * net.mlp_width
+    params[w_out:w_out + net.mlp_width] *= -1.0  # mostly hits, so t and normals are compared too
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision=precision)
+    m.set_params(params)
+    if precision == "fp8":
+        p, _ = scene.leaf_probes(sc.boxes, 8, seed=38)
+        m.calibrate_fp8(torch.from_numpy(p).cuda())
+    rays = torch.from_numpy(scene.pinhole_rays(160, 120)).cuda()
+    _say("staged levels", precision, log2_T, kb, staged)
+    ref = m.query(rays).clone().view(torch.int32)
+    assert (ref[:, 7] != -1).sum() > 1000
+    m.set_tuning(query_lds_kb=kb)
+    got = m.query(rays).view(torch.int32)
+    assert torch.equal(got, ref)
+    m.set_tuning(query_lds_kb=kb, query_waves=4, query_unroll=3)
+    got = m.query(rays).view(torch.int32)
+    assert torch.equal(got, ref)
