@@ -177,7 +177,8 @@ __global__ __launch_bounds__(64 * kTWaves) __attribute__((amdgpu_waves_per_eu(4)
   int* s_valid = (int*)(sB + kTM);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t base = blockIdx.x * kTM;
+  const uint32_t tile = die_contiguous_tile(blockIdx.x, gridDim.x);
+  const uint32_t base = tile * kTM;
   const uint64_t ldb = P.ldb;
   if (tid < kTM) {
     const uint32_t i = base + tid;
@@ -272,10 +273,10 @@ __global__ __launch_bounds__(64 * kTWaves) __attribute__((amdgpu_waves_per_eu(4)
         l_a += __shfl_xor(l_a, off);
       }
       if (lane == 0) {
-        P.loss_part[blockIdx.x * 4 + 0] = l_bce;
-        P.loss_part[blockIdx.x * 4 + 1] = l_t;
-        P.loss_part[blockIdx.x * 4 + 2] = l_n;
-        P.loss_part[blockIdx.x * 4 + 3] = l_a;
+        P.loss_part[tile * 4 + 0] = l_bce;
+        P.loss_part[tile * 4 + 1] = l_t;
+        P.loss_part[tile * 4 + 2] = l_n;
+        P.loss_part[tile * 4 + 3] = l_a;
       }
     }
   }

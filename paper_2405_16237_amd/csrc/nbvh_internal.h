@@ -232,4 +232,12 @@ __device__ inline void corners_level(const DevCfg& c, int l, const float x[3], u
 
 __device__ inline float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
 
+// Workgroups go to the 8 accelerator dies round-robin (workgroup b to die
+// b % 8). This bijection of [0, n) gives each die a contiguous range of
+// tiles, so neighbouring tiles (one leaf's probes) share that die's L2.
+__device__ inline uint32_t die_contiguous_tile(uint32_t b, uint32_t n) {
+  const uint32_t q = n / 8u, r = n % 8u, x = b % 8u;
+  return x * q + (x < r ? x : r) + b / 8u;
+}
+
 }  // namespace nbvh
