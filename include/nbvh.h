@@ -331,6 +331,23 @@ nbvh_status nbvh_first_hits(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_
                             const float* accept_dev, nbvh_probe* probes_dev, uint32_t* leaf_ids_dev,
                             uint32_t* n_out_dev, uint32_t* leaf_hits_dev, void* stream);
 
+/* Training probes grouped by leaf (Sec. 5.2: each training ray trains the
+ * first leaf it crosses, so a batch mixes leaves in ray order). Writes the n
+ * probes of probes_dev to probes_out_dev ordered by their leaf ids
+ * (leaf_ids_dev, as written by nbvh_first_hits), increasing, keeping the
+ * input order among probes of one leaf; the sorted ids go to leaf_ids_out_dev
+ * if it is not NULL (it may be leaf_ids_dev). Ids are compared on the bits
+ * that ids below the context's leaf count use; higher bits are carried
+ * along. The training kernels then find a leaf's probes side by side, which
+ * keeps their table lines in one die's L2 and lets the per-tile gradient
+ * sums merge a leaf's entries. probes_out_dev must not alias probes_dev.
+ * ws_dev: nbvh_group_ws_bytes(n) bytes (nbvh_workspace_bytes with
+ * max_batch >= n covers it). Deterministic. Asynchronous. */
+size_t      nbvh_group_ws_bytes(uint64_t n);
+nbvh_status nbvh_group_by_leaf(nbvh_ctx* ctx, const nbvh_probe* probes_dev, const uint32_t* leaf_ids_dev,
+                               uint64_t n, nbvh_probe* probes_out_dev, uint32_t* leaf_ids_out_dev, void* ws_dev,
+                               size_t ws_bytes, void* stream);
+
 /* Per-leaf training loss (Sec. 5.1, "Node error"): runs the network on the n
  * segments probes_dev with labels_dev and adds each segment's combined loss
  * (weights w_hit, w_t, w_normal, w_albedo; not divided by the batch size) to

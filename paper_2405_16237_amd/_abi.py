@@ -68,7 +68,7 @@ EXPORTS = [
     "nbvh_param_count", "nbvh_param_layout", "nbvh_aux_bytes", "nbvh_nodes_bytes", "nbvh_state_bytes", "nbvh_build",
     "nbvh_bind_params", "nbvh_reset_optimizer", "nbvh_sync_shadow", "nbvh_calibrate_fp8", "nbvh_workspace_bytes",
     "nbvh_traverse",
-    "nbvh_query", "nbvh_query_segments", "nbvh_first_hits", "nbvh_leaf_loss", "nbvh_encode", "nbvh_forward", "nbvh_backward", "nbvh_optimizer_step",
+    "nbvh_query", "nbvh_query_segments", "nbvh_first_hits", "nbvh_group_ws_bytes", "nbvh_group_by_leaf", "nbvh_leaf_loss", "nbvh_encode", "nbvh_forward", "nbvh_backward", "nbvh_optimizer_step",
     "nbvh_train_step", "nbvh_loss", "nbvh_batch_desc_bytes", "nbvh_batch_create", "nbvh_batch_workspace_bytes",
     "nbvh_batch_query", "nbvh_batch_destroy", "nbvh_get_tuning", "nbvh_set_tuning", "nbvh_profile_begin", "nbvh_profile_end", "nbvh_read_state", "nbvh_clear_flags", "nbvh_last_error", "nbvh_version",
     "nbvh_destroy",
@@ -110,6 +110,8 @@ def load(path: str = LIB_PATH):
         "nbvh_query_segments": (st, [P, P, U64, P, P, P, P, SZ, P]),
         "nbvh_encode": (st, [P, P, U64, P, P]),
         "nbvh_first_hits": (st, [P, P, U64, P, P, P, P, P, P, P]),
+        "nbvh_group_ws_bytes": (SZ, [U64]),
+        "nbvh_group_by_leaf": (st, [P, P, P, U64, P, P, P, SZ, P]),
         "nbvh_leaf_loss": (st, [P, P, P, P, U64, P, P, P, SZ, P]),
         "nbvh_forward": (st, [P, P, U64, P, P, SZ, P]),
         "nbvh_backward": (st, [P, P, U64, P, P, SZ, P]),

@@ -11,6 +11,8 @@ reached; a final, longer training round follows.
 Training rays are drawn uniformly in the inflated root box with uniform
 directions, and each trains only the first leaf it crosses, kept with a
 probability that grows with that leaf's rank (Sec. 5.2, "Ray distribution").
+The kept probes are grouped by leaf before each training step (a layout
+choice: the step's result does not depend on the order beyond rounding).
 The paper states it as max(r / r_max, 0.005); with r a sum of logarithms of
 numbers below one, r and r_max are negative and that ratio inverts the
 order, so the rank is used through exp(r - r_max) = q^2 p / (q^2 p)_max,
@@ -152,10 +154,11 @@ def construct(net, base, label_fn, schedule: Schedule, scene_lo, scene_side, par
             k = int(pick.integers(len(levels) + 1)) if levels else len(levels)
             tree, acc = (model, accept) if k == len(levels) else (levels[k][1], levels[k][2])
             rays, u = sampler.rays(schedule.rays_per_step)
-            probes, _ = tree.first_hits(rays, u, acc)
+            probes, leaf = tree.first_hits(rays, u, acc)
             done[0] += 1
             if probes.shape[0] == 0:
                 continue
+            probes, _ = tree.group_by_leaf(probes, leaf)  # a leaf's probes side by side
             lab = torch.from_numpy(label_fn(probes.cpu().numpy())).to(model.device)
             losses.append(tree.train_step(probes.contiguous(), lab))
         return float(torch.stack(losses)[:, 0].mean()) if losses else float("nan")

@@ -422,7 +422,7 @@ size_t nbvh_workspace_bytes(const nbvh_ctx* ctx, uint64_t max_rays, uint64_t max
   size_t q = query_layout(max_rays, max_segments).total;
   const int prec = ctx->cfg.precision == NBVH_FP8 ? NBVH_BF16 : ctx->cfg.precision;
   size_t t = train_ws_bytes(ctx->dev, prec, max_batch, ctx->tune);
-  size_t l = a256((max_batch / 256 + 2) * 16);
+  size_t l = std::max(a256((max_batch / 256 + 2) * 16), group_ws_bytes(max_batch));
   return std::max(q, std::max(t, l));
 }
 
@@ -496,6 +496,21 @@ nbvh_status nbvh_first_hits(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays
     return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
   return launch_first_hits(make_launch(ctx, stream), rays, (uint32_t)n_rays, u, accept, probes, leaf_ids, n_out,
                            leaf_hits);
+}
+
+size_t nbvh_group_ws_bytes(uint64_t n) { return group_ws_bytes(n); }
+
+nbvh_status nbvh_group_by_leaf(nbvh_ctx* ctx, const nbvh_probe* probes_in, const uint32_t* leaf_ids_in, uint64_t n,
+                               nbvh_probe* probes_out, uint32_t* leaf_ids_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return set_error("ctx is NULL"), NBVH_ERR_INVALID_ARG;
+  if (n > 0xfffffff0ull) return set_error("too many probes"), NBVH_ERR_UNSUPPORTED;
+  if (n == 0) return NBVH_OK;
+  if (!probes_in || !leaf_ids_in || !probes_out || !ws) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  if (probes_out == probes_in) return set_error("probes_out must not alias probes_in"), NBVH_ERR_INVALID_ARG;
+  const size_t need = group_ws_bytes(n);
+  if (ws_bytes < need) return set_error("workspace too small: need %zu, got %zu", need, ws_bytes), NBVH_ERR_CAPACITY;
+  return launch_group_by_leaf(make_launch(ctx, stream), ctx->n_leaves, probes_in, leaf_ids_in, (uint32_t)n,
+                              probes_out, leaf_ids_out, ws);
 }
 
 nbvh_status nbvh_leaf_loss(nbvh_ctx* ctx, const nbvh_probe* probes, const nbvh_label* labels, const uint32_t* leaf_ids,

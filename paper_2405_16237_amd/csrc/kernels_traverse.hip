@@ -421,6 +421,121 @@ __global__ __launch_bounds__(256) void k_scan_add(uint32_t* __restrict__ out, ui
 }
 
 // ---------------------------------------------------------------------------
+// Grouping of training probes by leaf: a stable least-significant-digit radix
+// sort of the leaf ids, 4 bits per pass over the bits that ids below the leaf
+// count use, then one gather of the probes. Each pass counts every block's
+// 256 keys per digit (digit-major, so one exclusive scan gives every
+// (digit, block) its first output slot) and scatters them, a key's rank
+// among its block's equal digits taken from wave ballots in element order.
+constexpr int kGroupDigits = 16;
+static inline size_t group_a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__global__ __launch_bounds__(256) void k_group_count(const uint32_t* __restrict__ keys, uint32_t n, int shift,
+                                                     uint32_t* __restrict__ counts) {
+  __shared__ uint32_t wc[4][kGroupDigits];
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t d = i < n ? (keys[i] >> shift) & (kGroupDigits - 1) : (uint32_t)kGroupDigits;
+#pragma unroll
+  for (uint32_t q = 0; q < (uint32_t)kGroupDigits; ++q) {
+    const uint64_t m = __ballot(d == q);
+    if (lane == 0) wc[wave][q] = (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  if (threadIdx.x < kGroupDigits) {
+    const int q = threadIdx.x;
+    counts[(size_t)q * gridDim.x + blockIdx.x] = wc[0][q] + wc[1][q] + wc[2][q] + wc[3][q];
+  }
+}
+
+// vals == nullptr: the values are the element indices (first pass)
+__global__ __launch_bounds__(256) void k_group_scatter(const uint32_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ vals, uint32_t n, int shift,
+                                                       const uint32_t* __restrict__ offs,
+                                                       uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t wc[4][kGroupDigits];
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool ok = i < n;
+  const uint32_t key = ok ? keys[i] : 0u;
+  const uint32_t d = ok ? (key >> shift) & (kGroupDigits - 1) : (uint32_t)kGroupDigits;
+  uint64_t mine = 0ull;
+#pragma unroll
+  for (uint32_t q = 0; q < (uint32_t)kGroupDigits; ++q) {
+    const uint64_t m = __ballot(d == q);
+    if (lane == 0) wc[wave][q] = (uint32_t)__popcll(m);
+    if (d == q) mine = m;
+  }
+  __syncthreads();
+  if (ok) {
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wc[w][d];
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const uint32_t dst = offs[(size_t)d * gridDim.x + blockIdx.x] + before + (uint32_t)__popcll(mine & below);
+    keys_out[dst] = key;
+    vals_out[dst] = vals ? vals[i] : i;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_group_gather(const nbvh_probe* __restrict__ in,
+                                                      const uint32_t* __restrict__ perm,
+                                                      const uint32_t* __restrict__ keys, uint32_t n,
+                                                      nbvh_probe* __restrict__ out, uint32_t* __restrict__ ids_out) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  const float4* src = (const float4*)(in + perm[i]);
+  float4* dst = (float4*)(out + i);
+  dst[0] = src[0];
+  dst[1] = src[1];
+  if (ids_out) ids_out[i] = keys[i];
+}
+
+size_t group_ws_bytes(uint64_t n) {
+  const uint64_t nb = (n + 255) / 256, cells = nb * kGroupDigits;
+  return 4 * group_a256(n * 4) + group_a256((cells + 1) * 4) * 2 + group_a256((cells / kScanTile + 2) * 4) + 256;
+}
+
+nbvh_status launch_exclusive_scan(hipStream_t s, const uint32_t* in, uint32_t n, uint32_t* out, uint32_t* sums,
+                                  uint32_t* total_out);
+
+nbvh_status launch_group_by_leaf(const LaunchCtx& L, uint32_t n_leaves, const nbvh_probe* in, const uint32_t* ids,
+                                 uint32_t n, nbvh_probe* out, uint32_t* ids_out, void* ws) {
+  if (n == 0) return NBVH_OK;
+  const uint32_t nb = (n + 255) / 256, cells = nb * kGroupDigits;
+  char* w = (char*)ws;
+  uint32_t* kbuf[2];
+  uint32_t* vbuf[2];
+  size_t off = 0;
+  for (int j = 0; j < 2; ++j) {
+    kbuf[j] = (uint32_t*)(w + off);
+    off += group_a256((size_t)n * 4);
+    vbuf[j] = (uint32_t*)(w + off);
+    off += group_a256((size_t)n * 4);
+  }
+  uint32_t* counts = (uint32_t*)(w + off);
+  off += group_a256(((size_t)cells + 1) * 4);
+  uint32_t* offs = (uint32_t*)(w + off);
+  off += group_a256(((size_t)cells + 1) * 4);
+  uint32_t* sums = (uint32_t*)(w + off);
+  off += group_a256(((size_t)cells / kScanTile + 2) * 4);
+  uint32_t* total = (uint32_t*)(w + off);
+  const int bits = n_leaves > 1 ? 32 - __builtin_clz(n_leaves - 1) : 1;
+  const int passes = (bits + 3) / 4;
+  const uint32_t* kin = ids;
+  const uint32_t* vin = nullptr;
+  for (int p = 0; p < passes; ++p) {
+    k_group_count<<<nb, 256, 0, L.stream>>>(kin, n, 4 * p, counts);
+    nbvh_status s = launch_exclusive_scan(L.stream, counts, cells, offs, sums, total);
+    if (s != NBVH_OK) return s;
+    k_group_scatter<<<nb, 256, 0, L.stream>>>(kin, vin, n, 4 * p, offs, kbuf[p & 1], vbuf[p & 1]);
+    kin = kbuf[p & 1];
+    vin = vbuf[p & 1];
+  }
+  k_group_gather<<<nb, 256, 0, L.stream>>>(in, vin, kin, n, out, ids_out);
+  return check_launch("group_by_leaf");
+}
+
+// ---------------------------------------------------------------------------
 nbvh_status launch_exclusive_scan(hipStream_t s, const uint32_t* in, uint32_t n, uint32_t* out, uint32_t* sums,
                                   uint32_t* total_out) {
   const uint32_t n_tiles = (n + kScanTile - 1) / kScanTile;

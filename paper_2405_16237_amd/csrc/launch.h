@@ -98,6 +98,10 @@ nbvh_status launch_first_hits(const LaunchCtx& L, const nbvh_ray* rays, uint32_t
                               const float* accept, nbvh_probe* probes, uint32_t* leaf_out, uint32_t* n_out,
                               uint32_t* leaf_hits);
 
+size_t group_ws_bytes(uint64_t n);
+nbvh_status launch_group_by_leaf(const LaunchCtx& L, uint32_t n_leaves, const nbvh_probe* in, const uint32_t* ids,
+                                 uint32_t n, nbvh_probe* out, uint32_t* ids_out, void* ws);
+
 nbvh_status launch_leaf_loss(const LaunchCtx& L, const nbvh_probe* probes, const nbvh_label* labels,
                              const uint32_t* leaf_ids, uint32_t n, float* z, float* leaf_loss, uint32_t* leaf_count);
 

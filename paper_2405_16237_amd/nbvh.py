@@ -211,6 +211,16 @@ class NBVH:
         k = int(cnt.item())
         return probes[:k], leaf[:k]
 
+    def group_by_leaf(self, probes: torch.Tensor, leaf_ids: torch.Tensor):
+        """(probes, leaf ids) reordered by leaf id, stable within a leaf."""
+        n = probes.shape[0]
+        out = torch.empty_like(probes)
+        ids = torch.empty_like(leaf_ids)
+        ws = self.workspace(0, 0, n)
+        check(self.lib.nbvh_group_by_leaf(self.ctx, _ptr(probes.contiguous()), _ptr(leaf_ids.contiguous()), n, _ptr(out),
+                                          _ptr(ids), _ptr(ws), ws.numel(), _stream()))
+        return out, ids
+
     def leaf_loss(self, probes: torch.Tensor, labels: torch.Tensor, leaf_ids: torch.Tensor,
                   leaf_loss: torch.Tensor, leaf_count: torch.Tensor):
         """Adds each segment's combined loss to leaf_loss[leaf] (float32) and

@@ -202,3 +202,29 @@ def test_levels_of_detail(lib, c1):
     _say("hit accuracy per level", accs, "segments", segs)
     assert min(accs) > 0.85 and accs[-1] > 0.9
     assert segs[0] < segs[-1]
+
+
+@pytest.mark.parametrize("n_leaves,n,tagged", [(64, 50_033, False), (1024, 70_001, True), (1, 300, False),
+                                               (20_000, 4_099, True)])
+def test_group_by_leaf_is_a_stable_sort(lib, n_leaves, n, tagged):
+    """Grouping probes by leaf is the stable sort by leaf id: compared with
+    numpy's stable argsort, bit for bit, for 1, 64, 1,024 and 20,000 leaves
+    (one to four 4-bit passes) and batch sizes that are not multiples of 256;
+    a bit above the leaf count (the inside tag) is carried along unsorted."""
+    rng = np.random.default_rng(n_leaves + n)
+    lo = rng.uniform(0.0, 0.9, size=(n_leaves, 3))
+    boxes = np.concatenate([lo, lo + rng.uniform(0.01, 0.1, size=(n_leaves, 3))], axis=1).astype(np.float32)
+    m = lib.NBVH(configs.C1_NET, boxes, np.zeros(3, np.float32), 1.0, precision="fp32")
+    ids = rng.integers(0, n_leaves, size=n).astype(np.uint32)
+    if tagged:
+        ids[::7] |= np.uint32(0x80000000)
+    probes = rng.standard_normal((n, 8)).astype(np.float32)
+    _say("group by leaf", n_leaves, n)
+    p_out, id_out = m.group_by_leaf(torch.from_numpy(probes).cuda(), torch.from_numpy(ids.view(np.int32)).cuda())
+    bits = max(1, int(n_leaves - 1).bit_length())
+    key = ids & np.uint32((1 << (4 * ((bits + 3) // 4))) - 1)
+    order = np.argsort(key, kind="stable")
+    assert np.array_equal(id_out.cpu().numpy().view(np.uint32), ids[order])
+    assert np.array_equal(p_out.cpu().numpy().view(np.int32), probes[order].view(np.int32))
+    e_p, e_i = m.group_by_leaf(torch.zeros((0, 8), device="cuda"), torch.zeros(0, dtype=torch.int32, device="cuda"))
+    assert e_p.shape == (0, 8) and e_i.shape == (0,)
