@@ -1498,7 +1498,10 @@ nbvh_status launch_optimizer(const LaunchCtx& L, bool reset, bool shadow_only) {
   const DevCfg& c = L.cfg;
   float* aux32 = (float*)L.aux;
   uint16_t* aux16 = (uint16_t*)((char*)L.aux + c.n_wt * 4);
-  const uint32_t grid = (uint32_t)((c.n_params + 255) / 256 < 4096 ? (c.n_params + 255) / 256 : 4096);
+  // a thread per four parameters (the table is updated in 16-byte vectors),
+  // so every thread's loads are in flight at once
+  const uint64_t want = (c.n_params / 4 + 255) / 256;
+  const uint32_t grid = (uint32_t)(want < 1 ? 1 : (want > (1u << 18) ? (1u << 18) : want));
   ProfScope ps(L.prof, NBVH_K_OPTIMIZER, L.stream);
   if (reset) {
     k_reset_state<<<1, 64, 0, L.stream>>>(L.state, L.loss_scale);
