@@ -193,3 +193,17 @@ def test_query_with_levels_staged_in_lds(lib, c1, precision, log2_T, kb):
     m.set_tuning(query_lds_kb=kb, query_waves=4, query_unroll=3)
     got = m.query(rays).view(torch.int32)
     assert torch.equal(got, ref)
+
+
+def test_query_lds_kb_is_validated(lib, c1):
+    """The LDS budget for staged coarse levels is 0..64 KiB; other values are
+    refused and leave the knobs as they were."""
+    sc = c1
+    m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="bf16")
+    before = m.get_tuning()
+    for bad in (-1, 65, 1024):
+        with pytest.raises(lib.NbvhError, match="query_lds_kb"):
+            m.set_tuning(query_lds_kb=bad)
+    assert m.get_tuning() == before
+    m.set_tuning(query_lds_kb=64)
+    assert m.get_tuning()["query_lds_kb"] == 64
