@@ -228,3 +228,32 @@ def test_group_by_leaf_is_a_stable_sort(lib, n_leaves, n, tagged):
     assert np.array_equal(p_out.cpu().numpy().view(np.int32), probes[order].view(np.int32))
     e_p, e_i = m.group_by_leaf(torch.zeros((0, 8), device="cuda"), torch.zeros(0, dtype=torch.int32, device="cuda"))
     assert e_p.shape == (0, 8) and e_i.shape == (0,)
+
+
+def test_backward_does_not_depend_on_probe_order(lib, c1):
+    """Grouping a batch by leaf changes its layout only: the gradients of a
+    shuffled batch and of the same batch regrouped by nbvh_group_by_leaf agree
+    to FP32 summation order (the same per-probe terms, summed in another
+    order)."""
+    sc = c1
+    net = configs.C1_NET
+    params = configs.init_params(net, "uniform", 0.5, seed_features=40, seed_mlp=41)
+    p, lf = scene.leaf_probes(sc.boxes, 64, seed=42)
+    perm = np.random.default_rng(43).permutation(p.shape[0])
+    p_s, lf_s = np.ascontiguousarray(p[perm]), np.ascontiguousarray(lf[perm]).astype(np.int32)
+    dz = (np.random.default_rng(44).standard_normal((p.shape[0], net.n_out)) * 1e-2).astype(np.float32)
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32")
+    m.set_params(params)
+    _say("backward, shuffled vs regrouped", p.shape)
+    g_p, g_ids = m.group_by_leaf(torch.from_numpy(p_s).cuda(), torch.from_numpy(lf_s).cuda())
+    order = np.argsort(lf_s, kind="stable")
+    assert np.array_equal(g_ids.cpu().numpy(), lf_s[order])
+    m.grad.zero_()
+    m.backward(torch.from_numpy(p_s).cuda(), torch.from_numpy(dz).cuda())
+    g_shuffled = m.grad.double().cpu().numpy()
+    m.grad.zero_()
+    m.backward(g_p, torch.from_numpy(np.ascontiguousarray(dz[order])).cuda())
+    g_grouped = m.grad.double().cpu().numpy()
+    scale = np.abs(g_shuffled).max()
+    assert scale > 0 and np.count_nonzero(g_shuffled) > 1000
+    assert np.abs(g_grouped - g_shuffled).max() <= 1e-4 * scale
