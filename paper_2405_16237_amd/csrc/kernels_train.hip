@@ -492,16 +492,24 @@ __global__ __launch_bounds__(512) void k_wgrad_rows(DevCfg c, WSlices sl, TrainP
 
 __global__ __launch_bounds__(256) void k_wgrad_reduce(DevCfg c, const float* __restrict__ wpart, int nsplit,
                                                       float* __restrict__ grad, DevState* __restrict__ state) {
+  // four lanes per parameter, lane q summing splits q, q + 4, ...; the four
+  // sums are combined in a fixed order, so the result does not depend on timing
   const uint64_t span = c.n_params - c.w_off[0];
-  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < span; j += (uint64_t)gridDim.x * blockDim.x) {
-    // inside a layer's block (not alignment padding)?
-    const uint64_t abs_i = c.w_off[0] + j;
-    bool inside = false;
-    for (int k = 0; k <= c.hidden; ++k)
-      if (abs_i >= c.w_off[k] && abs_i < c.w_off[k] + (uint64_t)c.fan_in[k] * c.fan_out[k]) inside = true;
-    if (!inside) continue;
-    float s = 0.f;
-    for (int p = 0; p < nsplit; ++p) s += wpart[(size_t)p * span + j];
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t j = t >> 2;
+  const int part = (int)(t & 3u);
+  if (j >= span) return;  // the four lanes of a parameter leave together
+  // inside a layer's block (not alignment padding)?
+  const uint64_t abs_i = c.w_off[0] + j;
+  bool inside = false;
+  for (int k = 0; k <= c.hidden; ++k)
+    if (abs_i >= c.w_off[k] && abs_i < c.w_off[k] + (uint64_t)c.fan_in[k] * c.fan_out[k]) inside = true;
+  if (!inside) return;
+  float s = 0.f;
+  for (int p = part; p < nsplit; p += 4) s += wpart[(size_t)p * span + j];
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  if (part == 0) {
     if (!isfinite(s)) atomicOr(&state->nonfinite_pending, 1u);
     grad[abs_i] += s;
   }
@@ -1460,7 +1468,7 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
       k_wgrad<AT><<<dim3(tiles.n, T.nsplit), 256, 0, L.stream>>>(c, tiles, P, kb, T.nsplit, wpart);
     }
     const uint64_t span = c.n_params - c.w_off[0];
-    k_wgrad_reduce<<<(uint32_t)((span + 255) / 256), 256, 0, L.stream>>>(c, wpart, T.nsplit, L.grad, L.state);
+    k_wgrad_reduce<<<(uint32_t)((4 * span + 255) / 256), 256, 0, L.stream>>>(c, wpart, T.nsplit, L.grad, L.state);
   }
   nbvh_status s = launch_scatter<F>(L, T, w, probes, n, P.duT, kb, P.gmax);
   if (s != NBVH_OK) return s;
