@@ -356,7 +356,8 @@ __global__ __launch_bounds__(256) void k_wgrad(DevCfg c, WTiles tiles, TrainPtrs
   if (o0 >= fo_pad) return;
   const int fi = c.fan_in[k];
   const uint64_t ldb = P.ldb;
-  const uint32_t chunk = (kb / nsplit + 31) / 32 * 32;
+  // ceil(kb / nsplit) rounded up to 32 batch entries: the splits cover the whole batch
+  const uint32_t chunk = ((kb + (uint32_t)nsplit - 1u) / (uint32_t)nsplit + 31u) / 32u * 32u;
   const uint32_t b_beg = split * chunk;
   uint32_t b_end = b_beg + chunk;
   if (b_end > kb) b_end = kb;
@@ -425,7 +426,8 @@ __global__ __launch_bounds__(512) void k_wgrad_rows(DevCfg c, WSlices sl, TrainP
   const int fo_pad = fan_out_pad(c, k), fi = c.fan_in[k];
   const int ncols = min(kWgCols, fi - i0);
   const uint64_t ldb = P.ldb;
-  const uint32_t chunk = (kb / nsplit + 31) / 32 * 32;
+  // ceil(kb / nsplit) rounded up to 32 batch entries: the splits cover the whole batch
+  const uint32_t chunk = ((kb + (uint32_t)nsplit - 1u) / (uint32_t)nsplit + 31u) / 32u * 32u;
   const uint32_t b_beg = min(kb, split * chunk);
   const uint32_t b_end = min(kb, b_beg + chunk);
   const int n_it = (int)((b_end - b_beg) / 32);

@@ -207,3 +207,41 @@ def test_query_lds_kb_is_validated(lib, c1):
     assert m.get_tuning() == before
     m.set_tuning(query_lds_kb=64)
     assert m.get_tuning()["query_lds_kb"] == 64
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("n", [64, 2112])
+def test_wgrad_splits_cover_the_batch(lib, c1, precision, n):
+    """The weight-gradient GEMMs split the batch over wgrad_splits
+    workgroups; every split count the tuning accepts must cover every probe
+    (65 does not divide a padded batch, 128 and 256 exceed a 64-probe batch's
+    32-entry steps), so the gradient equals the default split's and, in FP32,
+    the oracle's."""
+    sc = c1
+    net = configs.C1_NET
+    params = configs.init_params(net, "uniform", 0.5)
+    p, _ = scene.leaf_probes(sc.boxes, 2 * n // 64 + 1, seed=41)
+    # probes whose hidden pre-activations stay clear of the ReLU kink, where
+    # FP32 and FP64 could take different 0/1 derivatives
+    cfg = oracle.make_cfg(net, sc.lo, sc.side)
+    p = p[oracle.min_abs_preact(cfg, params.astype(np.float64), p) > 1e-4][:n]
+    assert p.shape[0] == n
+    dz = (np.random.default_rng(42).normal(size=(n, net.n_out)) / n).astype(np.float32)
+    grads = {}
+    for splits in (64, 65, 128, 256):
+        m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision=precision, loss_scale=1.0)
+        m.set_params(params)
+        m.set_tuning(wgrad_splits=splits)
+        _say("wgrad splits", precision, n, splits)
+        m.backward(torch.from_numpy(p).cuda(), torch.from_numpy(dz).cuda())
+        grads[splits] = m.unpad(m.grad)[net.n_table_params:].astype(np.float64)
+    ref = grads[64]
+    assert np.abs(ref).max() > 0
+    for splits in (65, 128, 256):
+        err = np.abs(grads[splits] - ref).max() / np.abs(ref).max()
+        assert err <= 1e-5, (splits, err)
+    if precision == "fp32":
+        o = oracle.backward(cfg, params.astype(np.float64), p, dz.astype(np.float64))[net.n_table_params:]
+        for splits, g in grads.items():
+            kept = np.abs(g - o).max() / np.abs(o).max()
+            assert kept <= 1e-4, (splits, kept)
