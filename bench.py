@@ -80,6 +80,46 @@ class Workload:
     """Inputs of one benchmark workload (all host arrays, seeded)."""
 
 
+def parity(torch, m, rays_np, sc, net, params, precision, inside, what):
+    """The library's query against the FP64 oracle on a subset of the
+    workload's rays, through nbvh_query_traced (the kernels and launch shapes
+    the timed query uses): hit-record agreement with the oracle's resolve,
+    depth error over agreeing hits (scene diagonals), and the largest logit
+    error |dz| / max(1, |z|) over the segments the GPU evaluated. BF16 is
+    compared with the oracle run on the BF16-rounded parameters (quantisation
+    of the parameters is the format's, not the kernels' error)."""
+    import oracle
+    rev = inside == "reverse"
+    tr = oracle.traverse(rays_np, sc.boxes, rev)
+    off, sr, sl, t0, t1 = tr
+    n_seg = int(off[-1])
+    hits, goff, _, zt, _ = m.query_traced(torch.from_numpy(rays_np).cuda(), n_seg + 64, z=True, u=False)
+    torch.cuda.synchronize()
+    hits = hits.cpu().numpy()
+    zt = zt[:n_seg].cpu().numpy().astype(np.float64)
+    same_queue = bool(np.array_equal(goff.cpu().numpy().astype(np.uint32).astype(np.uint64), off))
+    pref = params
+    if precision == "bf16":
+        pref = torch.from_numpy(params).to(torch.bfloat16).float().numpy()
+    cfg = oracle.make_cfg(net, sc.lo, sc.side)
+    rows = oracle.segment_rows(rays_np, sr, t0, t1, sl)
+    z = oracle.forward(cfg, pref.astype(np.float64), rows)
+    out = oracle.resolve(off, sl, t0, t1, z, net.n_out, rays_np[:, 3])
+    ev = ~np.isnan(zt[:, 0])
+    dz = np.abs(zt[ev] - z[ev]) / np.maximum(1.0, np.abs(z[ev]))
+    leaf = hits[:, 7].view(np.uint32).astype(np.int64)
+    leaf[leaf == 0xFFFFFFFF] = -1
+    oleaf = out[:, 4].astype(np.int64)
+    both = (leaf >= 0) & (leaf == oleaf)
+    dep = np.abs(hits[both, 0].astype(np.float64) - out[both, 0]) / sc.diagonal
+    return dict(rays=int(rays_np.shape[0]), sample=what, segments=n_seg, segments_evaluated=int(ev.sum()),
+                segment_queue_bitexact=same_queue, leaf_agreement=float((leaf == oleaf).mean()),
+                depth_err_mean=float(dep.mean()) if both.any() else None,
+                depth_err_p99=float(np.quantile(dep, 0.99)) if both.any() else None,
+                max_dz_rel=float(dz.max()) if ev.any() else None,
+                oracle_params="BF16-rounded" if precision == "bf16" else "FP32 master")
+
+
 def build_frame(configs, scene, samples=8):
     W = Workload()
     W.name = "frame"
@@ -96,7 +136,8 @@ def build_frame(configs, scene, samples=8):
     W.describe = ("1920x1080 primary rays on a 1,003,520-triangle displaced icosphere, 1,024 neural leaves; "
                   "hash grid L=16 F=2 T=2^19, %d samples/segment, MLP %d-4x128-5; train batch 2^18 probes"
                   % (samples, samples * 32))
-    W.cpu_sample = lambda stride: (W.rays.reshape(1080, 1920, 8)[::stride, ::stride].reshape(-1, 8),
+    W.parity_stride = 4
+    W.cpu_sample = lambda stride: (W.rays.reshape(1080, 1920, 8)[::stride, ::stride].reshape(-1, 8).copy(),
                                    ("every %dth row and column of the 1920x1080 frame" % stride) if stride > 1 else "the whole 1920x1080 frame")
     return W
 
@@ -132,7 +173,8 @@ def build_secondary(configs, scene, inside="reverse", offset=1e-4):
                   "displaced icosphere with per-vertex albedo, 16,384 neural leaves; hash grid L=16 F=4 T=2^22, "
                   "4 samples/segment, MLP 256-4x256-8 (hit, t, normal, albedo); origins offset by %g of the scene "
                   "diagonal along the normal; " % offset + how)
-    W.cpu_sample = lambda stride: (W.rays[::stride * stride * 16], "every %dth ray" % (stride * stride * 16))
+    W.parity_stride = 4  # every 256th bounce ray
+    W.cpu_sample = lambda stride: (W.rays[::stride * stride * 16].copy(), "every %dth ray" % (stride * stride * 16))
     return W
 
 
@@ -280,6 +322,25 @@ def run_single(args, W, P, torch, configs, scene):
         del f8, hits_f8
 
     roofline = rooflines(prof, net, bf.get_tuning(), evaluated, B, R, n_segments, W.name)
+    peaks = None
+    if not args.no_peaks:
+        from paper_2405_16237_amd import peaks as PK
+        peaks = PK.measure(torch)
+        log("measured ceilings:", {k: {a: round(b, 3) for a, b in v.items()} for k, v in peaks.items()})
+        against_ceilings(roofline, peaks, net, evaluated, B, sc_table_bytes(net))
+
+    # parity with the FP64 oracle on a subset of the same rays, trained parameters
+    par = None
+    if not args.no_parity:
+        sub, what = W.cpu_sample(W.parity_stride)
+        par = dict(bf16=parity(torch, bf, sub, sc, net, trained, "bf16", W.inside, what))
+        log("parity bf16:", par["bf16"])
+        if not args.no_fp32:
+            fpp = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32", inside=W.inside)
+            fpp.set_params(trained)
+            par["fp32"] = parity(torch, fpp, sub, sc, net, trained, "fp32", W.inside, what)
+            log("parity fp32:", par["fp32"])
+            del fpp
 
     lod = None
     if coarse is not None:
@@ -348,8 +409,66 @@ def run_single(args, W, P, torch, configs, scene):
         "fp8": fp8,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "parity": par,
+        "ceilings": peaks,
         **({"lod": lod} if lod is not None else {}),
     }
+
+
+def sc_table_bytes(net):
+    """Bytes of the BF16 table shadow the kernels gather from."""
+    return net.n_table_params * 2
+
+
+def _table_class(nbytes):
+    """The gather measurement whose table size is nearest above the table's:
+    4 MiB (L2 of one die), 32 MiB (Infinity Cache) or 512 MiB (HBM)."""
+    return 4 if nbytes <= (4 << 20) else 32 if nbytes <= (64 << 20) else 512
+
+
+def against_ceilings(roofline, peaks, net, evaluated, B, table_bytes):
+    """Adds to each per-kernel roofline the measured ceiling of the unit that
+    bounds it and the fraction reached, and matrix-core throughput for the
+    fused kernels:
+      query_eval / train_tile: table gathers (entry = F x 2 B, one per lane, 8
+        lines per wave: rays of a workgroup are neighbours) against the gather
+        loop on a table of the same size class;
+      scatter: FP32 read-modify-writes against the scattered FP32 atomic loop;
+      scatter_reduce, wgrad, optimizer, traverse: bytes against the streaming
+        read of a 1 GiB (HBM) buffer;
+      MLP FLOPs (2 per weight and segment forward; forward and input-gradient
+        products in the training tile) against the BF16 16x16x32 loop and the
+        data-sheet 2.5 PFLOP/s."""
+    S, L, F = net.n_samples, net.n_levels, net.n_features
+    eb = F * 2
+    gkey = "gather_%dMiB_%dB_8lines" % (_table_class(table_bytes), eb)
+    mlp = sum(fi * fo for fi, fo in net.layer_dims()) * 2.0
+    mf = peaks["mfma_bf16_16x16x32"]["tflops"]
+    hbm = peaks["stream_1024MiB"]["gbs"]
+    per = roofline["per_kernel"]
+    for k, r in per.items():
+        if k in ("query_eval", "train_tile"):
+            units = (evaluated if k == "query_eval" else B) * S * L * 8
+            rate = units / (r["avg_ms"] * 1e-3) / 1e9
+            r["ceiling"] = dict(name=gkey, glanes_per_s=round(peaks[gkey]["glanes_per_s"], 2))
+            r["gathers_glanes_per_s"] = round(rate, 2)
+            r["frac_ceiling"] = round(rate / peaks[gkey]["glanes_per_s"], 4)
+            flops = (evaluated if k == "query_eval" else 2 * B) * mlp
+            tf = flops / (r["avg_ms"] * 1e-3) / 1e12
+            r["mlp"] = dict(tflops=round(tf, 2), frac_peak=round(tf / BF16_PEAK_TFLOPS, 4),
+                            ceiling_tflops=round(mf, 1), frac_ceiling=round(tf / mf, 4))
+        elif k == "scatter":
+            rate = r["algorithmic"] / 4 / (r["avg_ms"] * 1e-3) / 1e9
+            c = peaks["atomic_f32_32MiB_run1"]["gadds_per_s"]
+            r["ceiling"] = dict(name="atomic_f32_32MiB_run1", gadds_per_s=round(c, 2))
+            r["frac_ceiling"] = round(rate / c, 4)
+        elif r["unit"] == "GB/s":
+            r["ceiling"] = dict(name="stream_1024MiB", gbs=round(hbm, 1))
+            r["frac_ceiling"] = round(r["achieved"] / hbm, 4)
+    dom = roofline["kernel"]
+    for key in ("ceiling", "frac_ceiling", "gathers_glanes_per_s", "mlp"):
+        if key in per.get(dom, {}):
+            roofline[key] = per[dom][key]
 
 
 def rooflines(prof, net, tune, evaluated, B, R, n_segments, workload):
@@ -474,10 +593,69 @@ def run_batched(args, P, torch, configs, scene):
     step_ms = time_loop(step, args.steps)
     q_ms = time_loop(lambda i: batch.query(rays, seg_cap, hits), args.steps)
     t_ms = time_loop(lambda i: g.replay(), args.steps)
+    # per-kernel-group device time over eager steps (the grouped query is
+    # recorded by the first object's context, each training step by its own)
+    ev0 = [m.read_state()["n_evaluated"] for m in models]
+    for m in models:
+        m.profile_begin()
+    for i in range(args.steps):
+        batch.query(rays, seg_cap, hits)
+        for k, m in enumerate(models):
+            m.train_step(*batches[k], loss=losses[k])
+    prof = {}
+    for m in models:
+        for key, (ms, calls) in m.profile_end().items():
+            a = prof.get(key, (0.0, 0))
+            prof[key] = (a[0] + ms, a[1] + calls)
+    evaluated = sum(m.read_state()["n_evaluated"] - e for m, e in zip(models, ev0)) / max(1, args.steps)
     batch.query(rays, seg_cap, hits)
     torch.cuda.synchronize()
     assert all(m.read_state()["flags"] & 1 == 0 for m in models), "segment capacity exceeded"
     acc = hit_error(hits.cpu().numpy()[gt_idx], gt, diag)
+    # grouped launches: one query_eval launch covers every object, the
+    # training groups run once per object and step
+    n_segments = sum(m.read_state()["last_n_segments"] for m in models)
+    net0 = objs[0][1]
+    nb_each = batches[0][0].shape[0]
+    roofline = rooflines(prof, net0, models[0].get_tuning(), evaluated, nb_each, R, n_segments / len(models),
+                         "batched")
+    roofline["note"] = ("query_eval: one grouped launch per query over all objects; training groups: per object "
+                        "(2^18 probes each), averaged over the objects")
+    peaks = None
+    if not args.no_peaks:
+        from paper_2405_16237_amd import peaks as PK
+        peaks = PK.measure(torch)
+        against_ceilings(roofline, peaks, net0, evaluated, nb_each,
+                         max(sc_table_bytes(net) for _, net in objs))
+    # CPU baseline and parity: the oracle's grouped query (every object, the
+    # closest hit over objects, ties to the lower object) on every 64th ray
+    cpu, par = None, None
+    if not (args.no_cpu_baseline and args.no_parity):
+        import oracle
+        sub_idx = np.arange(0, R, 64)
+        sub = rays_np[sub_idx]
+        trained = [m.get_params() for m in models]
+        t2 = time.time()
+        best_t = np.full(sub.shape[0], np.inf)
+        best_code = np.full(sub.shape[0], -1, np.int64)
+        for k, ((sc, net), prm) in enumerate(zip(objs, trained)):
+            out, _, _ = oracle.query(oracle.make_cfg(net, sc.lo, sc.side), prm.astype(np.float64), sub, sc.boxes)
+            better = (out[:, 4] >= 0) & (out[:, 0] < best_t)
+            best_t[better] = out[better, 0]
+            best_code[better] = (k << 24) | out[better, 4].astype(np.int64)
+        dt = time.time() - t2
+        if not args.no_cpu_baseline:
+            cpu = dict(value=sub.shape[0] / dt, unit="rays/s", cores=oracle.num_threads(), kind="oracle",
+                       sample="every 64th ray (%d rays) against all 8 objects, full query in FP64, FP32 master "
+                              "parameters, %.1f s" % (sub.shape[0], dt))
+        if not args.no_parity:
+            word = hits.cpu().numpy()[sub_idx, 7].view(np.uint32)
+            got = np.where(word == 0xFFFFFFFF, -1, word.astype(np.int64))
+            same = (got == best_code) & (best_code >= 0)
+            dep = np.abs(hits.cpu().numpy()[sub_idx][same, 0] - best_t[same]) / diag
+            par = dict(bf16=dict(rays=int(sub.shape[0]), sample="every 64th ray", leaf_agreement=float((got == best_code).mean()),
+                                 depth_err_mean=float(dep.mean()) if same.any() else None,
+                                 oracle_params="FP32 master"))
     nb = sum(p.shape[0] for p, _ in batches)
     log("batched: step %.3f ms (query %.3f, train graph %.3f), hit acc %.4f" % (step_ms, q_ms, t_ms,
                                                                                acc["hit_accuracy"]))
@@ -504,10 +682,13 @@ def run_batched(args, P, torch, configs, scene):
         },
         "query_ms": q_ms,
         "train_ms": t_ms,
+        "segments_per_s": evaluated / (q_ms * 1e-3),
         "train_segs_per_s": nb / (t_ms * 1e-3),
         "accuracy": acc,
-        "roofline": None,
-        "cpu_baseline": None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": par,
+        "ceilings": peaks,
     }
 
 
@@ -535,6 +716,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true")
+    ap.add_argument("--no-parity", action="store_true", help="skip the comparison with the FP64 oracle")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the ceiling micro-benchmarks")
     ap.add_argument("--copy-kernel-mib", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB five times: the reference "
                          "dispatch that scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")

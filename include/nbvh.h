@@ -307,6 +307,32 @@ nbvh_status nbvh_traverse(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_ra
 nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_rays, nbvh_hit* hits_dev,
                        uint64_t seg_capacity, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Optional outputs of nbvh_query_traced (each pointer nullable, device):
+ * seg_offsets_dev [n_rays + 1] and segs_dev [seg_capacity] receive the
+ * segment queue the traversal built (as nbvh_traverse writes them; the
+ * segments only if they fit); z_dev [seg_capacity][n_out] receives the raw
+ * network outputs of every segment the query evaluates and u_dev
+ * [seg_capacity][n_in] the encoded features the MLP read for it (FP32 copies
+ * of the values in the kernel's feature tile: BF16-rounded under BF16; not
+ * available under FP8), both at the segment's position in the queue. Rows of
+ * segments skipped by early termination are left untouched, so a caller that
+ * fills them with NaN first can tell which segments were evaluated. */
+typedef struct {
+  uint32_t* seg_offsets_dev;
+  nbvh_segment* segs_dev;
+  float* z_dev;
+  float* u_dev;
+} nbvh_query_trace;
+
+/* nbvh_query with the same kernels and launch shapes, also writing the
+ * outputs `trace` asks for (Sec. 5; Fig. "neural ray query pipeline": the
+ * per-leaf network queries behind each hit record). For checking a query
+ * against a reference segment by segment; `trace` must not be NULL.
+ * NBVH_ERR_UNSUPPORTED for a feature trace under FP8. */
+nbvh_status nbvh_query_traced(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_rays, nbvh_hit* hits_dev,
+                              uint64_t seg_capacity, void* ws_dev, size_t ws_bytes,
+                              const nbvh_query_trace* trace, void* stream);
+
 /* Query over a caller-given segment queue (offsets/segments as written by
  * nbvh_traverse): evaluation and resolve only. */
 nbvh_status nbvh_query_segments(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_rays,
@@ -358,6 +384,27 @@ nbvh_status nbvh_group_by_leaf(nbvh_ctx* ctx, const nbvh_probe* probes_dev, cons
 nbvh_status nbvh_leaf_loss(nbvh_ctx* ctx, const nbvh_probe* probes_dev, const nbvh_label* labels_dev,
                            const uint32_t* leaf_ids_dev, uint64_t n, float* leaf_loss_dev,
                            uint32_t* leaf_count_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Node error rank of each leaf for the error-driven construction (Sec. 5.1,
+ * "Node error"): rank_dev[i] = 2 log q + log p with q = leaf_loss_dev[i] /
+ * leaf_count_dev[i] (the mean combined loss of the leaf's first-hit training
+ * segments, as nbvh_leaf_loss sums them) and p = leaf_hits_dev[i] / n_rays
+ * (the fraction of the n_rays sampled rays crossing the leaf, as
+ * nbvh_first_hits counts them); -inf where the count, the crossings or the
+ * loss is zero. Binary32, all arrays [n_leaves] on the device. No context
+ * needed. Asynchronous. */
+nbvh_status nbvh_node_rank(const float* leaf_loss_dev, const uint32_t* leaf_count_dev, const uint32_t* leaf_hits_dev,
+                           uint32_t n_leaves, uint64_t n_rays, float* rank_dev, void* stream);
+
+/* Per-leaf acceptance probability of first-hit training rays (Sec. 5.2,
+ * "Ray distribution"): accept_dev[i] = max(exp(r_i - r_max), min_accept)
+ * over the finite ranks of rank_dev, min_accept where r_i = -inf, and 1 for
+ * every leaf when no rank is finite. The paper writes max(r / r_max, 0.005);
+ * with r a sum of logarithms of numbers below one that ratio inverts the
+ * order, so it is taken in linear space (q^2 p relative to its maximum).
+ * min_accept in [0, 1]. One workgroup; asynchronous. */
+nbvh_status nbvh_acceptance(const float* rank_dev, uint32_t n_leaves, float min_accept, float* accept_dev,
+                            void* stream);
 
 /* Encoding only (Sec. 3/4): u_dev[n][n_in] FP32 features of each probe's
  * samples, read from the FP32 table (precision FP32) or the BF16 shadow. */
@@ -459,6 +506,33 @@ nbvh_status nbvh_profile_end(nbvh_ctx* ctx, nbvh_profile* out);
 
 /* Copy the device state block to the host (synchronises `stream`). */
 nbvh_status nbvh_read_state(nbvh_ctx* ctx, nbvh_state_host* out, void* stream);
+
+/* The state block's sticky NBVH_FLAG_* bits alone (synchronises `stream`):
+ * whether a query overflowed its segment capacity or a training step saw a
+ * non-finite gradient and was skipped. */
+nbvh_status nbvh_device_status(nbvh_ctx* ctx, uint32_t* flags_host, void* stream);
+
+/* Caller-owned buffers of a context, by role (nbvh_param_bytes). */
+typedef enum {
+  NBVH_BUF_PARAMS = 0,    /* FP32 master parameters: table and MLP weights */
+  NBVH_BUF_PARAMS_LP = 1, /* BF16 shadow of the parameters */
+  NBVH_BUF_ADAM_M = 2,    /* Adam first moments (FP32) */
+  NBVH_BUF_ADAM_V = 3,    /* Adam second moments (FP32) */
+  NBVH_BUF_GRAD = 4,      /* gradient accumulator (FP32, times the loss scale) */
+  NBVH_BUF_STATE = 5,     /* device state block */
+  NBVH_BUF_AUX = 6        /* transposed weights, E4M3 weights and scales */
+} nbvh_buffer;
+
+/* Bytes the caller allocates for buffer `which` (nbvh_buffer) of this
+ * context's network (Sec. 3 hash grid and Sec. 6 MLP sizes, padded to the
+ * layout of nbvh_param_layout); 0 for an unknown role or a NULL context. */
+size_t nbvh_param_bytes(const nbvh_ctx* ctx, int which);
+
+/* dL/dparams as the last back-propagation left it in grad_dev, divided by
+ * the current loss scale (the training step's loss scaling undone on the
+ * device), written to out_dev ([n_params] FP32, same layout; may be
+ * grad_dev itself). clear != 0 also zeroes grad_dev. Asynchronous. */
+nbvh_status nbvh_unscaled_grad(nbvh_ctx* ctx, float* out_dev, int clear, void* stream);
 
 /* Clear the sticky flag bits. */
 nbvh_status nbvh_clear_flags(nbvh_ctx* ctx, void* stream);

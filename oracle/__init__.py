@@ -67,6 +67,8 @@ def _lib():
             L.oc_min_abs_preact.argtypes = [P, P, P, I, P]
             L.oc_layer_amax.argtypes = [P, P, P, I, P]
             L.oc_resolve.argtypes = [I, P, P, P, P, P, ctypes.c_int, P, P]
+            L.oc_node_rank.argtypes = [I, P, P, P, I, P]
+            L.oc_acceptance.argtypes = [I, P, D, P]
             L.oc_num_threads.restype = ctypes.c_int
             _LIB = L
     return _LIB
@@ -299,6 +301,26 @@ def train_step(cfg, params, m, v, step, segs, labels, lr=1e-2, beta1=0.9, beta2=
     g = backward(cfg, params, segs, dz)
     adam(params, g, m, v, step, lr, beta1, beta2, eps)
     return terms
+
+
+# -- construction ------------------------------------------------------------------
+def node_rank(loss_sum, count, hits, n_rays):
+    """Sec. 5.1 node error rank r = 2 log q + log p per leaf (-inf where the
+    leaf saw no segment, no crossing or zero loss)."""
+    loss_sum = _c(loss_sum, np.float64)
+    count = _c(count, np.int64)
+    hits = _c(hits, np.int64)
+    r = np.zeros(loss_sum.shape[0], dtype=np.float64)
+    _lib().oc_node_rank(r.shape[0], _p(loss_sum), _p(count), _p(hits), int(n_rays), _p(r))
+    return r
+
+
+def acceptance(r, floor=0.005):
+    """Sec. 5.2 per-leaf training-ray acceptance max(exp(r - r_max), floor)."""
+    r = _c(r, np.float64)
+    a = np.zeros_like(r)
+    _lib().oc_acceptance(r.shape[0], _p(r), float(floor), _p(a))
+    return a
 
 
 # -- query -------------------------------------------------------------------------

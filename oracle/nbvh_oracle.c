@@ -407,7 +407,8 @@ void oc_layer_amax(const oc_cfg* c, const double* params, const float* segs, int
 /* loss_out: total, bce, dist, normal (the last three unweighted; the       */
 /* albedo term only enters the total). dz (optional) = dL/dz.               */
 /* Relative L2 of one channel: (a_hat - a)^2 / (a_hat^2 + 0.01), mean over  */
-/* the three channels, differentiated through the denominator too.          */
+/* the three channels; the denominator only normalises the error and is     */
+/* held constant in the derivative, as in relative L2 losses generally.     */
 /* ------------------------------------------------------------------------ */
 static double oc_sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 static double oc_sgn(double v) { return (v > 0.0) - (v < 0.0); }
@@ -420,8 +421,9 @@ static double oc_albedo_term(const double* zi, const float* lb, double* dterm /*
     double den = ah * ah + kRelEps;
     s += (ah - a) * (ah - a) / den;
     if (dterm) {
-      /* d/da_hat of (a_hat - a)^2 / (a_hat^2 + eps), times d a_hat / dz */
-      double d = (2.0 * (ah - a) * den - (ah - a) * (ah - a) * 2.0 * ah) / (den * den);
+      /* 2 (a_hat - a) / (a_hat^2 + eps), the denominator held constant,   */
+      /* times d a_hat / dz                                                 */
+      double d = 2.0 * (ah - a) / den;
       dterm[ch] = d * ah * (1.0 - ah) / 3.0;
     }
   }
@@ -665,6 +667,44 @@ void oc_resolve(int64_t n_rays, const uint64_t* offsets, const uint32_t* seg_lea
     o[5] = (double)bs;
     if (n_out >= 8)
       for (int a = 0; a < 3; ++a) o[6 + a] = oc_sigmoid(zk[5 + a]);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Node error rank (Sec. 5.1, "Node error"): r = 2 log q + log p, where q is  */
+/* the leaf's mean combined training loss (loss_sum / count over the          */
+/* first-hit segments it received) and p the fraction of the n_rays sampled  */
+/* rays that cross it (hits / n_rays). No segment, no crossing or a zero loss */
+/* gives r = -inf.                                                            */
+/* ------------------------------------------------------------------------ */
+void oc_node_rank(int64_t n, const double* loss_sum, const int64_t* count, const int64_t* hits, int64_t n_rays,
+                  double* r) {
+  for (int64_t i = 0; i < n; ++i) {
+    if (count[i] <= 0 || hits[i] <= 0 || n_rays <= 0) {
+      r[i] = -INFINITY;
+      continue;
+    }
+    const double q = loss_sum[i] / (double)count[i];
+    const double p = (double)hits[i] / (double)n_rays;
+    r[i] = 2.0 * log(q) + log(p);
+  }
+}
+
+/* Acceptance probability of a leaf's first-hit training rays (Sec. 5.2, "Ray */
+/* distribution"), read in linear space: a = max(exp(r - r_max), floor) over  */
+/* the finite ranks, the floor for r = -inf, and 1 everywhere when no rank is */
+/* finite.                                                                    */
+void oc_acceptance(int64_t n, const double* r, double floor_, double* a) {
+  double rmax = -INFINITY;
+  for (int64_t i = 0; i < n; ++i)
+    if (isfinite(r[i]) && r[i] > rmax) rmax = r[i];
+  for (int64_t i = 0; i < n; ++i) {
+    if (!isfinite(rmax)) {
+      a[i] = 1.0;
+      continue;
+    }
+    const double e = isfinite(r[i]) ? exp(r[i] - rmax) : 0.0;
+    a[i] = e > floor_ ? e : floor_;
   }
 }
 

@@ -19,6 +19,8 @@ NBVH_MAX_LEVELS = 32
 NBVH_MISS = 0xFFFFFFFF
 NBVH_INSIDE_CLIP, NBVH_INSIDE_REVERSE = 0, 1
 NBVH_SEG_INSIDE = 0x80000000
+(NBVH_BUF_PARAMS, NBVH_BUF_PARAMS_LP, NBVH_BUF_ADAM_M, NBVH_BUF_ADAM_V, NBVH_BUF_GRAD, NBVH_BUF_STATE,
+ NBVH_BUF_AUX) = range(7)
 
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "CAPACITY", 3: "NOT_BOUND", 4: "HIP", 5: "UNSUPPORTED"}
 
@@ -57,6 +59,11 @@ class NbvhTuning(ctypes.Structure):
                 ("query_pairs", ctypes.c_int32), ("query_lds_kb", ctypes.c_int32)]
 
 
+class NbvhQueryTrace(ctypes.Structure):
+    _fields_ = [("seg_offsets_dev", ctypes.c_void_p), ("segs_dev", ctypes.c_void_p), ("z_dev", ctypes.c_void_p),
+                ("u_dev", ctypes.c_void_p)]
+
+
 class NbvhStateHost(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("skipped", ctypes.c_int64), ("loss_scale", ctypes.c_float),
                 ("flags", ctypes.c_uint32), ("last_loss", ctypes.c_float * 4), ("last_n_segments", ctypes.c_uint64),
@@ -68,9 +75,9 @@ EXPORTS = [
     "nbvh_param_count", "nbvh_param_layout", "nbvh_aux_bytes", "nbvh_nodes_bytes", "nbvh_state_bytes", "nbvh_build",
     "nbvh_bind_params", "nbvh_reset_optimizer", "nbvh_sync_shadow", "nbvh_calibrate_fp8", "nbvh_workspace_bytes",
     "nbvh_traverse",
-    "nbvh_query", "nbvh_query_segments", "nbvh_first_hits", "nbvh_group_ws_bytes", "nbvh_group_by_leaf", "nbvh_leaf_loss", "nbvh_encode", "nbvh_forward", "nbvh_backward", "nbvh_optimizer_step",
+    "nbvh_query", "nbvh_query_traced", "nbvh_query_segments", "nbvh_first_hits", "nbvh_group_ws_bytes", "nbvh_group_by_leaf", "nbvh_leaf_loss", "nbvh_node_rank", "nbvh_acceptance", "nbvh_encode", "nbvh_forward", "nbvh_backward", "nbvh_optimizer_step",
     "nbvh_train_step", "nbvh_loss", "nbvh_batch_desc_bytes", "nbvh_batch_create", "nbvh_batch_workspace_bytes",
-    "nbvh_batch_query", "nbvh_batch_destroy", "nbvh_get_tuning", "nbvh_set_tuning", "nbvh_profile_begin", "nbvh_profile_end", "nbvh_read_state", "nbvh_clear_flags", "nbvh_last_error", "nbvh_version",
+    "nbvh_batch_query", "nbvh_batch_destroy", "nbvh_get_tuning", "nbvh_set_tuning", "nbvh_profile_begin", "nbvh_profile_end", "nbvh_read_state", "nbvh_device_status", "nbvh_param_bytes", "nbvh_unscaled_grad", "nbvh_clear_flags", "nbvh_last_error", "nbvh_version",
     "nbvh_destroy",
 ]
 
@@ -107,12 +114,15 @@ def load(path: str = LIB_PATH):
         "nbvh_workspace_bytes": (SZ, [P, U64, U64, U64]),
         "nbvh_traverse": (st, [P, P, U64, P, P, U64, P, SZ, P]),
         "nbvh_query": (st, [P, P, U64, P, U64, P, SZ, P]),
+        "nbvh_query_traced": (st, [P, P, U64, P, U64, P, SZ, P, P]),
         "nbvh_query_segments": (st, [P, P, U64, P, P, P, P, SZ, P]),
         "nbvh_encode": (st, [P, P, U64, P, P]),
         "nbvh_first_hits": (st, [P, P, U64, P, P, P, P, P, P, P]),
         "nbvh_group_ws_bytes": (SZ, [U64]),
         "nbvh_group_by_leaf": (st, [P, P, P, U64, P, P, P, SZ, P]),
         "nbvh_leaf_loss": (st, [P, P, P, P, U64, P, P, P, SZ, P]),
+        "nbvh_node_rank": (st, [P, P, P, ctypes.c_uint32, U64, P, P]),
+        "nbvh_acceptance": (st, [P, ctypes.c_uint32, ctypes.c_float, P, P]),
         "nbvh_forward": (st, [P, P, U64, P, P, SZ, P]),
         "nbvh_backward": (st, [P, P, U64, P, P, SZ, P]),
         "nbvh_optimizer_step": (st, [P, P]),
@@ -129,6 +139,9 @@ def load(path: str = LIB_PATH):
         "nbvh_profile_end": (st, [P, P]),
         "nbvh_read_state": (st, [P, P, P]),
         "nbvh_clear_flags": (st, [P, P]),
+        "nbvh_device_status": (st, [P, P, P]),
+        "nbvh_param_bytes": (SZ, [P, ctypes.c_int]),
+        "nbvh_unscaled_grad": (st, [P, P, ctypes.c_int, P]),
         "nbvh_last_error": (ctypes.c_char_p, []),
         "nbvh_version": (ctypes.c_char_p, []),
         "nbvh_destroy": (None, [P]),

@@ -32,9 +32,8 @@ class NBVHFunction(torch.autograd.Function):
         (probes,) = ctx.saved_tensors
         model.grad.zero_()
         model.backward(probes, dz.contiguous().float())
-        scale = model.read_state()["loss_scale"]
-        g = model.grad / scale
-        model.grad.zero_()
+        # the library divides out its loss scale and clears its accumulator
+        g = model.unscaled_grad(clear=True)
         return g, None, None
 
 

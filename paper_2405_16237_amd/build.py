@@ -38,8 +38,27 @@ def _compile(src: str) -> str:
     return obj
 
 
+PEAKS_SRC = os.path.join(HERE, "peaks", "peaks.hip")
+PEAKS_OUT = os.path.join(HERE, "peaks", "libnbvh_peaks.so")
+
+
+def build_peaks(verbose: bool = False) -> str:
+    """The ceiling micro-benchmarks (a separate library: not part of the
+    N-BVH path)."""
+    tmp = PEAKS_OUT + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-shared", "-o", tmp, PEAKS_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for peaks.hip:\n%s" % r.stderr[-4000:])
+    os.replace(tmp, PEAKS_OUT)
+    if verbose:
+        print("built", PEAKS_OUT)
+    return PEAKS_OUT
+
+
 def build(verbose: bool = False) -> str:
-    """Compile all sources and link libnbvh.so (always rebuilds)."""
+    """Compile all sources and link libnbvh.so (always rebuilds), and the
+    ceiling micro-benchmarks."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
@@ -51,6 +70,7 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, OUT)
     if verbose:
         print("built", OUT)
+    build_peaks(verbose)
     return OUT
 
 

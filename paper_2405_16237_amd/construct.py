@@ -26,8 +26,9 @@ the current cut uniformly at random and trains on its nodes, each level with
 the acceptance probabilities it had when registered.
 
 The driver runs on the host; every per-ray and per-segment step (traversal,
-first-hit selection, crossing counts, network, loss, per-leaf sums,
-training) is a library call. Labels come from the caller (classical
+first-hit selection, crossing counts, network, loss, per-leaf sums, ranks,
+acceptance probabilities, training) is a library call; the host only orders
+the leaves by rank to choose the splits. Labels come from the caller (classical
 triangle intersection), as the paper's training data does.
 """
 from __future__ import annotations
@@ -38,7 +39,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from .nbvh import NBVH
+from .nbvh import NBVH, acceptance, node_rank
 
 
 @dataclass
@@ -64,24 +65,6 @@ class Cut:
     def boxes(self, base) -> np.ndarray:
         idx = np.asarray(self.nodes, dtype=np.int64)
         return np.concatenate([base["lo"][idx], base["hi"][idx]], axis=1).astype(np.float32)
-
-
-def rank(leaf_loss_sum: np.ndarray, leaf_count: np.ndarray, leaf_hits: np.ndarray, n_rays: int) -> np.ndarray:
-    """r = 2 log q + log p per leaf; -inf where a leaf saw no segment or no ray."""
-    q = np.where(leaf_count > 0, leaf_loss_sum / np.maximum(leaf_count, 1), 0.0)
-    p = leaf_hits / float(max(n_rays, 1))
-    with np.errstate(divide="ignore"):
-        return 2.0 * np.log(q) + np.log(p)
-
-
-def acceptance(r: np.ndarray, floor: float) -> np.ndarray:
-    """Training probability of each leaf's first-hit segments:
-    max(exp(r - r_max), floor); the floor where r is -inf."""
-    finite = np.isfinite(r)
-    if not finite.any():
-        return np.ones_like(r)
-    a = np.exp(np.where(finite, r - r[finite].max(), -np.inf))
-    return np.maximum(a, floor)
 
 
 def choose_splits(cut: Cut, base, r: np.ndarray, k: int) -> list:
@@ -182,13 +165,14 @@ def construct(net, base, label_fn, schedule: Schedule, scene_lo, scene_side, par
         if probes.shape[0]:
             lab = torch.from_numpy(label_fn(probes.cpu().numpy())).to(model.device)
             model.leaf_loss(probes.contiguous(), lab, leaf.contiguous(), loss, count)
-        return rank(loss.double().cpu().numpy(), count.cpu().numpy(), hits.cpu().numpy(), schedule.stats_rays)
+        return node_rank(loss, count, hits, schedule.stats_rays)
 
     iters, splits = float(schedule.iters), float(schedule.splits)
     while len(cut.nodes) < schedule.target_leaves:
         mean_loss = train(int(round(iters)))
-        r = statistics()
-        accept = torch.tensor(acceptance(r, schedule.min_accept), dtype=torch.float32, device=model.device)
+        r_dev = statistics()
+        accept = acceptance(r_dev, schedule.min_accept)
+        r = r_dev.double().cpu().numpy()
         maybe_register()
         k = min(int(round(splits)), schedule.target_leaves - len(cut.nodes))
         pos = choose_splits(cut, base, r, k)
@@ -198,13 +182,12 @@ def construct(net, base, label_fn, schedule: Schedule, scene_lo, scene_side, par
                                                                            mean_loss, len(pos)))
         if not pos:
             break  # nothing left to split
-        new_r = np.concatenate([r, np.zeros(len(pos))])
         cut = expand(cut, base, pos)
         model.rebuild(cut.boxes(base))
-        # children start from their parent's rank until the next statistics
-        for j, i in enumerate(pos):
-            new_r[len(cut.nodes) - len(pos) + j] = r[i]
-        accept = torch.tensor(acceptance(new_r, schedule.min_accept), dtype=torch.float32, device=model.device)
+        # children start from their parent's rank until the next statistics:
+        # the left child keeps the parent's position, the right one is appended
+        new_r = torch.cat([r_dev, r_dev[torch.as_tensor(pos, dtype=torch.int64, device=model.device)]])
+        accept = acceptance(new_r, schedule.min_accept)
         iters *= schedule.iters_growth
         splits *= schedule.splits_growth
     final = train(schedule.final_iters)

@@ -466,6 +466,41 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbv
                            (uint32_t)n_rays, seg_capacity);
 }
 
+nbvh_status nbvh_query_traced(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbvh_hit* hits,
+                              uint64_t seg_capacity, void* ws, size_t ws_bytes, const nbvh_query_trace* trace,
+                              void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  s = require_fp8_ready(ctx);
+  if (s != NBVH_OK) return s;
+  if (!trace) return set_error("trace is NULL"), NBVH_ERR_INVALID_ARG;
+  if (trace->u_dev && ctx->cfg.precision == NBVH_FP8)
+    return set_error("FP8 queries keep scaled E4M3 features: no feature trace"), NBVH_ERR_UNSUPPORTED;
+  if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
+  if ((n_rays && (!rays || !hits)) || !ws) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  if (seg_capacity > 0xffffffffull) seg_capacity = 0xffffffffull;
+  const QueryLayout Q = query_layout(n_rays, seg_capacity);
+  if (ws_bytes < Q.total) return set_error("workspace too small: need %zu, got %zu", Q.total, ws_bytes), NBVH_ERR_CAPACITY;
+  if (n_rays == 0) return NBVH_OK;
+  LaunchCtx L = make_launch(ctx, stream);
+  char* w = (char*)ws;
+  uint32_t* offsets = (uint32_t*)(w + Q.offsets);
+  uint32_t* misc = (uint32_t*)(w + Q.misc);
+  nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
+  s = launch_traverse(L, rays, (uint32_t)n_rays, offsets, segs, seg_capacity, hits, (uint32_t*)(w + Q.active), misc + 0,
+                      (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12, (float*)(w + Q.staging));
+  if (s != NBVH_OK) return s;
+  if (trace->seg_offsets_dev &&
+      hipMemcpyAsync(trace->seg_offsets_dev, offsets, (n_rays + 1) * 4, hipMemcpyDeviceToDevice, L.stream) != hipSuccess)
+    return set_error("copy of the segment offsets failed"), NBVH_ERR_HIP;
+  if (trace->segs_dev && seg_capacity &&
+      hipMemcpyAsync(trace->segs_dev, segs, seg_capacity * sizeof(nbvh_segment), hipMemcpyDeviceToDevice, L.stream) !=
+          hipSuccess)
+    return set_error("copy of the segment queue failed"), NBVH_ERR_HIP;
+  return launch_query_eval(L, rays, offsets, segs, (const uint32_t*)(w + Q.active), misc + 0, misc + 1, hits,
+                           (uint32_t)n_rays, seg_capacity, trace->z_dev, trace->u_dev);
+}
+
 nbvh_status nbvh_query_segments(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, const uint32_t* seg_offsets,
                                 const nbvh_segment* segs, nbvh_hit* hits, void* ws, size_t ws_bytes, void* stream) {
   nbvh_status s = require_bound(ctx);
@@ -527,6 +562,18 @@ nbvh_status nbvh_leaf_loss(nbvh_ctx* ctx, const nbvh_probe* probes, const nbvh_l
   if (ws_bytes < need) return set_error("workspace too small: need %zu", need), NBVH_ERR_CAPACITY;
   return launch_leaf_loss(make_launch(ctx, stream), probes, labels, leaf_ids, (uint32_t)n, (float*)ws, leaf_loss,
                           leaf_count);
+}
+
+nbvh_status nbvh_node_rank(const float* leaf_loss, const uint32_t* leaf_count, const uint32_t* leaf_hits,
+                           uint32_t n_leaves, uint64_t n_rays, float* rank, void* stream) {
+  if (n_leaves && (!leaf_loss || !leaf_count || !leaf_hits || !rank)) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  return launch_node_rank((hipStream_t)stream, leaf_loss, leaf_count, leaf_hits, n_leaves, n_rays, rank);
+}
+
+nbvh_status nbvh_acceptance(const float* rank, uint32_t n_leaves, float min_accept, float* accept, void* stream) {
+  if (n_leaves && (!rank || !accept)) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
+  if (!(min_accept >= 0.0f && min_accept <= 1.0f)) return set_error("min_accept outside [0, 1]"), NBVH_ERR_INVALID_ARG;
+  return launch_acceptance((hipStream_t)stream, rank, n_leaves, min_accept, accept);
 }
 
 nbvh_status nbvh_encode(nbvh_ctx* ctx, const nbvh_probe* probes, uint64_t n, float* u, void* stream) {
@@ -609,6 +656,42 @@ nbvh_status nbvh_read_state(nbvh_ctx* ctx, nbvh_state_host* out, void* stream) {
   out->last_n_segments = st.last_n_segments;
   out->n_evaluated = st.n_evaluated;
   return NBVH_OK;
+}
+
+nbvh_status nbvh_device_status(nbvh_ctx* ctx, uint32_t* flags_host, void* stream) {
+  if (!flags_host) return set_error("flags_host is NULL"), NBVH_ERR_INVALID_ARG;
+  nbvh_state_host st;
+  nbvh_status s = nbvh_read_state(ctx, &st, stream);
+  if (s != NBVH_OK) return s;
+  *flags_host = st.flags;
+  return NBVH_OK;
+}
+
+size_t nbvh_param_bytes(const nbvh_ctx* ctx, int which) {
+  if (!ctx) return 0;
+  const uint64_t n = ctx->dev.n_params;
+  switch (which) {
+    case NBVH_BUF_PARAMS:
+    case NBVH_BUF_ADAM_M:
+    case NBVH_BUF_ADAM_V:
+    case NBVH_BUF_GRAD:
+      return (size_t)n * 4;
+    case NBVH_BUF_PARAMS_LP:
+      return (size_t)n * 2;
+    case NBVH_BUF_STATE:
+      return sizeof(DevState);
+    case NBVH_BUF_AUX:
+      return (size_t)aux_total_bytes(ctx->dev);
+    default:
+      return 0;
+  }
+}
+
+nbvh_status nbvh_unscaled_grad(nbvh_ctx* ctx, float* out_dev, int clear, void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  if (!out_dev) return set_error("out_dev is NULL"), NBVH_ERR_INVALID_ARG;
+  return launch_unscale_grad(make_launch(ctx, stream), out_dev, clear != 0);
 }
 
 __global__ void k_clear_flags(DevState* s) {

@@ -84,6 +84,10 @@ struct QueryJob {
   DevState* state;
   uint32_t lds_words;  // 4-byte words of the table's leading levels copied to LDS (0: none)
   int lds_levels;      // levels gathered from that copy
+  // optional per-segment outputs (nullptr: not written), indexed by the
+  // segment's queue position: logits [cap][n_out] and features [cap][n_in]
+  float* z_trace;
+  float* u_trace;
 };
 
 // LDS bytes of the slot state and tiles, before the staged table levels
@@ -205,10 +209,24 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
       const PreBf16 pre0 = prefetch_bf16<NW>((const bf16*)J.W + c.w_off[0], c.fan_in[0], c.fan_in[0], c.fan_out[0]);
       encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM, 1.0f, ltab, J.lds_levels);
       __syncthreads();
+      if (J.u_trace) {
+        for (int e = threadIdx.x; e < kQM * c.n_in; e += blockDim.x) {
+          const int m = e / c.n_in, k = e - m * c.n_in;
+          if (s_valid[m]) J.u_trace[(size_t)s_cur[m] * c.n_in + k] = (float)act0[m * ld0 + k];
+        }
+        __syncthreads();
+      }
       mlp_forward_tile<kQM, NW, AT>(c, (const AT*)J.W, act0, ld0, act1, ld1, z, kOutPad, &pre0);
     } else {
       encode_tile<AT, F, LP, NW, U, PR>(c, J.table, sA, sB, s_valid, act0, ld0, kQM, 1.0f, ltab, J.lds_levels);
       __syncthreads();
+      if (J.u_trace) {  // uniform over the launch: the feature tile as the MLP reads it
+        for (int e = threadIdx.x; e < kQM * c.n_in; e += blockDim.x) {
+          const int m = e / c.n_in, k = e - m * c.n_in;
+          if (s_valid[m]) J.u_trace[(size_t)s_cur[m] * c.n_in + k] = (float)act0[m * ld0 + k];
+        }
+        __syncthreads();
+      }
       mlp_forward_tile<kQM, NW, AT>(c, (const AT*)J.W, act0, ld0, act1, ld1, z, kOutPad);
     }
 
@@ -218,6 +236,8 @@ __device__ inline void query_eval_loop(const DevCfg& c, const QueryJob& J, unsig
       const float t0 = sA[lane].w, t1 = sB[lane].w;
       float best_t = s_bt[lane];
       const float* zr = z + lane * kOutPad;
+      if (J.z_trace)
+        for (int o = 0; o < c.n_out; ++o) J.z_trace[(size_t)s_cur[lane] * c.n_out + o] = zr[o];
       const uint32_t leaf = s_leaf[lane];
       const bool in = (leaf & NBVH_SEG_INSIDE) != 0u;
       if (zr[0] > 0.0f) {
@@ -489,6 +509,8 @@ nbvh_status launch_query_eval_batch(const LaunchCtx* Ls, int n_obj, const DevCfg
     J.state = Lk.state;
     J.lds_words = 0;  // objects differ in their tables: nothing staged
     J.lds_levels = 0;
+    J.z_trace = nullptr;
+    J.u_trace = nullptr;
   }
 #define NBVH_QB(AT, F, LP, NW, U, PR) \
   return query_batch_t<AT, F, LP, NW, U, PR>(Ls, n_obj, cfgs_dev, jobs, per_obj, hits, n_rays)
@@ -499,7 +521,8 @@ nbvh_status launch_query_eval_batch(const LaunchCtx* Ls, int n_obj, const DevCfg
 template <typename AT, int F, bool LP, int NW, int U, bool PR>
 static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
                                 const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
-                                uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity) {
+                                uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity,
+                                float* z_trace, float* u_trace) {
   const DevCfg& c = L.cfg;
   // leading levels staged in LDS: as many whole levels as the budget holds
   int lds_levels = 0;
@@ -538,6 +561,8 @@ static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const 
   J.state = L.state;
   J.lds_words = (uint32_t)(staged / 4);
   J.lds_levels = lds_levels;
+  J.z_trace = z_trace;
+  J.u_trace = sizeof(AT) == 1 ? nullptr : u_trace;
   ProfScope ps(L.prof, NBVH_K_QUERY_EVAL, L.stream);
   kern<<<grid, 64 * NW, lds, L.stream>>>(c, J);
   return check_launch("query_eval");
@@ -545,9 +570,11 @@ static nbvh_status query_eval_t(const LaunchCtx& L, const nbvh_ray* rays, const 
 
 nbvh_status launch_query_eval(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
                               const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
-                              uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity) {
-#define NBVH_QE(AT, F, LP, NW, U, PR) \
-  return query_eval_t<AT, F, LP, NW, U, PR>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, capacity)
+                              uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity,
+                              float* z_trace, float* u_trace) {
+#define NBVH_QE(AT, F, LP, NW, U, PR)                                                                          \
+  return query_eval_t<AT, F, LP, NW, U, PR>(L, rays, offsets, segs, active, n_active, counter, hits, n_rays_bound, \
+                                            capacity, z_trace, u_trace)
   NBVH_DISPATCH_QUERY(L, NBVH_QE);
 #undef NBVH_QE
 }

@@ -134,9 +134,10 @@ __device__ inline void put(AT* p, float v) {
 }
 
 // Albedo (outputs 5..7 through a sigmoid; Sec. 5.2 "Auxiliary data"): relative
-// L2, (a_hat - a)^2 / (a_hat^2 + 0.01) averaged over the channels, its
-// derivative taken through the denominator as well. Returns the term and
-// writes d(term)/dz for the three outputs.
+// L2, (a_hat - a)^2 / (a_hat^2 + 0.01) averaged over the channels. As relative
+// L2 losses are defined, the denominator normalises the error and is held
+// constant in the derivative: d/da_hat = 2 (a_hat - a) / (a_hat^2 + 0.01).
+// Returns the term and writes d(term)/dz for the three outputs.
 __device__ inline float albedo_term(const float* zr, const float* a, float dz[3]) {
   float s = 0.0f;
 #pragma unroll
@@ -145,7 +146,7 @@ __device__ inline float albedo_term(const float* zr, const float* a, float dz[3]
     const float den = ah * ah + 0.01f;
     const float d = ah - a[ch];
     s += d * d / den;
-    dz[ch] = (2.0f * d * den - d * d * 2.0f * ah) / (den * den) * ah * (1.0f - ah) * (1.0f / 3.0f);
+    dz[ch] = 2.0f * d / den * ah * (1.0f - ah) * (1.0f / 3.0f);
   }
   return s * (1.0f / 3.0f);
 }
@@ -1502,6 +1503,89 @@ nbvh_status launch_loss(const LaunchCtx& L, const float* z, const nbvh_label* la
   k_loss<<<nb, 256, 0, L.stream>>>(z, labels, n, L.cfg.n_out, L.w_hit, L.w_t, L.w_normal, L.w_albedo, dz, part);
   k_loss_finalize<<<1, 256, 0, L.stream>>>(part, nb, n, L.w_hit, L.w_t, L.w_normal, L.w_albedo, loss_dev, L.state);
   return check_launch("loss");
+}
+
+// Node error rank of each leaf (Sec. 5.1): r = 2 log q + log p with q the
+// mean training loss of its first-hit segments and p the fraction of the
+// sampled rays crossing it; -inf without segments, crossings or loss.
+__global__ __launch_bounds__(256) void k_node_rank(const float* __restrict__ loss, const uint32_t* __restrict__ count,
+                                                  const uint32_t* __restrict__ hits, uint32_t n, float inv_rays,
+                                                  float* __restrict__ rank) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t c = count[i], h = hits[i];
+  float r = -INFINITY;
+  if (c > 0u && h > 0u && inv_rays > 0.0f) {
+    const float q = loss[i] / (float)c;
+    const float p = (float)h * inv_rays;
+    if (q > 0.0f) r = 2.0f * logf(q) + logf(p);
+  }
+  rank[i] = r;
+}
+
+// Acceptance of each leaf's first-hit training rays (Sec. 5.2, read in
+// linear space): max(exp(r - r_max), floor); floor for r = -inf; 1 when no
+// rank is finite. One workgroup: the maximum is a block reduction.
+__global__ __launch_bounds__(1024) void k_acceptance(const float* __restrict__ rank, uint32_t n, float floor_,
+                                                    float* __restrict__ accept) {
+  __shared__ float red[16];
+  float m = -INFINITY;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const float r = rank[i];
+    if (r > m && r < INFINITY) m = r;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    float v = threadIdx.x < (blockDim.x >> 6) ? red[threadIdx.x] : -INFINITY;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    if (threadIdx.x == 0) red[0] = v;
+  }
+  __syncthreads();
+  const float rmax = red[0];
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const float r = rank[i];
+    float a = 1.0f;
+    if (rmax > -INFINITY) {
+      const float e = (r > -INFINITY) ? expf(r - rmax) : 0.0f;
+      a = e > floor_ ? e : floor_;
+    }
+    accept[i] = a;
+  }
+}
+
+nbvh_status launch_node_rank(hipStream_t s, const float* loss, const uint32_t* count, const uint32_t* hits, uint32_t n,
+                             uint64_t n_rays, float* rank) {
+  if (n) k_node_rank<<<(n + 255) / 256, 256, 0, s>>>(loss, count, hits, n, n_rays ? 1.0f / (float)n_rays : 0.0f, rank);
+  return check_launch("node_rank");
+}
+
+nbvh_status launch_acceptance(hipStream_t s, const float* rank, uint32_t n, float floor_, float* accept) {
+  if (n) k_acceptance<<<1, 1024, 0, s>>>(rank, n, floor_, accept);
+  return check_launch("acceptance");
+}
+
+// dL/dparams without the loss scale: out = grad / state.loss_scale (the
+// scale the last backward multiplied in), grad cleared when asked.
+__global__ __launch_bounds__(256) void k_unscale_grad(float* __restrict__ grad, uint64_t n, const DevState* state,
+                                                     float* __restrict__ out, int clear) {
+  const float inv = 1.0f / state->loss_scale;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const float g = grad[i];
+    if (clear) grad[i] = 0.0f;
+    out[i] = g * inv;
+  }
+}
+
+nbvh_status launch_unscale_grad(const LaunchCtx& L, float* out, bool clear) {
+  const uint64_t n = L.cfg.n_params;
+  const uint64_t want = (n + 255) / 256;
+  const uint32_t grid = (uint32_t)(want < 1 ? 1 : (want > 65536 ? 65536 : want));
+  k_unscale_grad<<<grid, 256, 0, L.stream>>>(L.grad, n, L.state, out, clear ? 1 : 0);
+  return check_launch("unscale_grad");
 }
 
 nbvh_status launch_optimizer(const LaunchCtx& L, bool reset, bool shadow_only) {

@@ -85,9 +85,13 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
                             uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
                             uint32_t* scratch_total, float* staging);
 
+// z_trace / u_trace (nullable): each evaluated segment's logits [cap][n_out]
+// and FP32 copy of its LDS feature row [cap][n_in] (not in FP8), at the
+// segment's queue position; rows of segments not evaluated are untouched.
 nbvh_status launch_query_eval(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* offsets,
                               const nbvh_segment* segs, const uint32_t* active, const uint32_t* n_active,
-                              uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity);
+                              uint32_t* counter, nbvh_hit* hits, uint32_t n_rays_bound, uint64_t capacity,
+                              float* z_trace = nullptr, float* u_trace = nullptr);
 
 nbvh_status launch_query_eval_batch(const LaunchCtx* Ls, int n_obj, const DevCfg* cfgs_dev, const uint32_t* const* offsets,
                                     const nbvh_segment* const* segs, const uint32_t* const* active,
@@ -128,5 +132,9 @@ nbvh_status launch_train_fwd_bwd(const LaunchCtx& L, const nbvh_probe* probes, c
 nbvh_status launch_loss(const LaunchCtx& L, const float* z, const nbvh_label* labels, uint32_t n, float* loss_dev,
                         float* dz, void* ws, size_t ws_bytes);
 nbvh_status launch_optimizer(const LaunchCtx& L, bool reset, bool shadow_only);
+nbvh_status launch_unscale_grad(const LaunchCtx& L, float* out, bool clear);
+nbvh_status launch_node_rank(hipStream_t s, const float* loss, const uint32_t* count, const uint32_t* hits, uint32_t n,
+                             uint64_t n_rays, float* rank);
+nbvh_status launch_acceptance(hipStream_t s, const float* rank, uint32_t n, float floor_, float* accept);
 
 }  // namespace nbvh

@@ -252,6 +252,26 @@ class NBVH:
                                   _stream()))
         return hits
 
+    def query_traced(self, rays: torch.Tensor, seg_capacity: int | None = None, z=True, u=False):
+        """query() through nbvh_query_traced: returns (hits, offsets [n+1]
+        int32, segs [cap][4] int32, z [cap][n_out] or None, u [cap][n_in] or
+        None); rows of z and u stay NaN for segments the query did not
+        evaluate (early termination)."""
+        n = rays.shape[0]
+        if seg_capacity is None:
+            seg_capacity = 8 * n + 1024
+        hits = torch.empty((n, 8), dtype=torch.float32, device=self.device)
+        offsets = torch.empty(n + 1, dtype=torch.int32, device=self.device)
+        segs = torch.empty((max(seg_capacity, 1), 4), dtype=torch.int32, device=self.device)
+        zt = torch.full((max(seg_capacity, 1), self.net.n_out), float("nan"), device=self.device) if z else None
+        ut = torch.full((max(seg_capacity, 1), self.net.n_in), float("nan"), device=self.device) if u else None
+        tr = _abi.NbvhQueryTrace(_ptr(offsets).value, _ptr(segs).value, _ptr(zt).value if z else None,
+                                 _ptr(ut).value if u else None)
+        ws = self.workspace(n, seg_capacity, 0)
+        check(self.lib.nbvh_query_traced(self.ctx, _ptr(rays), n, _ptr(hits), seg_capacity, _ptr(ws), ws.numel(),
+                                         ctypes.byref(tr), _stream()))
+        return hits, offsets, segs, zt, ut
+
     def encode(self, probes: torch.Tensor):
         n = probes.shape[0]
         u = torch.empty((n, self.net.n_samples * self.net.n_levels * self.net.n_features), dtype=torch.float32,
@@ -330,6 +350,22 @@ class NBVH:
         return dict(step=s.step, skipped=s.skipped, loss_scale=s.loss_scale, flags=s.flags,
                     last_loss=list(s.last_loss), last_n_segments=s.last_n_segments, n_evaluated=s.n_evaluated)
 
+    def device_status(self) -> int:
+        """The sticky NBVH_FLAG_* bits (synchronises)."""
+        f = ctypes.c_uint32()
+        check(self.lib.nbvh_device_status(self.ctx, ctypes.byref(f), _stream()))
+        return f.value
+
+    def param_bytes(self, which: int) -> int:
+        return int(self.lib.nbvh_param_bytes(self.ctx, int(which)))
+
+    def unscaled_grad(self, out: torch.Tensor | None = None, clear: bool = False) -> torch.Tensor:
+        """grad / loss scale, computed on the device (out may be self.grad)."""
+        if out is None:
+            out = torch.empty_like(self.grad)
+        check(self.lib.nbvh_unscaled_grad(self.ctx, _ptr(out), 1 if clear else 0, _stream()))
+        return out
+
     def clear_flags(self):
         check(self.lib.nbvh_clear_flags(self.ctx, _stream()))
 
@@ -382,6 +418,26 @@ class NBVHBatch:
         for k, m in enumerate(self.models):
             m.train_step(probes[k], labels[k], losses[k])
         return losses
+
+
+def node_rank(leaf_loss: torch.Tensor, leaf_count: torch.Tensor, leaf_hits: torch.Tensor, n_rays: int) -> torch.Tensor:
+    """Per-leaf node error rank 2 log q + log p on the device (nbvh_node_rank)."""
+    lib = _abi.load()
+    n = leaf_loss.shape[0]
+    rank = torch.empty(n, dtype=torch.float32, device=leaf_loss.device)
+    check(lib.nbvh_node_rank(_ptr(leaf_loss.contiguous()), _ptr(leaf_count.contiguous()), _ptr(leaf_hits.contiguous()),
+                             n, int(n_rays), _ptr(rank), _stream()))
+    return rank
+
+
+def acceptance(rank: torch.Tensor, min_accept: float) -> torch.Tensor:
+    """Per-leaf training-ray acceptance max(exp(r - r_max), min_accept) on the
+    device (nbvh_acceptance)."""
+    lib = _abi.load()
+    rank = rank.contiguous().float()
+    out = torch.empty_like(rank)
+    check(lib.nbvh_acceptance(_ptr(rank), rank.shape[0], float(min_accept), _ptr(out), _stream()))
+    return out
 
 
 def hits_leaf(hits: torch.Tensor) -> torch.Tensor:

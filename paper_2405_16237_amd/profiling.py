@@ -129,7 +129,7 @@ def write_traffic(path: str, t: dict, copy_bytes: int, commands: list):
 
 def read_traffic(path: str) -> dict | None:
     """The summary written by write_traffic, or None if missing."""
-    if not os.path.exists(path):
+    if not os.path.isfile(path):
         return None
     out = {"kernels": {}}
     for line in open(path):

@@ -100,6 +100,32 @@ def test_leaf_loss_matches_oracle(lib, c1):
     assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max(), np.abs(got - ref).max() / np.abs(ref).max()
 
 
+@pytest.mark.parametrize("n_leaves", [1, 7, 1024, 16384 + 5])
+def test_node_rank_and_acceptance_match_oracle(lib, n_leaves):
+    """nbvh_node_rank / nbvh_acceptance (binary32) against the oracle's
+    binary64 rank and acceptance on per-leaf sums with empty leaves, leaves
+    without crossings and zero losses mixed in."""
+    from paper_2405_16237_amd.nbvh import acceptance, node_rank
+    rng = np.random.default_rng(n_leaves)
+    count = rng.integers(0, 400, n_leaves).astype(np.uint32)
+    loss = (rng.uniform(0.0, 3.0, n_leaves) * count).astype(np.float32)
+    loss[rng.uniform(size=n_leaves) < 0.05] = 0.0
+    hits = rng.integers(0, 5000, n_leaves).astype(np.uint32)
+    n_rays = 1 << 18
+    _say("node rank and acceptance:", n_leaves, "leaves")
+    r = node_rank(torch.from_numpy(loss).cuda(), torch.from_numpy(count).cuda(), torch.from_numpy(hits).cuda(), n_rays)
+    a = acceptance(r, 0.005).cpu().numpy().astype(np.float64)
+    r = r.cpu().numpy().astype(np.float64)
+    ro = oracle.node_rank(loss.astype(np.float64), count.astype(np.int64), hits.astype(np.int64), n_rays)
+    ao = oracle.acceptance(ro, 0.005)
+    fin = np.isfinite(ro)
+    assert np.array_equal(np.isfinite(r), fin)
+    assert np.all(r[~fin] == -np.inf)
+    if fin.any():
+        assert np.abs(r[fin] - ro[fin]).max() <= 2e-6 * max(1.0, np.abs(ro[fin]).max())
+    assert np.abs(a - ao).max() <= 2e-6, np.abs(a - ao).max()
+
+
 def test_construction_grows_cut_and_learns(lib, c1):
     """The cut grows from the root to the target through base-BVH nodes,
     every expansion splits the leaves of largest rank, and the constructed

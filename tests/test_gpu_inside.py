@@ -10,6 +10,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle
+from query_check import clear_rays, leaf_of
 from nbvh_synth import configs, scene
 
 pytestmark = pytest.mark.gpu
@@ -78,7 +79,11 @@ def test_first_hits_reverse_bit_exact(lib, c1):
     assert (rows[:, 3] < 0).sum() > 5000  # reversed chords start behind the origin
 
 
-def _compare(lib, c1, precision, params, band):
+def _compare(lib, c1, precision, params):
+    """Reverse-rule query against the oracle; a ray is clear when no hit
+    decision, no reversed hit's side of the origin and no distance tie can go
+    either way under the output tolerance (FP32 1e-5 of the segment's max |z|,
+    BF16 2e-2 max(1, |z|))."""
     sc, rays_np = c1
     net = configs.C1_NET
     m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision=precision, inside="reverse")
@@ -88,18 +93,12 @@ def _compare(lib, c1, precision, params, band):
     pref = params if precision == "fp32" else torch.from_numpy(params).to(torch.bfloat16).float().numpy()
     out, tr, z = oracle.query(oracle.make_cfg(net, sc.lo, sc.side), pref.astype(np.float64), rays_np, sc.boxes,
                               reverse=True)
-    off, sr, sl, t0, t1 = tr
-    # unambiguous rays: every logit clear of 0 and every reversed hit clear of the origin
-    tau = 1.0 / (1.0 + np.exp(-z[:, 1]))
-    a, b = t0.astype(np.float64), t1.astype(np.float64)
-    t_rev = b - tau * (b - a)
-    tmin = rays_np[sr, 3].astype(np.float64)
-    bad = np.abs(z[:, 0]) <= band * np.maximum(1.0, np.abs(z[:, 0]))
-    bad |= ((sl & TAG) != 0) & (np.abs(t_rev - tmin) <= 10 * band * np.maximum(1.0, np.abs(b - a)))
-    clear = np.ones(rays_np.shape[0], bool)
-    clear[np.unique(sr[bad])] = False
-    leaf = h[:, 7].view(np.uint32).astype(np.int64)
-    leaf[leaf == 0xFFFFFFFF] = -1
+    if precision == "fp32":
+        ztol = 1e-5 * np.repeat(np.abs(z).max(1, keepdims=True), net.n_out, 1)
+    else:
+        ztol = 2e-2 * np.maximum(1.0, np.abs(z))
+    clear = clear_rays(tr, z, out, rays_np[:, 3], ztol)
+    leaf = leaf_of(h)
     agree = leaf[clear] == out[clear, 4].astype(np.int64)
     return h, out, clear, agree
 
@@ -107,9 +106,9 @@ def _compare(lib, c1, precision, params, band):
 def test_query_reverse_fp32(lib, c1):
     net = configs.C1_NET
     params = configs.init_params(net, "uniform", 1.0, seed_features=93, seed_mlp=94)
-    h, out, clear, agree = _compare(lib, c1, "fp32", params, 1e-4)
-    assert clear.mean() > 0.9 and agree.mean() >= 0.999, (clear.mean(), agree.mean())
-    same = clear & (out[:, 4] >= 0) & (h[:, 7].view(np.uint32).astype(np.int64) == out[:, 4].astype(np.int64))
+    h, out, clear, agree = _compare(lib, c1, "fp32", params)
+    assert clear.mean() > 0.9 and agree.all(), (clear.mean(), agree.mean())
+    same = clear & (out[:, 4] >= 0) & (leaf_of(h) == out[:, 4].astype(np.int64))
     assert same.sum() > 2000
     dt = np.abs(h[same, 0] - out[same, 0]) / np.maximum(1.0, np.abs(out[same, 0]))
     assert dt.max() <= 1e-5, dt.max()
@@ -121,9 +120,9 @@ def test_query_reverse_bf16(lib, c1):
     net = configs.C1_NET
     params = configs.init_params(net, "uniform", 1.0, seed_features=95, seed_mlp=96)
     sc = c1[0]
-    h, out, clear, agree = _compare(lib, c1, "bf16", params, 2e-2)
-    assert agree.mean() >= 0.995, agree.mean()
-    same = clear & (out[:, 4] >= 0) & (h[:, 7].view(np.uint32).astype(np.int64) == out[:, 4].astype(np.int64))
+    h, out, clear, agree = _compare(lib, c1, "bf16", params)
+    assert clear.mean() > 0.5 and agree.all(), (clear.mean(), agree.mean())
+    same = clear & (out[:, 4] >= 0) & (leaf_of(h) == out[:, 4].astype(np.int64))
     assert np.abs(h[same, 0] - out[same, 0]).mean() <= 1e-3 * sc.diagonal
 
 

@@ -9,6 +9,7 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from nbvh_synth import configs, scene
+from query_check import clear_rays, leaf_of
 
 pytestmark = pytest.mark.gpu
 
@@ -223,26 +224,24 @@ def test_forward_bf16(lib, c1, name):
 
 # ------------------------------------------------------------------ query
 def _check_query(lib, net, sc, rays, precision, params):
+    """Query through nbvh_query against the oracle's query. A ray is clear
+    when no hit decision (|z0| within the tolerance on z) and no distance
+    tie between its winner and another hit segment can go either way under
+    the output tolerance: FP32 1e-5 of the segment's max |z|, BF16
+    2e-2 max(1, |z|)."""
     m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision=precision)
     m.set_params(params)
     _say("query", precision, rays.shape)
     hits = m.query(torch.from_numpy(rays).cuda()).cpu().numpy()
-    leaf = hits[:, 7].view(np.uint32).astype(np.int64)
-    leaf[leaf == 0xFFFFFFFF] = -1
+    leaf = leaf_of(hits)
     pref = params if precision == "fp32" else _bf16_round(params)
     out, tr, z = oracle.query(_ocfg(net, sc), pref.astype(np.float64), rays, sc.boxes)
-    off = tr[0]
-    # decisions are unambiguous where every segment's logit is clear of 0
-    band = 1e-4 if precision == "fp32" else 2e-2
-    clear = np.ones(rays.shape[0], bool)
-    if z.shape[0]:
-        bad = np.abs(z[:, 0]) <= band * np.maximum(1.0, np.abs(z[:, 0]))
-        seg_ray = tr[1]
-        clear[np.unique(seg_ray[bad])] = False
-        # near-ties between segments' t also make the winner ambiguous
-    oleaf = out[:, 4].astype(np.int64)
-    ok = clear
-    agree = (leaf[ok] == oleaf[ok])
+    if precision == "fp32":
+        ztol = 1e-5 * np.repeat(np.abs(z).max(1, keepdims=True), net.n_out, 1)
+    else:
+        ztol = 2e-2 * np.maximum(1.0, np.abs(z))
+    ok = clear_rays(tr, z, out, rays[:, 3], ztol)
+    agree = leaf[ok] == out[ok, 4].astype(np.int64)
     return m, hits, out, ok, agree, tr, z
 
 
@@ -252,11 +251,9 @@ def test_query_fp32_c1(lib, c1):
     params = _params(net, scale=1.0)
     m, hits, out, ok, agree, tr, z = _check_query(lib, net, sc, rays, "fp32", params)
     assert ok.mean() > 0.9
-    frac = agree.mean()
-    assert frac >= 0.999, frac
+    assert agree.all(), agree.mean()
     both = ok & (out[:, 4] >= 0)
-    both &= (hits[:, 7].view(np.uint32) != 0xFFFFFFFF)
-    same = both & (hits[:, 7].view(np.uint32).astype(np.int64) == out[:, 4].astype(np.int64))
+    same = both & (leaf_of(hits) == out[:, 4].astype(np.int64))
     assert same.sum() > 1000
     dt = np.abs(hits[same, 0] - out[same, 0]) / np.maximum(1.0, np.abs(out[same, 0]))
     assert dt.max() <= 1e-5, dt.max()
@@ -272,8 +269,9 @@ def test_query_bf16_c1(lib, c1):
     net = configs.C1_NET
     params = _params(net, scale=1.0)
     m, hits, out, ok, agree, tr, z = _check_query(lib, net, sc, rays, "bf16", params)
-    assert agree.mean() >= 0.995, agree.mean()
-    same = ok & (out[:, 4] >= 0) & (hits[:, 7].view(np.uint32).astype(np.int64) == out[:, 4].astype(np.int64))
+    assert ok.mean() > 0.5, ok.mean()
+    assert agree.all(), agree.mean()
+    same = ok & (out[:, 4] >= 0) & (leaf_of(hits) == out[:, 4].astype(np.int64))
     diag = sc.diagonal
     dt = np.abs(hits[same, 0] - out[same, 0])
     assert dt.mean() <= 1e-3 * diag, dt.mean()
@@ -364,30 +362,74 @@ def test_table_gradient_scatter_paths(lib, c1, path, order):
     assert np.abs(g - ref).max() <= 1e-5 * np.abs(ref).max(), np.abs(g - ref).max() / np.abs(ref).max()
 
 
+def _blocks(net):
+    """(name, slice) of each parameter block of the unpadded layout."""
+    out = [("table", slice(0, net.n_table_params))]
+    o = net.n_table_params
+    for k, (fi, fo) in enumerate(net.layer_dims()):
+        out.append(("W%d" % k, slice(o, o + fi * fo)))
+        o += fi * fo
+    return out
+
+
+def _check_bf16_grad(lib, net, sc, params, probes, seed, bound):
+    """BF16 back-propagation (BF16 activations, weights and gradients on the
+    matrix cores, FP32 accumulation) against the oracle's FP64 gradient of the
+    BF16-rounded parameters, element by element: |dg| <= bound * max|g| of
+    each block (table, W_0 .. W_H)."""
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", loss_scale=1024.0)
+    m.set_params(params)
+    n = probes.shape[0]
+    dz = (np.random.default_rng(seed).normal(size=(n, net.n_out)) / n).astype(np.float32)
+    m.backward(torch.from_numpy(probes).cuda(), torch.from_numpy(dz).cuda())
+    g = m.unpad(m.unscaled_grad())
+    ref = oracle.backward(_ocfg(net, sc), _bf16_round(params).astype(np.float64), probes, dz.astype(np.float64))
+    worst = {}
+    for name, sl in _blocks(net):
+        a, b = g[sl], ref[sl]
+        worst[name] = float(np.abs(a - b).max() / np.abs(b).max())
+    _say("bf16 gradient, worst |dg| / max|g| per block:", worst)
+    for name, w in worst.items():
+        assert w <= bound, (name, w)
+
+
 @pytest.mark.parametrize("name", ["c1", "c2", "f4", "c5"])
-def test_backward_bf16(lib, c1, name):
+def test_backward_bf16_active_units(lib, c1, name):
+    """Every hidden unit active on every probe (positive features and
+    weights), so no ReLU decision depends on rounding: the whole batch's
+    gradient is compared element by element."""
+    sc, _ = c1
+    net = NETS[name]
+    params = np.abs(_params(net, scale=1.0)).astype(np.float32)
+    params[: net.n_table_params] += np.float32(0.05)
+    n = 2048 + 5
+    probes = _probes(sc, n, 15)
+    assert oracle.min_abs_preact(_ocfg(net, sc), _bf16_round(params).astype(np.float64), probes).min() > 0.05
+    _say("backward bf16 (all units active)", name)
+    _check_bf16_grad(lib, net, sc, params, probes, 16, 2e-2)
+
+
+# margin above the largest change BF16 activations make to a hidden
+# pre-activation of these networks (about 3.6e-3 at their widths with U(-1, 1)
+# features), and the candidate pool that leaves enough probes clear of it
+KINK_CLEAR = {"c1": (6e-3, 40000, 1024), "f4": (6e-3, 4000, 1024), "c2": (4e-3, 409600, 160)}
+
+
+@pytest.mark.parametrize("name", sorted(KINK_CLEAR))
+def test_backward_bf16_kink_clear(lib, c1, name):
+    """Mixed-sign network: probes whose hidden pre-activations (oracle, BF16
+    parameters) all clear 0 by more than BF16 activations can move them, so
+    both sides take the same ReLU decisions; gradient element by element."""
     sc, _ = c1
     net = NETS[name]
     params = _params(net, scale=1.0)
-    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", loss_scale=1024.0)
-    m.set_params(params)
-    n = 2048 + 5
-    probes = _probes(sc, n, 15)
-    rng = np.random.default_rng(16)
-    dz = (rng.normal(size=(n, net.n_out)) / n).astype(np.float32)
-    _say("backward bf16", name)
-    m.backward(torch.from_numpy(probes).cuda(), torch.from_numpy(dz).cuda())
-    g = m.unpad(m.grad) / 1024.0
-    ref = oracle.backward(_ocfg(net, sc), _bf16_round(params).astype(np.float64), probes, dz.astype(np.float64))
-    nt = net.n_table_params
-    # BF16 activations move ReLU decisions and values by ~2^-9 relative; the
-    # gradient of that network differs from the FP64 one by a few percent in
-    # norm (a bf16-rounding emulation of the same data reproduces it)
-    for sl in (slice(nt, None), slice(0, nt)):
-        a, b = g[sl], ref[sl]
-        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
-        assert rel <= 0.1 and cos >= 0.99, (name, sl, rel, cos)
+    margin, pool, want = KINK_CLEAR[name]
+    cand = _probes(sc, pool, 21)
+    keep = oracle.min_abs_preact(_ocfg(net, sc), _bf16_round(params).astype(np.float64), cand) > margin
+    probes = cand[keep][:want]
+    assert probes.shape[0] >= min(want, 150), probes.shape[0]
+    _say("backward bf16 (kink-clear probes)", name, probes.shape[0])
+    _check_bf16_grad(lib, net, sc, params, probes, 22, 2e-2)
 
 
 def test_optimizer_same_gradient(lib, c1):

@@ -31,6 +31,11 @@ MUTATIONS = [
     ("nbvh_oracle.c", "t = b - tau * (b - a);", "t = a + tau * (b - a);"),           # reversed distance from the entry
     ("nbvh_oracle.c", "if (!(t > (double)ray_tmin[r])) continue;", ""),            # hits behind the origin kept
     ("__init__.py", "out[inside, 4:7] = -out[inside, 4:7]", "out[inside, 4:7] = out[inside, 4:7]"),  # direction not reversed
+    ("nbvh_oracle.c", "double d = 2.0 * (ah - a) / den;",
+     "double d = (2.0 * (ah - a) * den - (ah - a) * (ah - a) * 2.0 * ah) / (den * den);"),  # albedo denominator differentiated
+    ("nbvh_oracle.c", "r[i] = 2.0 * log(q) + log(p);", "r[i] = log(q) + log(p);"),  # rank: q not squared
+    ("nbvh_oracle.c", "exp(r[i] - rmax)", "exp(rmax - r[i])"),                     # acceptance order inverted
+    ("nbvh_oracle.c", "for (int j = 0; j < H * width; ++j) m =", "for (int j = width; j < H * width; ++j) m ="),  # kink scan skips layer 0
 ]
 
 

@@ -272,6 +272,34 @@ def test_mlp_identity_weights():
     assert np.array_equal(z, np.maximum(u, 0.0)[:, :5])
 
 
+def test_min_abs_preact_matches_library_matmul():
+    """The smallest |pre-activation| over every hidden unit of a segment,
+    from numpy float64 products of the encoded features, over all hidden
+    layers (and never the output layer)."""
+    net = Net(2, 2, 8, 2, [3, 5], mlp_width=16, mlp_hidden=3, n_out=5)
+    cfg = _cfg(net, (-1, -1, -1), 2.0)
+    rng = np.random.default_rng(35)
+    table = rng.normal(size=oracle.n_table_params(cfg))
+    W = rng.normal(size=oracle.n_mlp_params(cfg)) * 0.4
+    segs = _random_segments(rng, 300)
+    got = oracle.min_abs_preact(cfg, np.concatenate([table, W]), segs)
+    h = oracle.encode(cfg, table, segs).T
+    mats = _split_weights(net, W)
+    per_layer = []
+    for M in mats[:-1]:
+        a = M @ h
+        per_layer.append(np.abs(a).min(0))
+        h = np.maximum(a, 0.0)
+    ref = np.min(per_layer, axis=0)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-15)
+    # every hidden layer can hold the minimum on some segment; the output
+    # layer never does (its pre-activations are not ReLU inputs)
+    which = np.argmin(per_layer, axis=0)
+    assert set(which.tolist()) == {0, 1, 2}
+    z = (mats[-1] @ h).T
+    assert np.any(np.abs(z).min(1) < got)
+
+
 def test_layer_amax_identity_network():
     """With W_0 = +-I and W_1 = I the hidden layers carry ReLU(+-u), so the
     per-layer maxima are max|u|, then the largest positive (or negated
@@ -406,20 +434,32 @@ def test_albedo_loss_closed_forms():
 
 
 def test_albedo_loss_gradient_finite_difference():
+    """The relative L2 term's denominator is held constant in the derivative.
+    The label enters only the numerator, so central differences of the
+    loss in the label direction give -d/d(a_hat) with the denominator
+    constant; times the logistic slope sigma'(z) = e^-z / (1 + e^-z)^2 that
+    must be the gradient in z. (Differentiating the denominator too would
+    differ by (a_hat - a)^2 2 a_hat / (a_hat^2 + 0.01)^2.)"""
     net = Net(1, 2, 8, 1, [3], n_out=8)
     cfg = _cfg(net)
     rng = np.random.default_rng(37)
     lab = _albedo_labels(rng, 30)
+    lab[:, 4] = 1.0  # every segment hit: the albedo term is on
     z = rng.normal(size=(30, 8))
     _, dz = oracle.loss(cfg, z, lab)
     h = 1e-6
-    for i in range(0, 30, 7):
+    checked = 0
+    for i in range(30):
         for o in (5, 6, 7):
-            zp, zm = z.copy(), z.copy()
-            zp[i, o] += h
-            zm[i, o] -= h
-            fd = (oracle.loss(cfg, zp, lab, with_grad=False)[0][0] - oracle.loss(cfg, zm, lab, with_grad=False)[0][0]) / (2 * h)
-            assert abs(fd - dz[i, o]) <= 1e-7 * max(1.0, abs(dz[i, o])) + 1e-9, (i, o, fd, dz[i, o])
+            lp, lm = lab.copy(), lab.copy()
+            lp[i, o] += np.float32(h)
+            lm[i, o] -= np.float32(h)
+            step = float(lp[i, o]) - float(lm[i, o])
+            fd_a = (oracle.loss(cfg, z, lp, with_grad=False)[0][0] - oracle.loss(cfg, z, lm, with_grad=False)[0][0]) / step
+            slope = np.exp(-z[i, o]) / (1.0 + np.exp(-z[i, o])) ** 2
+            assert abs(-fd_a * slope - dz[i, o]) <= 1e-6 * abs(dz[i, o]) + 1e-10, (i, o, -fd_a * slope, dz[i, o])
+            checked += 1
+    assert checked == 90 and np.abs(dz[:, 5:8]).max() > 1e-3
 
 
 def test_loss_gradient_finite_difference():
@@ -713,3 +753,43 @@ def test_reverse_rule_with_exact_outputs_matches_ground_truth():
     got_hit = out[:, 4] >= 0
     assert np.array_equal(got_hit, gt["hit"]) and 0.2 < gt["hit"].mean() < 0.8
     assert np.abs(out[got_hit, 0] - gt["t"][got_hit]).max() < 1e-6
+
+
+# ------------------------------------------------------------------ construction: rank and acceptance
+def test_node_rank_closed_form():
+    """Sec. 5.1: r = 2 log q + log p, q = loss / count, p = hits / rays; a leaf
+    without segments, crossings or loss ranks -inf."""
+    loss = np.array([2.0, 0.0, 1.0, math.e ** -1.5, 3.0, 5.0])
+    count = np.array([4, 0, 2, 1, 3, 1])
+    hits = np.array([10, 5, 0, 25, 100, 1])
+    r = oracle.node_rank(loss, count, hits, 100)
+    assert abs(r[0] - (2 * math.log(0.5) + math.log(0.1))) < 1e-14
+    assert r[1] == -math.inf and r[2] == -math.inf
+    assert abs(r[3] - (-3.0 + math.log(0.25))) < 1e-14
+    assert abs(r[4]) < 1e-14  # q = 1, p = 1
+    assert abs(r[5] - (2 * math.log(5.0) + math.log(0.01))) < 1e-13
+    assert oracle.node_rank(np.array([0.0]), np.array([3]), np.array([3]), 10)[0] == -math.inf
+
+
+def test_acceptance_closed_form():
+    """Sec. 5.2, read in linear space: max(exp(r - r_max), floor); the worst
+    leaf is always trained, -inf takes the floor, no finite rank trains all."""
+    r = np.array([-1.0, -3.0, -math.inf, -20.0, -1.0 - math.log(4.0)])
+    a = oracle.acceptance(r, 0.005)
+    assert a[0] == 1.0 and abs(a[1] - math.exp(-2.0)) < 1e-15
+    assert a[2] == 0.005 and a[3] == 0.005 and abs(a[4] - 0.25) < 1e-15
+    assert np.all(oracle.acceptance(np.full(3, -math.inf), 0.005) == 1.0)
+    # the same leaf order as the ranks (monotone), invariant under a common shift
+    rr = np.random.default_rng(3).normal(size=50) * 3
+    aa = oracle.acceptance(rr, 0.0)
+    assert np.all(np.argsort(rr, kind="stable") == np.argsort(aa, kind="stable"))
+    assert np.allclose(oracle.acceptance(rr + 7.5, 0.0), aa, rtol=1e-14)
+    # rank of q^2 p: scaling every q by c leaves the acceptance unchanged
+    loss = np.random.default_rng(4).uniform(0.1, 2.0, 20)
+    cnt = np.random.default_rng(5).integers(1, 50, 20)
+    hit = np.random.default_rng(6).integers(1, 90, 20)
+    a1 = oracle.acceptance(oracle.node_rank(loss, cnt, hit, 100), 0.0)
+    a2 = oracle.acceptance(oracle.node_rank(3.0 * loss, cnt, hit, 100), 0.0)
+    assert np.allclose(a1, a2, rtol=1e-13)
+    q2p = (loss / cnt) ** 2 * hit
+    assert np.allclose(a1, q2p / q2p.max(), rtol=1e-13)
