@@ -307,6 +307,24 @@ nbvh_status nbvh_traverse(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_ra
 nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_rays, nbvh_hit* hits_dev,
                        uint64_t seg_capacity, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* nbvh_query for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, with the query's workspace taken from a
+ * library-owned static device buffer of 64 MiB instead of a caller workspace.
+ * Each GPU the library runs on holds its own copy until the process ends.
+ * The workspace of a query is 12 bytes per ray for offsets, counts and the
+ * active list, 144 bytes per ray of traversal staging, 16 bytes per segment
+ * of capacity, plus a few hundred bytes of counters and scan partials,
+ * each part rounded up to 256 bytes; a query needing more than 64 MiB returns
+ * NBVH_ERR_CAPACITY before enqueuing anything (about 230,000 rays at 8
+ * segments of capacity per ray fit). The call allocates nothing. Every call
+ * on one GPU shares that GPU's buffer, whatever the context: calls that may
+ * overlap on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller. Each call clears the counters it uses; the
+ * buffer otherwise keeps the last call's contents. */
+nbvh_status nbvh_query_noalloc(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_rays, nbvh_hit* hits_dev,
+                               uint64_t seg_capacity, void* stream);
+
 /* Optional outputs of nbvh_query_traced (each pointer nullable, device):
  * seg_offsets_dev [n_rays + 1] and segs_dev [seg_capacity] receive the
  * segment queue the traversal built (as nbvh_traverse writes them; the

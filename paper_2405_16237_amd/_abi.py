@@ -75,7 +75,7 @@ EXPORTS = [
     "nbvh_param_count", "nbvh_param_layout", "nbvh_aux_bytes", "nbvh_nodes_bytes", "nbvh_state_bytes", "nbvh_build",
     "nbvh_bind_params", "nbvh_reset_optimizer", "nbvh_sync_shadow", "nbvh_calibrate_fp8", "nbvh_workspace_bytes",
     "nbvh_traverse",
-    "nbvh_query", "nbvh_query_traced", "nbvh_query_segments", "nbvh_first_hits", "nbvh_group_ws_bytes", "nbvh_group_by_leaf", "nbvh_leaf_loss", "nbvh_node_rank", "nbvh_acceptance", "nbvh_encode", "nbvh_forward", "nbvh_backward", "nbvh_optimizer_step",
+    "nbvh_query", "nbvh_query_noalloc", "nbvh_query_traced", "nbvh_query_segments", "nbvh_first_hits", "nbvh_group_ws_bytes", "nbvh_group_by_leaf", "nbvh_leaf_loss", "nbvh_node_rank", "nbvh_acceptance", "nbvh_encode", "nbvh_forward", "nbvh_backward", "nbvh_optimizer_step",
     "nbvh_train_step", "nbvh_loss", "nbvh_batch_desc_bytes", "nbvh_batch_create", "nbvh_batch_workspace_bytes",
     "nbvh_batch_query", "nbvh_batch_destroy", "nbvh_get_tuning", "nbvh_set_tuning", "nbvh_profile_begin", "nbvh_profile_end", "nbvh_read_state", "nbvh_device_status", "nbvh_param_bytes", "nbvh_unscaled_grad", "nbvh_clear_flags", "nbvh_last_error", "nbvh_version",
     "nbvh_destroy",
@@ -115,6 +115,7 @@ def load(path: str = LIB_PATH):
         "nbvh_traverse": (st, [P, P, U64, P, P, U64, P, SZ, P]),
         "nbvh_query": (st, [P, P, U64, P, U64, P, SZ, P]),
         "nbvh_query_traced": (st, [P, P, U64, P, U64, P, SZ, P, P]),
+        "nbvh_query_noalloc": (st, [P, P, U64, P, U64, P]),
         "nbvh_query_segments": (st, [P, P, U64, P, P, P, P, SZ, P]),
         "nbvh_encode": (st, [P, P, U64, P, P]),
         "nbvh_first_hits": (st, [P, P, U64, P, P, P, P, P, P, P]),

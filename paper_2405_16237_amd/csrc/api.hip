@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -267,6 +268,37 @@ static QueryLayout query_layout(uint64_t n_rays, uint64_t cap) {
   return Q;
 }
 
+// Device memory of nbvh_query_noalloc: one query's workspace (segment
+// offsets and counts, active-ray list, scan partials, counters, traversal
+// staging, segment queue), at most kNoAllocBytes. A file-scope array, so each
+// GPU the library runs on holds its own copy until the process ends; its
+// address on a device comes from hipGetSymbolAddress with that device
+// current, and host code uses only that address.
+constexpr size_t kNoAllocBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// The current device's address of `scratch`, looked up once per device.
+static nbvh_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return set_error("no usable current device for the no-allocation query"), NBVH_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e)),
+             NBVH_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NBVH_OK;
+}
+
 }  // namespace nbvh
 
 using namespace nbvh;
@@ -365,6 +397,12 @@ nbvh_status nbvh_build(const nbvh_config* cfg, const float* leaf_boxes_host, uin
   ctx->n_cu = (hipGetDeviceProperties(&prop, dev) == hipSuccess) ? prop.multiProcessorCount : 256;
   if (ctx->n_cu <= 0) ctx->n_cu = 256;
   ctx->tune = nbvh_tuning{8, 0, 0, 8, 64, 0, 1, 8, 0, 0};
+  void* sp = nullptr;
+  s = scratch_for_current_device(&sp);  // set-up of the no-allocation query on this device
+  if (s != NBVH_OK) {
+    delete ctx;
+    return s;
+  }
   *out = ctx;
   return NBVH_OK;
 }
@@ -464,6 +502,24 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbv
   if (s != NBVH_OK) return s;
   return launch_query_eval(L, rays, offsets, segs, (const uint32_t*)(w + Q.active), misc + 0, misc + 1, hits,
                            (uint32_t)n_rays, seg_capacity);
+}
+
+nbvh_status nbvh_query_noalloc(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbvh_hit* hits,
+                               uint64_t seg_capacity, void* stream) {
+  nbvh_status s = require_bound(ctx);
+  if (s != NBVH_OK) return s;
+  if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
+  if (seg_capacity > 0xffffffffull) seg_capacity = 0xffffffffull;
+  const size_t need = query_layout(n_rays, seg_capacity).total;
+  if (need > kNoAllocBytes)
+    return set_error("query of %llu rays with %llu segments needs %zu bytes of scratch; the no-allocation query "
+                     "holds %zu",
+                     (unsigned long long)n_rays, (unsigned long long)seg_capacity, need, kNoAllocBytes),
+           NBVH_ERR_CAPACITY;
+  void* ws = nullptr;
+  s = scratch_for_current_device(&ws);
+  if (s != NBVH_OK) return s;
+  return nbvh_query(ctx, rays, n_rays, hits, seg_capacity, ws, kNoAllocBytes, stream);
 }
 
 nbvh_status nbvh_query_traced(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbvh_hit* hits,
