@@ -78,6 +78,7 @@ def hit_error(hits, gt, diag):
 
 class Workload:
     """Inputs of one benchmark workload (all host arrays, seeded)."""
+    inside_probes = None  # "surface": inside-starting training probes start on the surface
 
 
 def parity(torch, m, rays_np, sc, net, params, precision, inside, what):
@@ -142,24 +143,26 @@ def build_frame(configs, scene, samples=8):
     return W
 
 
-def build_secondary(configs, scene, inside="reverse", offset=1e-4):
+def build_secondary(configs, scene, inside="reverse", offset=1e-4, bounce_from="network", inside_probes="surface"):
     W = Workload()
     W.name = "secondary"
     W.sc = configs.make_scene(3_996_180, 16384, albedo_seed=scene.SEED_ALBEDO)
-    primary = scene.pinhole_rays(1920, 1080)
-    g = scene.ray_ground_truth(W.sc.mesh, primary)
-    hit = g["hit"]
-    pts = primary[hit, 0:3].astype(np.float64) + g["t"][hit, None] * primary[hit, 4:7].astype(np.float64)
-    W.rays = scene.cosine_bounces(pts, g["n"][hit], 1 << 24, seed=scene.SEED_SECONDARY,
-                                  offset=offset * W.sc.diagonal)
-    # ground truth on every 16th ray
-    W.gt_idx = np.arange(0, W.rays.shape[0], 16)
-    W.gt = scene.ray_ground_truth(W.sc.mesh, W.rays[W.gt_idx])
+    W.offset = offset * W.sc.diagonal
+    W.primary = scene.pinhole_rays(1920, 1080)
+    W.bounce_from = bounce_from
+    if bounce_from == "mesh":
+        g = scene.ray_ground_truth(W.sc.mesh, W.primary)
+        hit = g["hit"]
+        pts = W.primary[hit, 0:3].astype(np.float64) + g["t"][hit, None] * W.primary[hit, 4:7].astype(np.float64)
+        set_bounces(W, scene, pts, g["n"][hit])
+    else:
+        W.rays = None  # spawned from the trained network's own primary hits (spawn_from_network)
     W.net = configs.C5_NET
     W.params0 = configs.init_params(W.net, "normal", 1e-2)
     W.per_leaf = 16
     W.inside = inside
     W.seg_cap_per_ray = 8
+    W.inside_probes = None
     if inside == "reverse":
         # the leaf around each bounce origin is queried backwards along its
         # chord, so training needs only whole chords, as for camera rays
@@ -167,15 +170,61 @@ def build_secondary(configs, scene, inside="reverse", offset=1e-4):
         how = "leaves around the origin queried along the reversed chord; train batch 2^18 whole-chord probes"
     else:
         W.inside_fraction = 0.5  # half the probes start inside their leaf, as the bounce rays do
-        how = ("leaves around the origin queried from the origin on; train batch 2^18 probes, half of them "
-               "starting inside their leaf")
-    W.describe = ("2^24 cosine-weighted bounce rays from the 1920x1080 frame's primary hits on a 3,996,180-triangle "
-                  "displaced icosphere with per-vertex albedo, 16,384 neural leaves; hash grid L=16 F=4 T=2^22, "
-                  "4 samples/segment, MLP 256-4x256-8 (hit, t, normal, albedo); origins offset by %g of the scene "
-                  "diagonal along the normal; " % offset + how)
+        if inside_probes == "surface":
+            W.inside_probes = "surface"
+            how = ("leaves around the origin queried from the origin on; train batch 2^18 probes, half of them "
+                   "starting on the surface inside their leaf (offset along the normal, cosine-weighted directions)")
+        else:
+            how = ("leaves around the origin queried from the origin on; train batch 2^18 probes, half of them "
+                   "starting uniformly inside their leaf")
+    W.describe = ("2^24 cosine-weighted bounce rays from the 1920x1080 frame's primary hits (%s) on a "
+                  "3,996,180-triangle displaced icosphere with per-vertex albedo, 16,384 neural leaves; hash grid "
+                  "L=16 F=4 T=2^22, 4 samples/segment, MLP 256-4x256-8 (hit, t, normal, albedo); origins offset by "
+                  "%g of the scene diagonal along the normal; "
+                  % ("as the trained network predicts them" if bounce_from == "network" else "on the mesh", offset)
+                  + how)
     W.parity_stride = 4  # every 256th bounce ray
     W.cpu_sample = lambda stride: (W.rays[::stride * stride * 16].copy(), "every %dth ray" % (stride * stride * 16))
     return W
+
+
+def set_bounces(W, scene, points, normals):
+    """2^24 cosine-weighted bounce rays about the given hit points and unit
+    normals, and the triangle ground truth of every 16th."""
+    W.rays = scene.cosine_bounces(points, normals, 1 << 24, seed=scene.SEED_SECONDARY, offset=W.offset)
+    W.gt_idx = np.arange(0, W.rays.shape[0], 16)
+    W.gt = scene.ray_ground_truth(W.sc.mesh, W.rays[W.gt_idx])
+
+
+def spawn_from_network(W, scene, torch, model):
+    """Bounce rays from the model's own primary hits, as a renderer spawns
+    them: hit point o + t d, the predicted normal normalised and turned to
+    face the incoming ray."""
+    hits = model.query(torch.from_numpy(W.primary).cuda()).cpu().numpy()
+    leaf = hits[:, 7].view(np.uint32)
+    hit = leaf != 0xFFFFFFFF
+    pr = W.primary[hit].astype(np.float64)
+    pts = pr[:, 0:3] + hits[hit, 0:1].astype(np.float64) * pr[:, 4:7]
+    n = hits[hit, 1:4].astype(np.float64)
+    n /= np.maximum(np.linalg.norm(n, axis=1, keepdims=True), 1e-30)
+    n = np.where((n * pr[:, 4:7]).sum(1, keepdims=True) > 0, -n, n)
+    set_bounces(W, scene, pts, n)
+    return int(hit.sum())
+
+
+def training_probes(W, scene, seed):
+    """One training batch of the workload: whole-chord probes per leaf, and
+    for the clip rule on the bounce workload half of each leaf's probes
+    starting on the surface inside the leaf."""
+    sc = W.sc
+    if W.inside_probes != "surface":
+        pr, _ = scene.leaf_probes(sc.boxes, W.per_leaf, seed=seed, inside_fraction=W.inside_fraction)
+        return pr
+    k = int(round(W.inside_fraction * W.per_leaf))
+    outer, _ = scene.leaf_probes(sc.boxes, W.per_leaf - k, seed=seed)
+    surf = scene.surface_probes(sc.verts, sc.tris, sc.tri_leaf, sc.boxes, k, W.offset, seed=seed + 2000)
+    nl = sc.boxes.shape[0]
+    return np.concatenate([outer.reshape(nl, -1, 8), surf.reshape(nl, k, 8)], axis=1).reshape(-1, 8)
 
 
 def timer(torch):
@@ -208,12 +257,11 @@ def run_single(args, W, P, torch, configs, scene):
     sc, net = W.sc, W.net
     batches = []
     for i in range(args.batches):
-        pr, _ = scene.leaf_probes(sc.boxes, W.per_leaf, seed=scene.SEED_PROBES + i, inside_fraction=W.inside_fraction)
+        pr = training_probes(W, scene, scene.SEED_PROBES + i)
         lb = scene.probe_labels(sc.mesh, pr)
         batches.append((torch.from_numpy(pr).cuda(), torch.from_numpy(lb).cuda()))
     B = batches[0][0].shape[0]
-    rays = torch.from_numpy(W.rays).cuda()
-    R = rays.shape[0]
+    R = W.rays.shape[0] if W.rays is not None else 1 << 24
     seg_cap = W.seg_cap_per_ray * R
     log("data ready in %.1fs: %d rays, %d triangles, %d leaves, batch %d" %
         (time.time() - t0, R, sc.tris.shape[0], sc.boxes.shape[0], B))
@@ -250,6 +298,12 @@ def run_single(args, W, P, torch, configs, scene):
     torch.cuda.synchronize()
     log("pretrain %d steps in %.1fs, loss %s" % (args.pretrain, time.time() - t1,
                                                  None if loss is None else loss.cpu().numpy().round(4).tolist()))
+    if W.rays is None:
+        t2 = time.time()
+        n_hit = spawn_from_network(W, scene, torch, bf)
+        log("bounce rays spawned from %d network primary hits in %.1fs (true hit rate %.5f)" %
+            (n_hit, time.time() - t2, float(W.gt["hit"].mean())))
+    rays = torch.from_numpy(W.rays).cuda()
     hits_bf = torch.empty((R, 8), dtype=torch.float32, device="cuda")
 
     def run_steps(m, n):
@@ -405,6 +459,7 @@ def run_single(args, W, P, torch, configs, scene):
         "segments_per_s": evaluated / (q_ms * 1e-3),
         "train_segs_per_s": B / (t_ms * 1e-3),
         "accuracy": acc_bf,
+        **({"always_miss_accuracy": float(1.0 - W.gt["hit"].mean())} if W.name == "secondary" else {}),
         "fp32": fp32,
         "fp8": fp8,
         "roofline": roofline,
@@ -568,19 +623,22 @@ def run_batched(args, P, torch, configs, scene):
         for m, (p, l) in zip(models, batches):
             m.train_step(p, l)
     torch.cuda.synchronize()
-    # the training step of all objects as one HIP graph
+    # the training step of all objects as one HIP graph: each object's step
+    # is a branch of its own (its own stream during capture), so the
+    # objects' kernels overlap
     losses = torch.zeros((len(models), 4), dtype=torch.float32, device="cuda")
+    obj_streams = [torch.cuda.Stream() for _ in models]
+    probes_k = [p for p, _ in batches]
+    labels_k = [l for _, l in batches]
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        for k, m in enumerate(models):
-            m.train_step(*batches[k], loss=losses[k])
+        batch.train_step(probes_k, labels_k, losses, streams=None if args.serial_graph else obj_streams)
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        for k, m in enumerate(models):
-            m.train_step(*batches[k], loss=losses[k])
+        batch.train_step(probes_k, labels_k, losses, streams=None if args.serial_graph else obj_streams)
     time_loop = timer(torch)
     for _ in range(args.warmup):
         batch.query(rays, seg_cap, hits)
@@ -676,7 +734,8 @@ def run_batched(args, P, torch, configs, scene):
             "workload": "8 displaced icospheres (50,000..1,997,120 triangles, 256..8,192 leaves, own tables "
                         "T=2^16..2^20, L=16 F=2, 8 samples, MLP 256-4x128-5) queried together by 2^22 rays "
                         "crossing 1..32 leaves (log-uniform); training step of 2^18 probes per object as one "
-                        "HIP graph",
+                        "HIP graph (%s)" % ("objects one after another" if args.serial_graph else
+                                            "one parallel branch per object"),
             "rays": R, "objects": len(objs), "train_batch": nb,
             "step": "one grouped query + one graph-captured training step of every object",
         },
@@ -713,11 +772,20 @@ def main():
                     help="secondary workload: how a leaf around a bounce origin is queried")
     ap.add_argument("--bounce-offset", type=float, default=1e-4,
                     help="secondary workload: origin offset along the normal, in scene diagonals")
+    ap.add_argument("--bounce-from", choices=("network", "mesh"), default="network",
+                    help="secondary workload: spawn the bounces from the trained network's own primary hits (as a "
+                         "renderer would) or from the mesh's exact primary hits")
+    ap.add_argument("--inside-probes", choices=("surface", "uniform"), default="surface",
+                    help="secondary workload with --inside clip: the inside-starting training probes start on the "
+                         "surface inside their leaf (as bounce rays do) or uniformly inside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true")
     ap.add_argument("--no-parity", action="store_true", help="skip the comparison with the FP64 oracle")
     ap.add_argument("--no-peaks", action="store_true", help="skip the ceiling micro-benchmarks")
+    ap.add_argument("--serial-graph", action="store_true",
+                    help="batched workload: capture the objects' training steps one after another instead of as "
+                         "parallel graph branches")
     ap.add_argument("--copy-kernel-mib", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB five times: the reference "
                          "dispatch that scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
@@ -741,7 +809,9 @@ def main():
         out = run_batched(args, P, torch, configs, scene)
     else:
         W = build_frame(configs, scene, args.samples) if args.workload == "frame" else build_secondary(configs, scene, args.inside,
-                                                                                           args.bounce_offset)
+                                                                                           args.bounce_offset,
+                                                                                           args.bounce_from,
+                                                                                           args.inside_probes)
         if args.per_leaf > 0:
             W.per_leaf = args.per_leaf
             W.describe = W.describe.replace("train batch 2^18 probes", "train batch %d probes" % (args.per_leaf * W.sc.boxes.shape[0]))

@@ -391,6 +391,48 @@ def leaf_probes(boxes: np.ndarray, per_leaf: int, seed: int = SEED_PROBES, radiu
     return out.reshape(-1, 8), leaf_ids
 
 
+def surface_probes(verts: np.ndarray, tris: np.ndarray, tri_leaf: np.ndarray, boxes: np.ndarray, per_leaf: int,
+                   offset: float, seed: int = SEED_PROBES + 2000):
+    """Probe segments that start on the surface inside their leaf, as bounce
+    rays do: per leaf, points uniform on the leaf's triangles (area-weighted),
+    origin moved `offset` along the triangle's winding-order normal,
+    direction cosine-weighted about that normal, segment [0, exit of the
+    leaf box]. Origins that the offset moves out of the box are drawn again.
+    Returns [n_leaves * per_leaf][8] float32 probes, leaf-major."""
+    rng = np.random.default_rng(seed)
+    nl = boxes.shape[0]
+    lo = boxes[:, :3].astype(np.float64)
+    hi = boxes[:, 3:].astype(np.float64)
+    v = verts.astype(np.float64)
+    a, b, c = v[tris[:, 0]], v[tris[:, 1]], v[tris[:, 2]]
+    cr = np.cross(b - a, c - a)
+    area = 0.5 * np.linalg.norm(cr, axis=1)
+    nrm = cr / np.maximum(2.0 * area[:, None], 1e-300)
+    order = np.argsort(tri_leaf, kind="stable")
+    bounds = np.searchsorted(tri_leaf[order], np.arange(nl + 1))
+    out = np.zeros((nl, per_leaf, 8), dtype=np.float32)
+    for leaf in range(nl):
+        ts = order[bounds[leaf]:bounds[leaf + 1]]
+        cdf = np.cumsum(area[ts])
+        got = 0
+        while got < per_leaf:
+            m = 2 * (per_leaf - got)
+            t = ts[np.minimum(np.searchsorted(cdf, rng.uniform(0.0, cdf[-1], m)), ts.size - 1)]
+            r1, r2 = np.sqrt(rng.uniform(size=m)), rng.uniform(size=m)
+            p = (1 - r1)[:, None] * a[t] + (r1 * (1 - r2))[:, None] * b[t] + (r1 * r2)[:, None] * c[t]
+            o = p + offset * nrm[t]
+            d = cosine_bounces(np.zeros((m, 3)), nrm[t], m, seed=int(rng.integers(1 << 31)))[:, 4:7].astype(np.float64)
+            inside = np.all((o >= lo[leaf]) & (o <= hi[leaf]), axis=1)
+            _, tf = _clip_box64(o, d, np.broadcast_to(lo[leaf], o.shape), np.broadcast_to(hi[leaf], o.shape))
+            ok = np.nonzero(inside & (tf > 0.0))[0][: per_leaf - got]
+            rows = out[leaf, got:got + ok.size]
+            rows[:, 0:3] = o[ok]
+            rows[:, 4:7] = d[ok]
+            rows[:, 7] = tf[ok]
+            got += ok.size
+    return out.reshape(-1, 8)
+
+
 # --------------------------------------------------------------------------
 # ground truth
 # --------------------------------------------------------------------------

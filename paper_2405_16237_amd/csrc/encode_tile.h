@@ -57,9 +57,15 @@ template <int F, bool LP>
 __device__ inline typename RawEntry<F, LP>::T load_raw(const void* table, uint32_t param_index) {
   typedef typename RawEntry<F, LP>::T T;
   // 32-bit byte offset from a uniform base: one VGPR per address (tables
-  // are far below 4 GiB)
+  // are far below 4 GiB); the pointer is a global one, so the load is a
+  // global (not a flat) load whichever other loads sit beside it
   const uint32_t byte_off = param_index * (LP ? 2u : 4u);
-  return *(const T*)((const char*)table + byte_off);
+  typedef uint32_t W __attribute__((ext_vector_type(sizeof(T) / 4)));
+  const W w = *(const W __attribute__((address_space(1)))*)((const char __attribute__((address_space(1)))*)table +
+                                                             byte_off);
+  T r;
+  __builtin_memcpy(&r, &w, sizeof(T));
+  return r;
 }
 
 template <int F, bool LP>
@@ -92,7 +98,12 @@ __device__ inline void unpack_raw(const typename RawEntry<F, LP>::T& r, float v[
 template <int F, bool LP>
 __device__ inline typename RawEntry<F, LP>::T load_raw_lds(const unsigned char* ltab, uint32_t param_index) {
   typedef typename RawEntry<F, LP>::T T;
-  return *(const T*)(ltab + param_index * (LP ? 2u : 4u));
+  typedef uint32_t W __attribute__((ext_vector_type(sizeof(T) / 4)));
+  const W w = *(const W __attribute__((address_space(3)))*)((const unsigned char __attribute__((address_space(3)))*)ltab +
+                                                             param_index * (LP ? 2u : 4u));
+  T r;
+  __builtin_memcpy(&r, &w, sizeof(T));
+  return r;
 }
 
 // Two adjacent table entries (an x-neighbour pair) as loaded.
@@ -145,7 +156,7 @@ __device__ inline void encode_tile(const DevCfg& c, const void* table, const flo
   typedef typename RawEntry<F, LP>::T Raw;
   constexpr bool kPairs = PAIRS && !(F == 4 && !LP);  // a 32-byte fp32 pair has no single load
   constexpr int U = UNROLL > 0 ? UNROLL : 2;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int L = c.n_levels, S = c.n_samples;
   const uint32_t hmask = (1u << c.log2_T) - 1u;
   for (int m = lane; m < M; m += 64) {
@@ -204,19 +215,33 @@ __device__ inline void encode_tile(const DevCfg& c, const void* table, const flo
                   raw[u][2 * j + 1] = even ? pair_half<F, LP>(p, (h1 & 1u) != 0u) : load_raw<F, LP>(table, base + h1 * F);
                 }
               }
-            } else if (l < lds_levels) {  // wave-uniform
-#pragma unroll
-              for (int k = 0; k < 8; ++k) {
-                const uint32_t idx = base + corner_index(dense, N, hmask, cx + (k & 1), cy + ((k >> 1) & 1),
-                                                         cz + ((k >> 2) & 1)) * F;
-                raw[u][k] = load_raw_lds<F, LP>(ltab, idx);
-              }
             } else {
+              // the 8 corner entries first (the dense/hashed choice is
+              // uniform over the wave, so one branch per level), then the 8
+              // loads back to back: dense levels index x + (N+1)(y + (N+1) z),
+              // hashed ones XOR the per-axis products, the upper y and z
+              // products being the lower ones plus the prime
+              uint32_t idx[8];
+              if (dense) {
+                const uint32_t r1 = (uint32_t)N + 1u, r2 = r1 * r1;
+                const uint32_t i0 = (uint32_t)cx + r1 * ((uint32_t)cy + r1 * (uint32_t)cz);
 #pragma unroll
-              for (int k = 0; k < 8; ++k) {
-                const uint32_t idx = base + corner_index(dense, N, hmask, cx + (k & 1), cy + ((k >> 1) & 1),
-                                                         cz + ((k >> 2) & 1)) * F;
-                raw[u][k] = load_raw<F, LP>(table, idx);
+                for (int k = 0; k < 8; ++k)
+                  idx[k] = base + (i0 + (uint32_t)(k & 1) + ((k & 2) ? r1 : 0u) + ((k & 4) ? r2 : 0u)) * F;
+              } else {
+                const uint32_t hy0 = (uint32_t)cy * 2654435761u, hz0 = (uint32_t)cz * 805459861u;
+                const uint32_t hy1 = hy0 + 2654435761u, hz1 = hz0 + 805459861u;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                  idx[k] = base + ((((uint32_t)cx + (uint32_t)(k & 1)) ^ ((k & 2) ? hy1 : hy0) ^ ((k & 4) ? hz1 : hz0)) &
+                                   hmask) * F;
+              }
+              if (l < lds_levels) {  // wave-uniform
+#pragma unroll
+                for (int k = 0; k < 8; ++k) raw[u][k] = load_raw_lds<F, LP>(ltab, idx[k]);
+              } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) raw[u][k] = load_raw<F, LP>(table, idx[k]);
               }
             }
           }

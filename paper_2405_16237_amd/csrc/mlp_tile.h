@@ -54,7 +54,7 @@ struct PreBf16 {
 
 template <int NWAVES>
 __device__ inline PreBf16 prefetch_bf16(const bf16* __restrict__ W, int ldw, int K, int N) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int n = wave * 16 + (lane & 15);
   PreBf16 p{zero_bf16x8(), zero_bf16x8()};
   if (n < N) {
@@ -70,7 +70,7 @@ __device__ inline PreBf16 prefetch_bf16(const bf16* __restrict__ W, int ldw, int
 template <int M, int NWAVES, typename Epi>
 __device__ inline void gemm_tile_bf16(const bf16* act_in, int ld_in, int K, const bf16* __restrict__ W, int ldw,
                                       int N, Epi epi, const PreBf16* pre = nullptr) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int r16 = lane & 15, q = lane >> 4;
   const int n_tiles = (N + 15) >> 4;
   for (int nt = wave; nt < n_tiles; nt += NWAVES) {
@@ -113,7 +113,7 @@ __device__ inline void gemm_tile_bf16(const bf16* act_in, int ld_in, int K, cons
 template <int M, int NWAVES, typename Epi>
 __device__ inline void gemm_tile_f32(const float* act_in, int ld_in, int K, const float* __restrict__ W, int ldw,
                                      int N, Epi epi) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int r16 = lane & 15, q = lane >> 4;
   const int n_tiles = (N + 15) >> 4;
   for (int nt = wave; nt < n_tiles; nt += NWAVES) {
@@ -146,7 +146,7 @@ __device__ inline void gemm_tile_f32(const float* act_in, int ld_in, int K, cons
 template <int M, int NWAVES, typename Epi>
 __device__ inline void gemm_tile_fp8(const uint8_t* act_in, int ld_in, int K, const uint8_t* __restrict__ W, int ldw,
                                      int N, Epi epi) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int r16 = lane & 15, q = lane >> 4;
   const int n_tiles = (N + 15) >> 4;
   for (int nt = wave; nt < n_tiles; nt += NWAVES) {

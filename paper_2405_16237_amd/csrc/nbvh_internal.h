@@ -90,6 +90,11 @@ __device__ __host__ inline uint16_t f32_to_bf16_bits(float f) {
 // rounding per operation (the translation units are built without FP
 // contraction); identical operation order to the definition used for parity.
 // ---------------------------------------------------------------------------
+// Index of the calling thread's wavefront in its workgroup, as a
+// wave-uniform (scalar) value: loops and table look-ups keyed by it then use
+// scalar registers, scalar loads of per-level constants and uniform branches.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 __device__ inline void sample_position(const DevCfg& c, const float o[3], const float d[3], float t0,
                                        float t1, int s, float x[3]) {
   float frac = c.frac[s];

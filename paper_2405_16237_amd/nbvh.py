@@ -411,12 +411,27 @@ class NBVHBatch:
                                         _stream()))
         return hits
 
-    def train_step(self, probes, labels, losses=None):
-        """One optimiser step per object (batches probes[k], labels[k])."""
+    def train_step(self, probes, labels, losses=None, streams=None):
+        """One optimiser step per object (batches probes[k], labels[k]).
+        streams (optional, one torch stream per object, default priority):
+        each object's step is enqueued on its own stream, forked from and
+        joined back into the current stream, so the objects' kernels can run
+        concurrently (and a HIP graph captured around the call holds them as
+        parallel branches). The objects share no buffers."""
         if losses is None:
             losses = torch.empty((len(self.models), 4), dtype=torch.float32, device=self.device)
+        if streams is None:
+            for k, m in enumerate(self.models):
+                m.train_step(probes[k], labels[k], losses[k])
+            return losses
+        assert len(streams) == len(self.models)
+        cur = torch.cuda.current_stream()
         for k, m in enumerate(self.models):
-            m.train_step(probes[k], labels[k], losses[k])
+            streams[k].wait_stream(cur)
+            with torch.cuda.stream(streams[k]):
+                m.train_step(probes[k], labels[k], losses[k])
+        for st in streams:
+            cur.wait_stream(st)
         return losses
 
 

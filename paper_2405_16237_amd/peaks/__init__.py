@@ -56,7 +56,7 @@ def measure(torch, n_cu: int = 256, repeat: int = 3) -> dict:
     iters = 64
     for mb in (4, 32, 512):
         for eb in (4, 8):
-            for lines in (8, 64):
+            for lines in ((1, 2, 4, 8, 16, 64) if (mb == 32 and eb == 4) else (8, 64)):
                 ms = best(lambda: _ok(L.peaks_gather(bp, mb << 20, eb, lines, grid, iters, sp, s), "gather"))
                 n = grid * 256 * iters * 8
                 out["gather_%dMiB_%dB_%dlines" % (mb, eb, lines)] = dict(

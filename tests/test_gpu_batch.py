@@ -10,6 +10,7 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from nbvh_synth import configs, scene
+from query_check import clear_rays
 
 pytestmark = pytest.mark.gpu
 
@@ -70,11 +71,86 @@ def test_batch_query_matches_merged_oracle(objects):
     assert np.abs(hits[same, 0] - best_t[same]).max() <= 1e-5 * max(1.0, np.abs(best_t[same]).max())
 
 
-def test_graph_captured_batch_train_step(objects):
-    """The multi-object training step captured once in a HIP graph and
-    replayed three times (eager work and synchronisation in between) moves
-    the parameters as three eager steps do, within FP32 atomic-order
-    rounding."""
+@pytest.fixture(scope="module")
+def c4_shape():
+    """Objects with the batched workload's network (L=16, F=2, 8 samples,
+    256 -> 4x128 -> 5), its range of table sizes (T = 2^16, 2^18, 2^20) and
+    leaf counts (256, 1,024, 8,192), on meshes of at most 400,000 triangles,
+    and rays crossing 1..31 leaves (log-uniform)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_16237_amd as P
+    P.load()
+    specs = configs.c4_objects()
+    out = []
+    for k, log2_T in zip((0, 3, 7), (16, 18, 20)):
+        o = specs[k]
+        sc = configs.make_scene(min(o["n_tris"], 400_000), o["n_leaves"], seed=o["seed"], offset=o["offset"])
+        net = configs.NetConfig(16, 2, log2_T, 8, 16, 1.38, 128, 4, 5)
+        params = configs.init_params(net, "uniform", 1.0, seed_features=400 + k, seed_mlp=500 + k)
+        out.append((sc, net, params))
+    boxes_all = np.concatenate([sc.boxes for sc, _, _ in out])
+    rays, counts = configs.c4_rays(boxes_all, 20_000, seed=45, hi=32)
+    return P, out, rays, counts
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_batch_query_config4_shape(c4_shape, precision):
+    """The grouped query at the batched workload's network shape against the
+    per-object oracle queries merged by closest hit: 100 % agreement on rays
+    whose answer is unambiguous in every object and whose two best objects'
+    distances are apart by more than the distance tolerance."""
+    P, objs, rays, counts = c4_shape
+    models = []
+    for sc, net, params in objs:
+        m = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision=precision)
+        m.set_params(params)
+        models.append(m)
+    batch = P.NBVHBatch(models)
+    _say("batch query at the batched workload's shape:", precision, rays.shape[0], "rays, segments per ray %d..%d"
+         % (counts.min(), counts.max()))
+    hits = batch.query(torch.from_numpy(rays).cuda(), 40 * rays.shape[0]).cpu().numpy()
+    word = hits[:, 7].view(np.uint32)
+    n = rays.shape[0]
+    ts = np.full((len(objs), n), np.inf)
+    clear = np.ones(n, bool)
+    codes = np.full((len(objs), n), -1, np.int64)
+    tol = 1e-5 if precision == "fp32" else 2e-2
+    for k, (sc, net, params) in enumerate(objs):
+        pref = params if precision == "fp32" else torch.from_numpy(params).to(torch.bfloat16).float().numpy()
+        out, tr, z = oracle.query(oracle.make_cfg(net, sc.lo, sc.side), pref.astype(np.float64), rays, sc.boxes)
+        ztol = (tol * np.repeat(np.abs(z).max(1, keepdims=True), net.n_out, 1) if precision == "fp32"
+                else tol * np.maximum(1.0, np.abs(z)))
+        clear &= clear_rays(tr, z, out, rays[:, 3], ztol)
+        hit = out[:, 4] >= 0
+        ts[k, hit] = out[hit, 0]
+        codes[k, hit] = (k << 24) | out[hit, 4].astype(np.int64)
+    order = np.argsort(ts, axis=0, kind="stable")
+    best, second = order[0], order[1]
+    t_best = ts[best, np.arange(n)]
+    t_second = ts[second, np.arange(n)]
+    gap = 1e-4 if precision == "fp32" else 2e-2
+    clear &= ~(np.isfinite(t_second) & (t_second - t_best <= gap * np.maximum(1.0, np.abs(t_best))))
+    want = np.where(np.isfinite(t_best), codes[best, np.arange(n)], -1)
+    got = np.where(word == 0xFFFFFFFF, -1, word.astype(np.int64))
+    _say("clear share %.4f, agreement on clear rays %.6f, overall %.6f" %
+         (clear.mean(), (got[clear] == want[clear]).mean(), (got == want).mean()))
+    assert clear.mean() > 0.5 and counts.max() >= 24
+    assert np.array_equal(got[clear], want[clear])
+    same = clear & (want >= 0)
+    assert same.sum() > 1000
+    dt = np.abs(hits[same, 0] - t_best[same])
+    if precision == "fp32":
+        assert dt.max() <= 1e-5 * max(1.0, np.abs(t_best[same]).max())
+
+
+@pytest.mark.parametrize("branches", [False, True])
+def test_graph_captured_batch_train_step(objects, branches):
+    """The multi-object training step captured once in a HIP graph (the
+    objects one after another, or each on a stream of its own so that the
+    graph holds them as parallel branches) and replayed three times (eager
+    work and synchronisation in between) moves the parameters as three eager
+    steps do, within FP32 atomic-order rounding."""
     P, objs = objects
     probes, labels = [], []
     for k, (sc, net, params) in enumerate(objs):
@@ -104,8 +180,9 @@ def test_graph_captured_batch_train_step(objects):
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     _say("capturing the batch train step")
+    streams = [torch.cuda.Stream() for _ in objs] if branches else None
     with torch.cuda.graph(g, stream=s):
-        graphed.train_step(probes, labels, losses)
+        graphed.train_step(probes, labels, losses, streams=streams)
     torch.cuda.synchronize()
     # capture does not execute: parameters are untouched
     assert np.array_equal(graphed.models[0].get_params(), objs[0][2])

@@ -196,6 +196,56 @@ def test_view_shares_the_network(lib, c1):
         lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp8").view(coarse)
 
 
+def test_lod_view_training_step_matches_oracle(lib, c1):
+    """Levels of detail (Sec. 5.3) against the oracle: training rays through
+    a coarse cut's view (first leaf of the coarse cut, per-leaf acceptance)
+    are the oracle's first hits on that cut, bit for bit; one FP32 training
+    step on them through the view moves the shared parameters as the
+    oracle's step does, and the fine tree sees the moved parameters."""
+    sc = c1
+    net = configs.C1_NET
+    params = configs.init_params(net, "uniform", 1.0, seed_features=81, seed_mlp=82)
+    coarse, _ = scene.median_split_leaves(sc.verts, sc.tris, 16)
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32", loss_scale=1.0)
+    m.set_params(params)
+    v = m.view(coarse)
+    rays = _box_rays(sc, 12_000 + 7, 83)
+    rng = np.random.default_rng(84)
+    u = rng.uniform(size=rays.shape[0]).astype(np.float32)
+    accept = rng.uniform(0.2, 1.0, size=coarse.shape[0]).astype(np.float32)
+    _say("first hits through a 16-leaf view")
+    probes, leaf = v.first_hits(torch.from_numpy(rays).cuda(), torch.from_numpy(u).cuda(),
+                                torch.from_numpy(accept).cuda())
+    probes, leaf = v.group_by_leaf(probes, leaf)
+    p = probes.cpu().numpy()
+    ray, oleaf, t0, t1, _ = oracle.first_hits(rays, coarse, u, accept)
+    ref = np.zeros((ray.size, 8), dtype=np.float32)
+    ref[:, 0:3], ref[:, 3], ref[:, 4:7], ref[:, 7] = rays[ray, 0:3], t0, rays[ray, 4:7], t1
+    assert p.shape[0] == ray.size > 2000
+    kg, ko = np.lexsort(p.view(np.int32).T[::-1]), np.lexsort(ref.view(np.int32).T[::-1])
+    assert np.array_equal(p[kg].view(np.int32), ref[ko].view(np.int32))
+    assert np.array_equal(leaf.cpu().numpy()[kg].astype(np.int64), oleaf[ko])
+    lab = scene.probe_labels(sc.mesh, p)
+    cfg = oracle.make_cfg(net, sc.lo, sc.side)
+    p64 = params.astype(np.float64)
+    clear = oracle.min_abs_preact(cfg, p64, p) > 1e-4  # FP32 ReLU decisions equal the oracle's
+    assert clear.mean() > 0.5
+    p, lab = np.ascontiguousarray(p[clear]), np.ascontiguousarray(lab[clear])
+    _say("one training step through the view:", p.shape[0], "probes")
+    loss = v.train_step(torch.from_numpy(p).cuda(), torch.from_numpy(lab).cuda()).cpu().numpy()
+    mm, vv = np.zeros_like(p64), np.zeros_like(p64)
+    z = oracle.forward(cfg, p64, p)
+    terms, dz = oracle.loss(cfg, z, lab)
+    g = oracle.backward(cfg, p64, p, dz)
+    oracle.train_step(cfg, p64, mm, vv, 1, p, lab)
+    assert np.allclose(loss, terms, rtol=1e-5, atol=1e-7), (loss, terms)
+    got = m.get_params()  # the fine tree's parameters: one buffer
+    sel = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert sel.sum() > 1000
+    assert np.abs(got[sel] - p64[sel]).max() <= 1e-6
+    assert m.read_state()["step"] == 1
+
+
 def test_levels_of_detail(lib, c1):
     """Construction with levels of detail (Sec. 5.3): several cuts of one
     base BVH, coarse to fine, trained together on one network. Every level
