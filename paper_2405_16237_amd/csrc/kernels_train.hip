@@ -129,8 +129,8 @@ struct TrainPtrs {
 };
 
 template <typename AT>
-__device__ inline void put(AT* p, float v) {
-  p[0] = (AT)v;
+__device__ inline void put(AT* p, float v) {  // a global activation or gradient entry
+  global_store<AT>(p, (AT)v);
 }
 
 // Albedo (outputs 5..7 through a sigmoid; Sec. 5.2 "Auxiliary data"): relative
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(64 * kTWaves) __attribute__((amdgpu_waves_per_eu(4)
     AT* h0 = (AT*)P.hT[0];
     for (int e = tid; e < kTM * c.n_in; e += blockDim.x) {
       const int i = e / kTM, m = e - i * kTM;
-      h0[(size_t)i * ldb + base + m] = act0[(size_t)m * ld0 + i];
+      global_store<AT>(h0 + (size_t)i * ldb + base + m, act0[(size_t)m * ld0 + i]);
     }
   }
 
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(64 * kTWaves) __attribute__((amdgpu_waves_per_eu(4)
 #pragma unroll
     for (int o = 0; o < kGPad; ++o) {
       gz[(size_t)m * ldg + o] = (AT)g[o];
-      gH[(size_t)o * ldb + base + m] = (AT)g[o];
+      global_store<AT>(gH + (size_t)o * ldb + base + m, (AT)g[o]);
     }
     if (WITH_LABELS) {
       // wave reduction of the per-probe loss terms
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(64 * kTWaves) __attribute__((amdgpu_waves_per_eu(4)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const float x = ok ? v[i] : 0.0f;
-          du[(size_t)(col + i) * ldb + base + m] = x;
+          global_store<float>(du + (size_t)(col + i) * ldb + base + m, x);
           gm = fmaxf(gm, fabsf(x));
           bad = bad || !isfinite(x);
         }

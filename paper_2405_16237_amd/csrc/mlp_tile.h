@@ -93,13 +93,13 @@ __device__ inline void gemm_tile_bf16(const bf16* act_in, int ld_in, int K, cons
       }
 #pragma unroll
       for (int mt = 0; mt < M / 16; ++mt) {
-        bf16x8 b0 = *(const bf16x8*)(arow + (size_t)mt * 16 * ld_in + k0);
+        bf16x8 b0 = lds_load<bf16x8>(arow + (size_t)mt * 16 * ld_in + k0);
         acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[mt], 0, 0, 0);
       }
       if (two) {
 #pragma unroll
         for (int mt = 0; mt < M / 16; ++mt) {
-          bf16x8 b1 = *(const bf16x8*)(arow + (size_t)mt * 16 * ld_in + k0 + 32);
+          bf16x8 b1 = lds_load<bf16x8>(arow + (size_t)mt * 16 * ld_in + k0 + 32);
           acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[mt], 0, 0, 0);
         }
       }
@@ -128,7 +128,7 @@ __device__ inline void gemm_tile_f32(const float* act_in, int ld_in, int K, cons
       float4 a = nvalid ? *(const float4*)(wrow + k0) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int mt = 0; mt < M / 16; ++mt) {
-        float4 b = *(const float4*)(arow + (size_t)mt * 16 * ld_in + k0);
+        const f32x4 b = lds_load<f32x4>(arow + (size_t)mt * 16 * ld_in + k0);
         acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[mt], 0, 0, 0);
         acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[mt], 0, 0, 0);
         acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[mt], 0, 0, 0);
@@ -161,7 +161,7 @@ __device__ inline void gemm_tile_fp8(const uint8_t* act_in, int ld_in, int K, co
       const long a = nvalid ? *(const long*)(wrow + k0) : 0l;
 #pragma unroll
       for (int mt = 0; mt < M / 16; ++mt) {
-        const long b = *(const long*)(arow + (size_t)mt * 16 * ld_in + k0);
+        const long b = lds_load<long>(arow + (size_t)mt * 16 * ld_in + k0);
         acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc[mt], 0, 0, 0);
       }
     }
@@ -228,15 +228,16 @@ __device__ inline void gemm_tile(const AT* act_in, int ld_in, int K, const AT* W
     gemm_tile_f32<M, NWAVES>(act_in, ld_in, K, W, ldw, N, epi);
 }
 
+// four consecutive activations of an LDS tile row
 template <typename AT>
 __device__ inline void store4(AT* dst, f32x4 v) {
   if constexpr (sizeof(AT) == 2) {
     bf16x4 b;
 #pragma unroll
     for (int i = 0; i < 4; ++i) b[i] = (bf16)v[i];
-    *(bf16x4*)dst = b;
+    lds_store<bf16x4>(dst, b);
   } else {
-    *(f32x4*)dst = v;
+    lds_store<f32x4>(dst, v);
   }
 }
 

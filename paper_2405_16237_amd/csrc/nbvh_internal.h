@@ -90,6 +90,25 @@ __device__ __host__ inline uint16_t f32_to_bf16_bits(float f) {
 // rounding per operation (the translation units are built without FP
 // contraction); identical operation order to the definition used for parity.
 // ---------------------------------------------------------------------------
+// Explicit address spaces for accesses through pointers whose space the
+// compiler cannot infer (a pointer picked at run time from several LDS
+// tiles, or read from a kernel-argument struct): LDS accesses then compile to
+// ds_read/ds_write and global ones to global_load/store, not to flat ones.
+#define NBVH_LDS __attribute__((address_space(3)))
+#define NBVH_GLOBAL __attribute__((address_space(1)))
+template <typename V, typename T>
+__device__ inline V lds_load(const T* p) {
+  return *(const V NBVH_LDS*)((const char NBVH_LDS*)p);
+}
+template <typename V, typename T>
+__device__ inline void lds_store(T* p, V v) {
+  *(V NBVH_LDS*)((char NBVH_LDS*)p) = v;
+}
+template <typename V, typename T>
+__device__ inline void global_store(T* p, V v) {
+  *(V NBVH_GLOBAL*)((char NBVH_GLOBAL*)p) = v;
+}
+
 // Index of the calling thread's wavefront in its workgroup, as a
 // wave-uniform (scalar) value: loops and table look-ups keyed by it then use
 // scalar registers, scalar loads of per-level constants and uniform branches.
