@@ -774,11 +774,12 @@ def run_batched(args, P, torch, configs, scene):
 def run_construct(args, P, torch, configs, scene):
     """Error-driven construction (Sec. 5.1) at the frame workload's size: a
     cut of the 1,003,520-triangle mesh's base BVH (16 triangles per node)
-    grown to 1,024 leaves while the frame network trains on 2^18 candidate
-    rays per step (first leaf only, per-leaf acceptance), then a final
-    training round. Labels come from the host's Moller-Trumbore (the
-    classical intersection the paper's training data comes from); their
-    time is reported apart from the library's."""
+    grown to 1,024 leaves while the frame network trains on 2^16 candidate
+    rays per step (first leaf only, per-leaf acceptance; 2^18 rays per
+    statistics round), then a final training round of --pretrain steps.
+    Labels come from the host's Moller-Trumbore (the classical intersection
+    the paper's training data comes from); their time is reported apart
+    from the library's."""
     from paper_2405_16237_amd import construct as C
     t0 = time.time()
     sc = configs.make_scene(1_003_520, 1024)
@@ -795,8 +796,8 @@ def run_construct(args, P, torch, configs, scene):
         label_s[1] += p.shape[0]
         return out
 
-    sched = C.Schedule(target_leaves=1024, iters=60, iters_growth=1.25, splits=8, splits_growth=1.6,
-                       final_iters=args.pretrain, rays_per_step=1 << 18, stats_rays=1 << 18)
+    sched = C.Schedule(target_leaves=1024, iters=30, iters_growth=1.2, splits=16, splits_growth=1.7,
+                       final_iters=args.pretrain, rays_per_step=1 << 16, stats_rays=1 << 18)
     prep = time.time() - t0
     torch.cuda.synchronize()
     t1 = time.time()
@@ -815,7 +816,7 @@ def run_construct(args, P, torch, configs, scene):
         "value": total, "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
         "config": {"workload": "cut of the base BVH (16 triangles per node) of a 1,003,520-triangle displaced "
                                "icosphere grown to 1,024 leaves; network L=16 F=2 T=2^19, 8 samples, MLP 256-4x128-5; "
-                               "2^18 candidate rays per training step and per statistics round"},
+                               "2^16 candidate rays per training step, 2^18 per statistics round"},
         "host_labels_s": label_s[0], "labelled_probes": label_s[1], "library_and_driver_s": total - label_s[0],
         "training_steps": steps, "rounds": len(hist), "leaves": len(cut.nodes), "setup_s": prep,
         "accuracy_480x270": acc, "history": hist,
