@@ -123,6 +123,40 @@ def parity(torch, m, rays_np, sc, net, params, precision, inside, what):
                 oracle_params="BF16-rounded" if precision == "bf16" else "FP32 master")
 
 
+def node_visits(model, rays_np):
+    """Mean nodes a ray's own walk visits (the root, then every inner child
+    whose box the ray hits: one node load and two slab tests each), counted
+    on the host from the node buffer the library built, with the slab test in
+    binary32 as the kernels evaluate it."""
+    boxes, children = model.tree()
+    o = rays_np[:, 0:3].astype(np.float32)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = (np.float32(1.0) / rays_np[:, 4:7]).astype(np.float32)
+    neg = np.signbit(rays_np[:, 4:7])
+    tmin, tmax = rays_np[:, 3].astype(np.float32), rays_np[:, 7].astype(np.float32)
+    ray = np.arange(rays_np.shape[0])
+    node = np.zeros_like(ray)
+    visits = 0
+    while ray.size:
+        visits += ray.size
+        nxt_r, nxt_n = [], []
+        for k in range(2):
+            c = children[node, k].astype(np.int64)
+            b = boxes[node, k]
+            with np.errstate(invalid="ignore"):
+                ta = (b[:, 0:3] - o[ray]) * inv[ray]
+                tb = (b[:, 3:6] - o[ray]) * inv[ray]
+            near = np.where(neg[ray], tb, ta)
+            far = np.where(neg[ray], ta, tb)
+            tn = np.fmax(tmin[ray], np.fmax.reduce(near, axis=1))
+            tf = np.fmin(tmax[ray], np.fmin.reduce(far, axis=1))
+            enter = (tn <= tf) & (c >= 0) & (c != 0x7FFFFFFF)
+            nxt_r.append(ray[enter])
+            nxt_n.append(c[enter])
+        ray, node = np.concatenate(nxt_r), np.concatenate(nxt_n)
+    return visits / max(1, rays_np.shape[0])
+
+
 def build_frame(configs, scene, samples=8):
     W = Workload()
     W.name = "frame"
@@ -394,6 +428,16 @@ def run_single(args, W, P, torch, configs, scene):
         del f8, hits_f8
 
     roofline = rooflines(prof, net, bf.get_tuning(), evaluated, B, R, n_segments, W.name)
+    # traversal rate in node visits: visits per ray counted on the parity
+    # sample, times the rays of the timed traversal
+    tr = roofline["per_kernel"].get("traverse")
+    if tr is not None:
+        sub, what = W.cpu_sample(W.parity_stride)
+        vpr = node_visits(bf, sub)
+        tr["node_visits_per_ray"] = round(vpr, 3)
+        tr["node_visits_per_s"] = round(vpr * R / (tr["avg_ms"] * 1e-3), 1)
+        tr["node_visits_sample"] = what
+        log("traversal: %.2f node visits per ray, %.3g visits/s" % (vpr, tr["node_visits_per_s"]))
     peaks = None
     if not args.no_peaks:
         from paper_2405_16237_amd import peaks as PK

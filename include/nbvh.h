@@ -216,6 +216,10 @@ typedef struct {
                                there whole once per workgroup and gathered from LDS; as many leading
                                levels as fit, none if the first does not; ignored with query_pairs
                                and by grouped queries: 0..64 (0) */
+  int32_t traverse_mode;    /* how a wave walks the tree: 0 = each lane its own ray (per-lane stacks),
+                               1 = the wave together over the union of its rays' nodes (one node load
+                               per wave), 2 = the wave together when its rays are coherent (directions
+                               and origins close), else each lane alone (2) */
 } nbvh_tuning;
 
 /* Read / replace the context's launch knobs (validated). */
@@ -237,7 +241,14 @@ nbvh_status nbvh_param_layout(const nbvh_config* cfg, uint64_t* offsets);
  * weights and per-layer scales (written by nbvh_calibrate_fp8). */
 size_t nbvh_aux_bytes(const nbvh_config* cfg);
 
-/* Bytes of the node buffer nbvh_build writes for n_leaves leaves. */
+/* Bytes of the node buffer nbvh_build writes for n_leaves leaves:
+ * max(1, n_leaves - 1) nodes of 64 bytes, node 0 the root. A node holds the
+ * boxes of its two children and their indices: float lo0[3], hi0[3],
+ * lo1[3], hi1[3]; int32 c0, c1; int32 pad[2]. A child index c >= 0 is the
+ * inner node c (always after its parent), c < 0 the leaf ~c; c1 = 0x7fffffff
+ * marks the missing second child of a single-leaf tree. The layout is fixed
+ * so that callers may read the tree (for instance to count the nodes a ray
+ * visits); the library only reads the buffer after nbvh_build. */
 size_t nbvh_nodes_bytes(uint32_t n_leaves);
 
 /* Bytes of the device state block. */

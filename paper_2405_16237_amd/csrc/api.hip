@@ -396,7 +396,7 @@ nbvh_status nbvh_build(const nbvh_config* cfg, const float* leaf_boxes_host, uin
   hipDeviceProp_t prop;
   ctx->n_cu = (hipGetDeviceProperties(&prop, dev) == hipSuccess) ? prop.multiProcessorCount : 256;
   if (ctx->n_cu <= 0) ctx->n_cu = 256;
-  ctx->tune = nbvh_tuning{8, 0, 0, 8, 64, 0, 1, 8, 0, 0};
+  ctx->tune = nbvh_tuning{8, 0, 0, 8, 64, 0, 1, 8, 0, 0, 2};
   void* sp = nullptr;
   s = scratch_for_current_device(&sp);  // set-up of the no-allocation query on this device
   if (s != NBVH_OK) {
@@ -801,6 +801,7 @@ nbvh_status nbvh_set_tuning(nbvh_ctx* ctx, const nbvh_tuning* t) {
     return set_error("scatter_hash_levels in 0..32"), NBVH_ERR_INVALID_ARG;
   if (t->query_pairs != 0 && t->query_pairs != 1) return set_error("query_pairs must be 0 or 1"), NBVH_ERR_INVALID_ARG;
   if (t->query_lds_kb < 0 || t->query_lds_kb > 64) return set_error("query_lds_kb in 0..64"), NBVH_ERR_INVALID_ARG;
+  if (t->traverse_mode < 0 || t->traverse_mode > 2) return set_error("traverse_mode must be 0, 1 or 2"), NBVH_ERR_INVALID_ARG;
   ctx->tune = *t;
   return NBVH_OK;
 }

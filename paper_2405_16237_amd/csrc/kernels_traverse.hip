@@ -14,8 +14,10 @@ namespace nbvh {
 struct RayPre {
   float o[3], d[3], inv[3];
   float tmin, tmax;
+  bool neg[3];  // the direction's sign bit: the far plane of the slab is lo
 };
 
+// inv = 1 / d, also where d is zero (inv = +-inf; see slab).
 __device__ inline RayPre load_ray(const nbvh_ray* rays, uint32_t r) {
   const float4* p = (const float4*)(rays + r);
   float4 a = p[0], b = p[1];
@@ -29,11 +31,18 @@ __device__ inline RayPre load_ray(const nbvh_ray* rays, uint32_t r) {
   R.d[2] = b.z;
   R.tmax = b.w;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) R.inv[k] = (R.d[k] == 0.0f) ? 0.0f : 1.0f / R.d[k];
+  for (int k = 0; k < 3; ++k) {
+    R.inv[k] = 1.0f / R.d[k];
+    R.neg[k] = __float_as_uint(R.d[k]) >> 31;
+  }
   return R;
 }
 
 // hit iff tn <= tf; axis with zero direction: origin must lie in the slab.
+// That case needs no branch: inv is +-inf, so (plane - o) * inv is -inf or
+// +inf by the side of the plane the origin lies on (the interval is left
+// alone or made empty) and NaN when the origin lies on the plane, which
+// fmaxf / fminf ignore (the plane counts as inside).
 // REV (reversed inside queries): `inside` is set when the ray's line enters
 // the box before tmin (entry te = the largest near-plane distance) and the
 // box is hit, i.e. the origin lies in the box; the interval is then the chord
@@ -42,25 +51,16 @@ template <bool REV>
 __device__ inline bool slab(const RayPre& R, const float lo[3], const float hi[3], float& t0, float& t1,
                             bool& inside) {
   float tn = R.tmin, tf = R.tmax, te = -INFINITY;
-  bool ok = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if (R.d[a] == 0.0f) {
-      ok = ok && !(R.o[a] < lo[a] || R.o[a] > hi[a]);
-    } else {
-      float ta = (lo[a] - R.o[a]) * R.inv[a];
-      float tb = (hi[a] - R.o[a]) * R.inv[a];
-      if (R.inv[a] < 0.0f) {
-        float s = ta;
-        ta = tb;
-        tb = s;
-      }
-      tn = fmaxf(tn, ta);
-      if (REV) te = fmaxf(te, ta);
-      tf = fminf(tf, tb);
-    }
+    const float ta = (lo[a] - R.o[a]) * R.inv[a];
+    const float tb = (hi[a] - R.o[a]) * R.inv[a];
+    const float tnear = R.neg[a] ? tb : ta, tfar = R.neg[a] ? ta : tb;
+    tn = fmaxf(tn, tnear);
+    if (REV) te = fmaxf(te, tnear);
+    tf = fminf(tf, tfar);
   }
-  const bool hit = ok && (tn <= tf);
+  const bool hit = tn <= tf;
   inside = REV && hit && te < R.tmin;
   t0 = inside ? te : tn;
   t1 = tf;
@@ -120,27 +120,189 @@ __device__ inline void walk(const Node* __restrict__ nodes, const RayPre& R, Emi
   }
 }
 
-// Staged runs are plane-major: record i of ray r is (leaf, t0, t1) at
-// planes 3i, 3i+1, 3i+2 of n_rays floats each, so that neighbouring rays
-// (lanes) touch neighbouring words. Insert (leaf, t0, t1) into ray r's
-// sorted run of k records (order (t0, leaf id)).
-__device__ inline void insert_staged(float* st, size_t plane, uint32_t k, int32_t leaf, float t0, float t1) {
-  uint32_t j = k;
-  while (j > 0) {
-    const float p0 = st[(3 * (j - 1) + 1) * plane];
-    const uint32_t pl = __float_as_uint(st[(3 * (j - 1)) * plane]);
-    if (p0 > t0 || (p0 == t0 && pl > (uint32_t)leaf)) {
-      st[(3 * j) * plane] = __uint_as_float(pl);
-      st[(3 * j + 1) * plane] = p0;
-      st[(3 * j + 2) * plane] = st[(3 * (j - 1) + 2) * plane];
-      --j;
+// Wave-coherent walk: the wave visits the union of its live lanes' nodes in
+// one order that every lane shares. The node index is uniform, so a visit
+// reads the node's 64 bytes once through the scalar cache instead of once per
+// lane through the vector memory path; each lane tests both children against
+// its own ray, and a child is entered when any lane hits it. The stack is one
+// register holding entry i in lane i (pushes select the lane, pops read it),
+// at most kMaxDepth < 64 entries. Both children entered: the one nearer along
+// the guide direction g first, so that each lane's leaves come out mostly in
+// front-to-back order. Must be called by every lane of the wave together.
+template <bool REV, typename Emit>
+__device__ inline void walk_wave(const Node* __restrict__ nodes, const RayPre& R, bool live, Emit emit, float gx,
+                                 float gy, float gz) {
+  const int lane = (int)(threadIdx.x & 63);
+  int32_t stk = 0;
+  int sp = 0;
+  int32_t node = 0;
+  while (true) {
+    const float4* p = (const float4*)(nodes + node);
+    float4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+    const float lo0[3] = {q0.x, q0.y, q0.z}, hi0[3] = {q0.w, q1.x, q1.y};
+    const float lo1[3] = {q1.z, q1.w, q2.x}, hi1[3] = {q2.y, q2.z, q2.w};
+    const int32_t c0 = __float_as_int(q3.x), c1 = __float_as_int(q3.y);
+    float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
+    bool ia = false, ib = false;
+    const bool h0 = live && slab<REV>(R, lo0, hi0, a0, a1, ia);
+    const bool h1 = live && (c1 != kEmptyChild) && slab<REV>(R, lo1, hi1, b0, b1, ib);
+    if (h0 && c0 < 0) emit(~c0, a0, a1, ia);
+    if (h1 && c1 < 0) emit(~c1, b0, b1, ib);
+    const bool e0 = c0 >= 0 && __ballot(h0) != 0ull;
+    const bool e1 = c1 >= 0 && c1 != kEmptyChild && __ballot(h1) != 0ull;
+    int32_t next;
+    if (e0 && e1) {
+      const float k0 = (lo0[0] + hi0[0]) * gx + (lo0[1] + hi0[1]) * gy + (lo0[2] + hi0[2]) * gz;
+      const float k1 = (lo1[0] + hi1[0]) * gx + (lo1[1] + hi1[1]) * gy + (lo1[2] + hi1[2]) * gz;
+      const bool first1 = __builtin_amdgcn_readfirstlane((int)(k1 < k0)) != 0;
+      const int32_t later = first1 ? c0 : c1;
+      stk = (lane == sp) ? later : stk;
+      ++sp;
+      next = first1 ? c1 : c0;
+    } else if (e0) {
+      next = c0;
+    } else if (e1) {
+      next = c1;
     } else {
-      break;
+      if (sp == 0) break;
+      --sp;
+      next = __builtin_amdgcn_readlane(stk, sp);
+    }
+    node = __builtin_amdgcn_readfirstlane(next);
+  }
+}
+
+// traverse_mode: 0 = per-lane walk, 1 = wave-coherent walk, 2 = per wave,
+// the wave-coherent walk when the wave's rays are coherent: every live
+// lane's unit direction within kCoherentDir (max-norm) of the first live
+// lane's and its origin within 1/kCoherentOrg of the root box's largest
+// extent of that lane's. Coherent rays share most of their nodes: a
+// 64-pixel row of a 1920-pixel camera visits 7 % more nodes as a union than
+// its slowest lane alone, and the walk per wave is 20-40 % faster on camera
+// rays at 1,024 and 16,384 leaves; on scattered bounce rays and on random
+// training rays it is 25-75 % slower.
+constexpr float kCoherentDir = 0.25f;
+constexpr float kCoherentOrg = 32.0f;
+
+__device__ inline float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Whether this wave walks together, and its guide direction. Called by every
+// lane of the wave; lanes without a ray pass live = false.
+__device__ inline bool wave_walks(int mode, const Node* __restrict__ nodes, const RayPre& R, bool live, float g[3]) {
+  const uint64_t lm = __ballot(live);
+  if (mode == 0 || lm == 0ull) return false;
+  const int gl = __ffsll((unsigned long long)lm) - 1;
+  const float n2 = R.d[0] * R.d[0] + R.d[1] * R.d[1] + R.d[2] * R.d[2];
+  const float inv = n2 > 0.0f ? 1.0f / sqrtf(n2) : 0.0f;
+  float dn[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    dn[k] = R.d[k] * inv;
+    g[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dn[k]), gl));
+  }
+  if (mode == 1) return true;
+  const float4* p = (const float4*)nodes;
+  const float4 q0 = p[0], q1 = p[1], q2 = p[2];
+  const float ext = fmaxf(fmaxf(fmaxf(q0.w, q2.y) - fminf(q0.x, q1.z), fmaxf(q1.x, q2.z) - fminf(q0.y, q1.w)),
+                          fmaxf(q1.y, q2.w) - fminf(q0.z, q2.x));
+  float dev = 0.0f;
+  if (live) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float og = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(R.o[k]), gl));
+      dev = fmaxf(dev, fabsf(dn[k] - g[k]) * (1.0f / kCoherentDir));
+      dev = fmaxf(dev, fabsf(R.o[k] - og) * kCoherentOrg / fmaxf(ext, 1e-30f));
     }
   }
-  st[(3 * j) * plane] = __uint_as_float((uint32_t)leaf);
+  return wave_max(dev) <= 1.0f;
+}
+
+// The walk the mode asks for. Called by every lane of the wave (the
+// wave-coherent walk needs them all); lanes with live = false emit nothing.
+template <bool REV, typename Emit>
+__device__ inline void walk_mode(int mode, const Node* __restrict__ nodes, const RayPre& R, bool live, Emit emit,
+                                 int32_t* stk, uint32_t stride) {
+  float g[3] = {0.f, 0.f, 0.f};
+  if (wave_walks(mode, nodes, R, live, g))
+    walk_wave<REV>(nodes, R, live, emit, g[0], g[1], g[2]);
+  else if (live)
+    walk<REV>(nodes, R, emit, stk, stride);
+}
+
+// The last record of a sorted run, kept in registers: a segment that sorts
+// after it is appended without reading the run back.
+struct RunTail {
+  float t0 = 0.0f;
+  uint32_t tag = 0u;
+  __device__ bool before(float t, uint32_t g) const { return t0 < t || (t0 == t && tag < g); }
+};
+
+// Staged runs are plane-major: record i of ray r is (leaf, t0, t1) at
+// planes 3i, 3i+1, 3i+2 of n_rays floats each, so that neighbouring rays
+// (lanes) touch neighbouring words. Insert (tag, t0, t1) into ray r's sorted
+// run of k records (order (t0, tag)).
+__device__ inline void insert_staged(float* st, size_t plane, uint32_t k, uint32_t tag, float t0, float t1,
+                                     RunTail& tail) {
+  uint32_t j = k;
+  if (k == 0 || tail.before(t0, tag)) {
+    tail.t0 = t0;
+    tail.tag = tag;
+  } else {
+    while (j > 0) {
+      const float p0 = st[(3 * (j - 1) + 1) * plane];
+      const uint32_t pl = __float_as_uint(st[(3 * (j - 1)) * plane]);
+      if (p0 > t0 || (p0 == t0 && pl > tag)) {
+        st[(3 * j) * plane] = __uint_as_float(pl);
+        st[(3 * j + 1) * plane] = p0;
+        st[(3 * j + 2) * plane] = st[(3 * (j - 1) + 2) * plane];
+        --j;
+      } else {
+        break;
+      }
+    }
+  }
+  st[(3 * j) * plane] = __uint_as_float(tag);
   st[(3 * j + 1) * plane] = t0;
   st[(3 * j + 2) * plane] = t1;
+}
+
+// Insert (tag, t0, t1) into ray r's sorted run segs[beg, k) of the queue.
+__device__ inline void insert_queue(nbvh_segment* __restrict__ segs, uint32_t beg, uint32_t k, uint32_t r, uint32_t tag,
+                                    float t0, float t1, RunTail& tail) {
+  uint32_t j = k;
+  if (k == beg || tail.before(t0, tag)) {
+    tail.t0 = t0;
+    tail.tag = tag;
+  } else {
+    while (j > beg) {
+      const nbvh_segment prev = segs[j - 1];
+      if (prev.t0 > t0 || (prev.t0 == t0 && prev.leaf > tag)) {
+        segs[j] = prev;
+        --j;
+      } else {
+        break;
+      }
+    }
+  }
+  segs[j] = nbvh_segment{r, tag, t0, t1};
+}
+
+// A ray's precomputed form, or an inert one for lanes without a ray.
+__device__ inline RayPre load_ray_or_none(const nbvh_ray* rays, uint32_t r, bool live) {
+  if (live) return load_ray(rays, r);
+  RayPre R;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    R.o[k] = R.d[k] = R.inv[k] = 0.0f;
+    R.neg[k] = false;
+  }
+  R.tmin = 1.0f;
+  R.tmax = 0.0f;
+  return R;
 }
 
 // counts[r] = leaves crossed. If `hits` is given (full query), rays with no
@@ -153,20 +315,23 @@ template <bool REV>
 __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
                                                         uint32_t n_rays, uint32_t* __restrict__ counts,
                                                         nbvh_hit* __restrict__ hits, uint32_t* __restrict__ active,
-                                                        uint32_t* __restrict__ n_active, float* __restrict__ staging) {
+                                                        uint32_t* __restrict__ n_active, float* __restrict__ staging,
+                                                        int mode) {
   extern __shared__ int32_t s_stack[];
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = r < n_rays;
   uint32_t cnt = 0;
-  if (r < n_rays) {
-    RayPre R = load_ray(rays, r);
-    float* run = staging ? staging + r : nullptr;
-    walk<REV>(
-        nodes, R,
-        [&](int32_t leaf, float t0, float t1, bool inside) {
-          if (run && cnt < kStage) insert_staged(run, n_rays, cnt, (int32_t)seg_leaf(leaf, inside), t0, t1);
-          ++cnt;
-        },
-        s_stack + threadIdx.x, blockDim.x);
+  RunTail tail;
+  const RayPre R = load_ray_or_none(rays, r, live);
+  float* run = (staging && live) ? staging + r : nullptr;
+  walk_mode<REV>(
+      mode, nodes, R, live,
+      [&](int32_t leaf, float t0, float t1, bool inside) {
+        if (run && cnt < kStage) insert_staged(run, n_rays, cnt, seg_leaf(leaf, inside), t0, t1, tail);
+        ++cnt;
+      },
+      s_stack + threadIdx.x, blockDim.x);
+  if (live) {
     counts[r] = cnt;
     if (hits && cnt == 0) {
       float4* h = (float4*)(hits + r);
@@ -175,7 +340,7 @@ __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__
     }
   }
   if (active) {
-    const bool want = (r < n_rays) && cnt > 0;
+    const bool want = live && cnt > 0;
     const uint64_t mask = __ballot(want);
     if (mask) {
       const int lane = threadIdx.x & 63;
@@ -191,78 +356,37 @@ __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__
   }
 }
 
-template <bool REV>
-__global__ __launch_bounds__(256) void k_traverse_fill(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
-                                                       uint32_t n_rays, const uint32_t* __restrict__ offsets,
-                                                       nbvh_segment* __restrict__ segs, uint64_t capacity) {
-  extern __shared__ int32_t s_stack[];
-  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_rays) return;
-  if ((uint64_t)offsets[n_rays] > capacity) return;  // overflow flagged by the scan
-  const uint32_t beg = offsets[r], end = offsets[r + 1];
-  if (beg == end) return;
-  RayPre R = load_ray(rays, r);
-  uint32_t k = beg;
-  walk<REV>(
-      nodes, R,
-      [&](int32_t leaf, float t0, float t1, bool inside) {
-        // insertion into the sorted run [beg, k)
-        const uint32_t tag = seg_leaf(leaf, inside);
-        uint32_t j = k;
-        while (j > beg) {
-          nbvh_segment prev = segs[j - 1];
-          if (prev.t0 > t0 || (prev.t0 == t0 && prev.leaf > tag)) {
-            segs[j] = prev;
-            --j;
-          } else {
-            break;
-          }
-        }
-        segs[j] = nbvh_segment{r, tag, t0, t1};
-        ++k;
-      },
-      s_stack + threadIdx.x, blockDim.x);
-}
-
-// Compaction from the staging runs (rays with more than kStage segments walk
-// the tree again, as k_traverse_fill does).
+// Compaction from the staging runs: rays with more than kStage segments walk
+// the tree again and insert their segments into the queue directly.
 template <bool REV>
 __global__ __launch_bounds__(256) void k_traverse_compact(const Node* __restrict__ nodes,
                                                           const nbvh_ray* __restrict__ rays, uint32_t n_rays,
                                                           const uint32_t* __restrict__ offsets,
                                                           const float* __restrict__ staging,
-                                                          nbvh_segment* __restrict__ segs, uint64_t capacity) {
+                                                          nbvh_segment* __restrict__ segs, uint64_t capacity, int mode) {
   extern __shared__ int32_t s_stack[];
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_rays) return;
-  if ((uint64_t)offsets[n_rays] > capacity) return;  // overflow flagged by the scan
-  const uint32_t beg = offsets[r], end = offsets[r + 1];
-  if (beg == end) return;
-  if (end - beg <= kStage) {
+  if ((uint64_t)offsets[n_rays] > capacity) return;  // overflow flagged by the scan (uniform)
+  const uint32_t beg = r < n_rays ? offsets[r] : 0u, end = r < n_rays ? offsets[r + 1] : 0u;
+  if (end > beg && end - beg <= kStage) {
     const float* run = staging + r;
     const size_t plane = n_rays;
     for (uint32_t i = 0; i < end - beg; ++i)
       segs[beg + i] = nbvh_segment{r, __float_as_uint(run[(3 * i) * plane]), run[(3 * i + 1) * plane],
                                    run[(3 * i + 2) * plane]};
-    return;
   }
-  RayPre R = load_ray(rays, r);
+  const bool live = end - beg > kStage;
+  if (__ballot(live) == 0ull) return;  // no ray of the wave needs the walk
+  const RayPre R = load_ray_or_none(rays, r, live);
   uint32_t k = beg;
-  walk<REV>(
-      nodes, R,
+  RunTail tail;
+  walk_mode<REV>(
+      mode, nodes, R, live,
       [&](int32_t leaf, float t0, float t1, bool inside) {
-        const uint32_t tag = seg_leaf(leaf, inside);
-        uint32_t j = k;
-        while (j > beg) {
-          nbvh_segment prev = segs[j - 1];
-          if (prev.t0 > t0 || (prev.t0 == t0 && prev.leaf > tag)) {
-            segs[j] = prev;
-            --j;
-          } else {
-            break;
-          }
-        }
-        segs[j] = nbvh_segment{r, tag, t0, t1};
+        // the counting pass found end - beg leaves along this ray; a walk
+        // reports the same ones (every inner box is the union of its
+        // children's), the bound keeps the writes inside the run regardless
+        if (k < end) insert_queue(segs, beg, k, r, seg_leaf(leaf, inside), t0, t1, tail);
         ++k;
       },
       s_stack + threadIdx.x, blockDim.x);
@@ -278,29 +402,27 @@ __global__ __launch_bounds__(256) void k_first_hits(const Node* __restrict__ nod
                                                     uint32_t n, const float* __restrict__ u,
                                                     const float* __restrict__ accept, nbvh_probe* __restrict__ probes,
                                                     uint32_t* __restrict__ leaf_out, uint32_t* __restrict__ n_out,
-                                                    uint32_t* __restrict__ leaf_hits) {
+                                                    uint32_t* __restrict__ leaf_hits, int mode) {
   extern __shared__ int32_t s_stack[];
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = r < n;
   bool take = false, b_in = false;
   int32_t best = -1;
   float b0 = 0.f, b1 = 0.f;
-  RayPre R;
-  if (r < n) {
-    R = load_ray(rays, r);
-    walk<REV>(
-        nodes, R,
-        [&](int32_t leaf, float t0, float t1, bool inside) {
-          if (leaf_hits) atomicAdd(&leaf_hits[leaf], 1u);
-          if (best < 0 || t0 < b0 || (t0 == b0 && leaf < best)) {
-            best = leaf;
-            b0 = t0;
-            b1 = t1;
-            b_in = inside;
-          }
-        },
-        s_stack + threadIdx.x, blockDim.x);
-    take = best >= 0 && u[r] < accept[best];
-  }
+  const RayPre R = load_ray_or_none(rays, r, live);
+  walk_mode<REV>(
+      mode, nodes, R, live,
+      [&](int32_t leaf, float t0, float t1, bool inside) {
+        if (leaf_hits) atomicAdd(&leaf_hits[leaf], 1u);
+        if (best < 0 || t0 < b0 || (t0 == b0 && leaf < best)) {
+          best = leaf;
+          b0 = t0;
+          b1 = t1;
+          b_in = inside;
+        }
+      },
+      s_stack + threadIdx.x, blockDim.x);
+  take = live && best >= 0 && u[r] < accept[best];
   const uint64_t mask = __ballot(take);
   if (mask) {
     const int lane = threadIdx.x & 63;
@@ -332,7 +454,7 @@ nbvh_status launch_first_hits(const LaunchCtx& L, const nbvh_ray* rays, uint32_t
   k_zero_u32<<<1, 64, 0, L.stream>>>(n_out, 1);
   if (n > 0)
     (L.cfg.inside_reverse ? k_first_hits<true> : k_first_hits<false>)<<<(n + 255) / 256, 256, stack_lds(L), L.stream>>>(
-        L.nodes, rays, n, u, accept, probes, leaf_out, n_out, leaf_hits);
+        L.nodes, rays, n, u, accept, probes, leaf_out, n_out, leaf_hits, L.tune.traverse_mode);
   return check_launch("first_hits");
 }
 
@@ -551,6 +673,7 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
                             nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
                             uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
                             uint32_t* scratch_total, float* staging) {
+  if (segs && !staging) return set_error("traversal staging buffer missing"), NBVH_ERR_INVALID_ARG;
   ProfScope ps(L.prof, NBVH_K_TRAVERSE, L.stream);
   const int grid = (int)((n_rays + 255) / 256);
   if (n_active) {
@@ -558,21 +681,17 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
   }
   if (n_rays > 0)
     (L.cfg.inside_reverse ? k_traverse_count<true> : k_traverse_count<false>)<<<grid, 256, stack_lds(L), L.stream>>>(
-        L.nodes, rays, n_rays, scratch_counts, hits, active, n_active, segs ? staging : nullptr);
+        L.nodes, rays, n_rays, scratch_counts, hits, active, n_active, segs ? staging : nullptr,
+        L.tune.traverse_mode);
   const uint32_t n_tiles = (n_rays + kScanTile - 1) / kScanTile;
   if (n_rays > 0) k_scan_tiles<<<n_tiles, 256, 0, L.stream>>>(scratch_counts, n_rays, offsets, scratch_sums);
   k_scan_sums<<<1, 1024, 0, L.stream>>>(scratch_sums, n_tiles, scratch_total);
   k_scan_add<<<grid > 0 ? grid : 1, 256, 0, L.stream>>>(offsets, n_rays, scratch_sums, scratch_total, capacity,
                                                         L.state);
-  if (segs && n_rays > 0) {
-    if (staging)
-      (L.cfg.inside_reverse ? k_traverse_compact<true> : k_traverse_compact<false>)<<<grid, 256, stack_lds(L),
-                                                                                       L.stream>>>(
-          L.nodes, rays, n_rays, offsets, staging, segs, capacity);
-    else
-      (L.cfg.inside_reverse ? k_traverse_fill<true> : k_traverse_fill<false>)<<<grid, 256, stack_lds(L), L.stream>>>(
-          L.nodes, rays, n_rays, offsets, segs, capacity);
-  }
+  if (segs && n_rays > 0)
+    (L.cfg.inside_reverse ? k_traverse_compact<true> : k_traverse_compact<false>)<<<grid, 256, stack_lds(L),
+                                                                                     L.stream>>>(
+        L.nodes, rays, n_rays, offsets, staging, segs, capacity, L.tune.traverse_mode);
   return check_launch("traverse");
 }
 

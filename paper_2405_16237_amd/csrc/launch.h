@@ -77,8 +77,9 @@ void set_error(const char* fmt, ...);
 __global__ void k_zero_u32(uint32_t* p, uint32_t n);
 __global__ void k_zero_f32(float* p, uint64_t n);
 
-// `staging` (optional, traverse_staging_bytes(n_rays)): sorted per-ray runs
-// kept by the counting pass so that the fill copies instead of walking again.
+// `staging` (traverse_staging_bytes(n_rays), required with `segs`): sorted
+// per-ray runs kept by the counting pass so that the compaction copies them
+// instead of walking again.
 size_t traverse_staging_bytes(uint64_t n_rays);
 nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n_rays, uint32_t* offsets,
                             nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,

@@ -196,6 +196,16 @@ class NBVH:
                                   _ptr(nodes), nb, _stream(), ctypes.byref(ctx)))
         return ctx, nodes, lb.shape[0]
 
+    def tree(self):
+        """The node buffer nbvh_build wrote, as host arrays: child boxes
+        [n_nodes][2][6] float32 (lo.xyz, hi.xyz) and child indices
+        [n_nodes][2] int32 (>= 0 inner node, < 0 leaf ~c, 0x7fffffff none)."""
+        raw = self.nodes.cpu().numpy()
+        f = raw.view(np.float32).reshape(-1, 16)
+        boxes = f[:, :12].reshape(-1, 2, 6).copy()
+        children = raw.view(np.int32).reshape(-1, 16)[:, 12:14].copy()
+        return boxes, children
+
     # -- calls --------------------------------------------------------------------
     def first_hits(self, rays: torch.Tensor, u: torch.Tensor, accept: torch.Tensor,
                    leaf_hits: torch.Tensor | None = None):

@@ -47,9 +47,11 @@ def _box_rays(sc, n, seed):
     return r
 
 
-def test_first_hits_match_oracle(lib, c1):
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_first_hits_match_oracle(lib, c1, mode):
     sc = c1
     m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="fp32")
+    m.set_tuning(traverse_mode=mode)
     rays = _box_rays(sc, 50_000 + 33, 71)
     rng = np.random.default_rng(72)
     u = rng.uniform(size=rays.shape[0]).astype(np.float32)
@@ -57,7 +59,7 @@ def test_first_hits_match_oracle(lib, c1):
     accept[:5] = 1.0
     accept[5:8] = 0.0
     hits = torch.zeros(sc.boxes.shape[0], dtype=torch.int32, device="cuda")
-    _say("first hits", rays.shape)
+    _say("first hits", rays.shape, "mode", mode)
     probes, leaf = m.first_hits(torch.from_numpy(rays).cuda(), torch.from_numpy(u).cuda(),
                                 torch.from_numpy(accept).cuda(), leaf_hits=hits)
     ray, oleaf, t0, t1, ohits = oracle.first_hits(rays, sc.boxes, u, accept)

@@ -43,12 +43,14 @@ def c1():
     return sc, rays
 
 
-def test_traverse_reverse_bit_exact(lib, c1):
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_traverse_reverse_bit_exact(lib, c1, mode):
     sc, rays_np = c1
     m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="fp32", inside="reverse")
+    m.set_tuning(traverse_mode=mode)
     off_o, sr, sl, t0, t1 = oracle.traverse(rays_np, sc.boxes, reverse=True)
     assert ((sl & TAG) != 0).sum() > 20_000
-    _say("reverse traversal", rays_np.shape)
+    _say("reverse traversal", rays_np.shape, "mode", mode)
     off_g, segs = m.traverse(torch.from_numpy(rays_np).cuda(), int(off_o[-1]) + 16)
     torch.cuda.synchronize()
     assert np.array_equal(off_g.cpu().numpy().astype(np.uint64), off_o)
@@ -59,13 +61,15 @@ def test_traverse_reverse_bit_exact(lib, c1):
     assert np.array_equal(sg[:, 3].view(np.float32), t1)
 
 
-def test_first_hits_reverse_bit_exact(lib, c1):
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_first_hits_reverse_bit_exact(lib, c1, mode):
     sc, rays_np = c1
     m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="fp32", inside="reverse")
+    m.set_tuning(traverse_mode=mode)
     rng = np.random.default_rng(92)
     u = rng.uniform(size=rays_np.shape[0]).astype(np.float32)
     accept = rng.uniform(0.3, 1.0, size=sc.boxes.shape[0]).astype(np.float32)
-    _say("reverse first hits")
+    _say("reverse first hits, mode", mode)
     probes, leaf = m.first_hits(torch.from_numpy(rays_np).cuda(), torch.from_numpy(u).cuda(),
                                 torch.from_numpy(accept).cuda())
     rows, oleaf = oracle.first_hit_probes(rays_np, sc.boxes, u, accept, reverse=True)

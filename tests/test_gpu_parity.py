@@ -61,8 +61,12 @@ def _rel_inf(a, b):
 
 
 # ------------------------------------------------------------------ traversal
-def _check_traverse(lib, rays_np, boxes, sc_lo, sc_side, net):
+TRAVERSE_MODES = [0, 1, 2]  # per-lane walk, wave-coherent walk, chosen per wave
+
+
+def _check_traverse(lib, rays_np, boxes, sc_lo, sc_side, net, mode=2):
     m = lib.NBVH(net, boxes, sc_lo, sc_side, precision="fp32")
+    m.set_tuning(traverse_mode=mode)
     rays = torch.from_numpy(rays_np).cuda()
     off_o, sr, sl, t0, t1 = oracle.traverse(rays_np, boxes)
     cap = int(off_o[-1]) + 16
@@ -80,21 +84,23 @@ def _check_traverse(lib, rays_np, boxes, sc_lo, sc_side, net):
     return int(off_o[-1])
 
 
-def test_traverse_bitexact_c1(lib, c1):
+@pytest.mark.parametrize("mode", TRAVERSE_MODES)
+def test_traverse_bitexact_c1(lib, c1, mode):
     sc, rays = c1
-    _say("traverse c1: 65536 camera rays, 64 leaves")
-    n = _check_traverse(lib, rays, sc.boxes, sc.lo, sc.side, configs.C1_NET)
+    _say("traverse c1: 65536 camera rays, 64 leaves, mode", mode)
+    n = _check_traverse(lib, rays, sc.boxes, sc.lo, sc.side, configs.C1_NET, mode)
     assert n > 30000
 
 
-def test_traverse_tiny_scenes(lib):
+@pytest.mark.parametrize("mode", TRAVERSE_MODES)
+def test_traverse_tiny_scenes(lib, mode):
     rng = np.random.default_rng(5)
     net = configs.C1_NET
     # 1 leaf, 2 overlapping leaves, 7 leaves (ragged tree), with axis-aligned and grazing rays
     for boxes in (np.array([[0, 0, 0, 1, 1, 1]], np.float32),
                   np.array([[0, 0, 0, 1, 1, 1], [0.5, 0.25, 0.5, 1.5, 0.75, 2.0]], np.float32),
                   np.concatenate([rng.uniform(-1, 0, (7, 3)), rng.uniform(0.1, 1, (7, 3))], 1).astype(np.float32)):
-        _say("traverse tiny scene with", boxes.shape[0], "leaves")
+        _say("traverse tiny scene with", boxes.shape[0], "leaves, mode", mode)
         n = 3000
         rays = np.zeros((n, 8), np.float32)
         rays[:, 0:3] = rng.uniform(-3, 3, (n, 3))
@@ -110,10 +116,11 @@ def test_traverse_tiny_scenes(lib):
         g = rng.integers(0, n, 200)
         rays[g, 0:3] = boxes[0, [0, 4, 2]]
         rays[g, 4:7] = [1.0, 0.0, 0.0]
-        _check_traverse(lib, rays, boxes, boxes[:, :3].min(0), np.float32(4.0), net)
+        _check_traverse(lib, rays, boxes, boxes[:, :3].min(0), np.float32(4.0), net, mode)
 
 
-def test_traverse_many_overlapping_leaves(lib):
+@pytest.mark.parametrize("mode", TRAVERSE_MODES)
+def test_traverse_many_overlapping_leaves(lib, mode):
     """Rays crossing up to 40 leaves: longer runs than the counting pass
     keeps sorted per ray, so the fill walks the tree again for them."""
     rng = np.random.default_rng(6)
@@ -126,8 +133,8 @@ def test_traverse_many_overlapping_leaves(lib):
     d = -rays[:, 0:3] + rng.uniform(-0.3, 0.3, (n, 3))
     rays[:, 4:7] = d / np.linalg.norm(d, axis=1, keepdims=True)
     rays[:, 7] = np.inf
-    _say("traverse 40 overlapping leaves")
-    total = _check_traverse(lib, rays, boxes, boxes[:, :3].min(0), np.float32(4.0), configs.C1_NET)
+    _say("traverse 40 overlapping leaves, mode", mode)
+    total = _check_traverse(lib, rays, boxes, boxes[:, :3].min(0), np.float32(4.0), configs.C1_NET, mode)
     assert total > 20 * n
 
 

@@ -179,11 +179,13 @@ def frame():
     return sc, rays
 
 
-def test_traverse_bitexact_frame(lib, frame):
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_traverse_bitexact_frame(lib, frame, mode):
     sc, rays = frame
     m = lib.NBVH(configs.C2_NET, sc.boxes, sc.lo, sc.side, precision="fp32")
+    m.set_tuning(traverse_mode=mode)
     off_o, sr, sl, t0, t1 = oracle.traverse(rays, sc.boxes)
-    _say("traverse frame subset", rays.shape[0], "rays, 1024 leaves")
+    _say("traverse frame subset", rays.shape[0], "rays, 1024 leaves, mode", mode)
     off, segs = m.traverse(torch.from_numpy(rays).cuda(), int(off_o[-1]) + 16)
     off = off.cpu().numpy().astype(np.uint32).astype(np.uint64)
     sg = segs[: int(off_o[-1])].cpu().numpy()
@@ -192,6 +194,22 @@ def test_traverse_bitexact_frame(lib, frame):
     assert np.array_equal(sg[:, 2].view(np.float32), t0) and np.array_equal(sg[:, 3].view(np.float32), t1)
     counts = np.diff(off_o.astype(np.int64))
     assert counts.max() >= 4 and (counts > 0).mean() > 0.3
+
+
+def test_query_same_for_every_walk(lib, frame):
+    """How a wave walks the tree changes neither the segment queue nor the
+    query: the hit records are bit-identical for the three walk modes."""
+    sc, rays = frame
+    m = lib.NBVH(configs.C2_NET, sc.boxes, sc.lo, sc.side, precision="bf16")
+    m.set_params(_seeded(configs.C2_NET))
+    r = torch.from_numpy(rays).cuda()
+    out = []
+    for mode in (0, 1, 2):
+        _say("query frame subset, walk mode", mode)
+        m.set_tuning(traverse_mode=mode)
+        out.append(m.query(r).cpu().numpy().view(np.uint32))
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    assert (out[0][:, 7] != 0xFFFFFFFF).sum() > 1000
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
