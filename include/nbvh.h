@@ -324,10 +324,10 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_rays,
  * library-owned static device buffer of 64 MiB instead of a caller workspace.
  * Each GPU the library runs on holds its own copy until the process ends.
  * The workspace of a query is 12 bytes per ray for offsets, counts and the
- * active list, 144 bytes per ray of traversal staging, 16 bytes per segment
+ * active list, 192 bytes per ray of traversal staging, 16 bytes per segment
  * of capacity, plus a few hundred bytes of counters and scan partials,
  * each part rounded up to 256 bytes; a query needing more than 64 MiB returns
- * NBVH_ERR_CAPACITY before enqueuing anything (about 230,000 rays at 8
+ * NBVH_ERR_CAPACITY before enqueuing anything (about 200,000 rays at 8
  * segments of capacity per ray fit). The call allocates nothing. Every call
  * on one GPU shares that GPU's buffer, whatever the context: calls that may
  * overlap on one GPU (other streams, other host threads) race and must be

@@ -310,7 +310,7 @@ __device__ inline RayPre load_ray_or_none(const nbvh_ray* rays, uint32_t r, bool
 // `active` (wave-aggregated atomic). If `staging` is given, the first
 // kStage segments of ray r are also kept there, sorted, so that the
 // compaction after the scan need not walk the tree again.
-constexpr uint32_t kStage = 12;
+constexpr uint32_t kStage = 16;
 template <bool REV>
 __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
                                                         uint32_t n_rays, uint32_t* __restrict__ counts,
@@ -357,7 +357,13 @@ __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__
 }
 
 // Compaction from the staging runs: rays with more than kStage segments walk
-// the tree again and insert their segments into the queue directly.
+// the tree again and insert their segments into the queue directly. A wave
+// whose rays all have short runs copies them together: its runs are one
+// contiguous range of the queue, each lane records in LDS which (lane, run
+// record) fills each slot of the range, then the lanes take consecutive
+// slots, so the stores are coalesced and the wave waits on two or three
+// rounds of loads instead of its longest run's.
+constexpr uint32_t kWaveSlots = 64 * kStage;
 template <bool REV>
 __global__ __launch_bounds__(256) void k_traverse_compact(const Node* __restrict__ nodes,
                                                           const nbvh_ray* __restrict__ rays, uint32_t n_rays,
@@ -365,18 +371,35 @@ __global__ __launch_bounds__(256) void k_traverse_compact(const Node* __restrict
                                                           const float* __restrict__ staging,
                                                           nbvh_segment* __restrict__ segs, uint64_t capacity, int mode) {
   extern __shared__ int32_t s_stack[];
+  __shared__ uint16_t s_slot[4][kWaveSlots];
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if ((uint64_t)offsets[n_rays] > capacity) return;  // overflow flagged by the scan (uniform)
   const uint32_t beg = r < n_rays ? offsets[r] : 0u, end = r < n_rays ? offsets[r + 1] : 0u;
-  if (end > beg && end - beg <= kStage) {
+  const bool live = end - beg > kStage;
+  const size_t plane = n_rays;
+  if (__ballot(live) == 0ull) {
+    const uint32_t lane = threadIdx.x & 63u, r0 = r - lane;
+    if (r0 >= n_rays) return;  // the whole wave
+    const uint32_t wbeg = offsets[r0], wend = offsets[min(r0 + 64u, n_rays)];  // wend - wbeg <= kWaveSlots
+    uint16_t* slot = s_slot[threadIdx.x >> 6];
+    for (uint32_t i = 0; i < end - beg; ++i) slot[beg - wbeg + i] = (uint16_t)(lane | (i << 6));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t k = lane; k < wend - wbeg; k += 64u) {
+      const uint32_t e = slot[k], o = r0 + (e & 63u), i = e >> 6;
+      const float* run = staging + o;
+      segs[wbeg + k] = nbvh_segment{o, __float_as_uint(run[(3 * i) * plane]), run[(3 * i + 1) * plane],
+                                    run[(3 * i + 2) * plane]};
+    }
+    return;
+  }
+  if (end > beg && !live) {
     const float* run = staging + r;
-    const size_t plane = n_rays;
     for (uint32_t i = 0; i < end - beg; ++i)
       segs[beg + i] = nbvh_segment{r, __float_as_uint(run[(3 * i) * plane]), run[(3 * i + 1) * plane],
                                    run[(3 * i + 2) * plane]};
   }
-  const bool live = end - beg > kStage;
-  if (__ballot(live) == 0ull) return;  // no ray of the wave needs the walk
   const RayPre R = load_ray_or_none(rays, r, live);
   uint32_t k = beg;
   RunTail tail;

@@ -141,6 +141,13 @@ def _check_traced(lib, net, sc, rays, params, precision, inside="clip", trained=
             assert (lit > BF16_TOL).mean() <= 0.05, (lit > BF16_TOL).mean()
         ztol = BF16_TOL * np.maximum(1.0, np.maximum(np.abs(z_all), zscale[:, None]))
     clear = clear_rays(tr, z_all, out, rays[:, 3], ztol)
+    # rays with an evaluated segment whose hit or distance logit is off by
+    # more than its tolerance are not clear either: their answer may flip,
+    # and such logits are bounded above (none for FP32 and seeded BF16, a
+    # share for the trained BF16 network)
+    off_band = np.zeros(n_seg, bool)
+    off_band[np.flatnonzero(ev)] = (np.abs(zg - z_ref)[:, :2] > ztol[ev][:, :2]).any(1)
+    clear[np.unique(sr[off_band])] = False
     leaf = leaf_of(hits)
     oleaf = out[:, 4].astype(np.int64)
     agree_clear = float((leaf[clear] == oleaf[clear]).mean())
@@ -148,6 +155,7 @@ def _check_traced(lib, net, sc, rays, params, precision, inside="clip", trained=
     both = (leaf >= 0) & (leaf == oleaf)
     depth = np.abs(hits[both, 0] - out[both, 0]) / sc.diagonal
     summary = dict(rays=rays.shape[0], segments=n_seg, evaluated=int(ev.sum()), clear=float(clear.mean()),
+                   off_band_segments=int(off_band.sum()),
                    agree_clear=agree_clear, agree_all=agree_all, hits=int((oleaf >= 0).sum()),
                    depth_mean=float(depth.mean()) if both.any() else 0.0, max_dz=float(np.abs(zg - z_ref).max()))
     _say(summary)
