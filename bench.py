@@ -81,6 +81,7 @@ def hit_error(hits, gt, diag):
 class Workload:
     """Inputs of one benchmark workload (all host arrays, seeded)."""
     inside_probes = None  # "surface": inside-starting training probes start on the surface
+    tuning = {}  # launch knobs the caller of this workload sets (nbvh_tuning fields)
 
 
 def parity(torch, m, rays_np, sc, net, params, precision, inside, what):
@@ -221,6 +222,10 @@ def build_secondary(configs, scene, inside="reverse", offset=1e-4, bounce_from="
                   + how)
     W.parity_stride = 4  # every 256th bounce ray
     W.cpu_sample = lambda stride: (W.rays[::stride * stride * 16].copy(), "every %dth ray" % (stride * stride * 16))
+    # the rays come in 24 passes over the primary hits (one bounce per hit and
+    # pass): rays leaving one point are 690,000 places apart, so the caller asks
+    # the library to evaluate them in the order of their origins
+    W.tuning = {"query_order": 1}
     return W
 
 
@@ -324,6 +329,8 @@ def run_single(args, W, P, torch, configs, scene):
 
     bf = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", loss_scale=1024.0, inside=W.inside)
     bf.set_params(W.params0)
+    default_tuning = bf.get_tuning()
+    bf.set_tuning(**W.tuning)
     bf.workspace(R, seg_cap, B)
     # levels of detail (Sec. 5.3): a coarser cut of the same median-split
     # hierarchy over the same network, trained on a randomly chosen cut per step
@@ -380,6 +387,17 @@ def run_single(args, W, P, torch, configs, scene):
     time_loop = timer(torch)
     q_ms = time_loop(lambda i: bf.query(rays, seg_cap, hits_bf), args.steps)
     t_ms = time_loop(lambda i: bf.train_step(*batches[i % len(batches)]), args.steps)
+    q_ms_default = None
+    if W.tuning:
+        # the same query with the library's default knobs, for comparison
+        bf.set_tuning(**{k: default_tuning[k] for k in W.tuning})
+        bf.workspace(R, seg_cap, B)
+        bf.query(rays, seg_cap, hits_bf)
+        q_ms_default = time_loop(lambda i: bf.query(rays, seg_cap, hits_bf), args.steps)
+        bf.set_tuning(**W.tuning)
+        bf.workspace(R, seg_cap, B)
+        bf.query(rays, seg_cap, hits_bf)
+        log("query with the default knobs: %.3f ms (with %s: %.3f ms)" % (q_ms_default, W.tuning, q_ms))
     # per-kernel-group device time (HIP events on the launch stream)
     bf.profile_begin()
     run_steps(bf, args.steps)
@@ -397,6 +415,7 @@ def run_single(args, W, P, torch, configs, scene):
     if not args.no_fp32:
         fp = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp32", loss_scale=1024.0, inside=W.inside)
         fp.set_params(trained)
+        fp.set_tuning(**W.tuning)
         fp.workspace(R, seg_cap, B)
         hits_fp = torch.empty((R, 8), dtype=torch.float32, device="cuda")
         fp.query(rays, seg_cap, hits_fp)
@@ -415,6 +434,7 @@ def run_single(args, W, P, torch, configs, scene):
     if not args.no_fp8:
         f8 = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="fp8", inside=W.inside)
         f8.set_params(trained)
+        f8.set_tuning(**W.tuning)
         f8.calibrate_fp8(batches[0][0][: 1 << 16].contiguous())
         f8.workspace(R, seg_cap, 0)
         hits_f8 = torch.empty((R, 8), dtype=torch.float32, device="cuda")
@@ -515,8 +535,10 @@ def run_single(args, W, P, torch, configs, scene):
                                       "random cut per step" % args.lod if args.lod else ""),
             "rays": R, "segments": int(n_segments), "segments_evaluated": int(evaluated), "train_batch": B,
             "step": "one full query + one training step (forward, loss, backward, Adam)",
+            **({"tuning": W.tuning} if W.tuning else {}),
         },
         "query_ms": q_ms,
+        **({"query_ms_default_knobs": q_ms_default} if q_ms_default is not None else {}),
         "train_ms": t_ms,
         "segments_per_s": evaluated / (q_ms * 1e-3),
         "train_segs_per_s": B / (t_ms * 1e-3),
@@ -552,7 +574,8 @@ def against_ceilings(roofline, peaks, net, evaluated, B, table_bytes):
       query_eval / train_tile: table gathers (entry = F x 2 B, one per lane, 8
         lines per wave: rays of a workgroup are neighbours) against the gather
         loop on a table of the same size class;
-      scatter: FP32 read-modify-writes against the scattered FP32 atomic loop;
+      scatter: FP32 adds against the LDS 64-bit integer atomic loop (the hash
+        route sums a tile's gradients in LDS before its few global atomics);
       scatter_reduce, wgrad, optimizer, traverse: bytes against the streaming
         read of a 1 GiB (HBM) buffer;
       MLP FLOPs (2 per weight and segment forward; forward and input-gradient
@@ -577,9 +600,11 @@ def against_ceilings(roofline, peaks, net, evaluated, B, table_bytes):
             r["mlp"] = dict(tflops=round(tf, 2), frac_peak=round(tf / BF16_PEAK_TFLOPS, 4),
                             ceiling_tflops=round(mf, 1), frac_ceiling=round(tf / mf, 4))
         elif k == "scatter":
+            # the hash route sums each tile's corner gradients with LDS integer
+            # atomics before few global ones: priced against the LDS loop
             rate = r["algorithmic"] / 4 / (r["avg_ms"] * 1e-3) / 1e9
-            c = peaks["atomic_f32_32MiB_run1"]["gadds_per_s"]
-            r["ceiling"] = dict(name="atomic_f32_32MiB_run1", gadds_per_s=round(c, 2))
+            c = peaks["lds_atomic_u64"]["gadds_per_s"]
+            r["ceiling"] = dict(name="lds_atomic_u64", gadds_per_s=round(c, 2))
             r["frac_ceiling"] = round(rate / c, 4)
         elif r["unit"] == "GB/s":
             r["ceiling"] = dict(name="stream_1024MiB", gbs=round(hbm, 1))

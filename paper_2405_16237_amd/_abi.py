@@ -57,7 +57,7 @@ class NbvhTuning(ctypes.Structure):
                 ("train_waves", ctypes.c_int32), ("wgrad_splits", ctypes.c_int32), ("scatter_lds_kb", ctypes.c_int32),
                 ("scatter_binned", ctypes.c_int32), ("scatter_hash_levels", ctypes.c_int32),
                 ("query_pairs", ctypes.c_int32), ("query_lds_kb", ctypes.c_int32),
-                ("traverse_mode", ctypes.c_int32)]
+                ("traverse_mode", ctypes.c_int32), ("query_order", ctypes.c_int32)]
 
 
 class NbvhQueryTrace(ctypes.Structure):

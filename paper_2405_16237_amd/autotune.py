@@ -4,7 +4,7 @@ Times candidate knob settings (nbvh_tuning) on the caller's own workload with
 HIP events and keeps the fastest. The search runs in stages, each a grid over
 a few knobs with the best of the earlier stages applied: for the query, waves
 per workgroup x gather unroll x pair loads, then persistent workgroups per CU
-x coarse levels in LDS, then how waves walk the tree;
+x coarse levels in LDS, then how waves walk the tree x the order rays are evaluated in;
 for back-propagation, training-tile waves x weight-gradient splits, then the
 scatter's LDS budget x hash-aggregated levels x binning. Results can be
 cached in a JSON file keyed by the workload signature.
@@ -19,7 +19,7 @@ import torch
 
 QUERY_STAGES = [dict(query_waves=(4, 8), query_unroll=(2, 3, 4), query_pairs=(0, 1)),
                 dict(query_wgs_per_cu=(0, 1, 2), query_lds_kb=(0, 24, 64)),
-                dict(traverse_mode=(0, 1, 2))]
+                dict(traverse_mode=(0, 1, 2), query_order=(0, 1))]
 TRAIN_STAGES = [dict(train_waves=(4, 8), wgrad_splits=(16, 32, 64)),
                 dict(scatter_lds_kb=(0, 144), scatter_hash_levels=(0, 4, 8, 12), scatter_binned=(0, 1))]
 

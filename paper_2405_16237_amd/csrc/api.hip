@@ -242,12 +242,13 @@ static LaunchCtx make_launch(const nbvh_ctx* ctx, void* stream) {
 
 // query workspace carve-up
 struct QueryLayout {
-  size_t offsets, counts, active, sums, misc, staging, segs, total;
+  size_t offsets, counts, active, sums, misc, staging, segs, order, total;
 };
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static QueryLayout query_layout(uint64_t n_rays, uint64_t cap) {
+// `ordered`: room for sorting the active rays by origin (tuning query_order)
+static QueryLayout query_layout(uint64_t n_rays, uint64_t cap, bool ordered = false) {
   QueryLayout Q;
   size_t off = 0;
   Q.offsets = off;
@@ -264,6 +265,8 @@ static QueryLayout query_layout(uint64_t n_rays, uint64_t cap) {
   off = a256(off + traverse_staging_bytes(n_rays));
   Q.segs = off;
   off = a256(off + cap * sizeof(nbvh_segment));
+  Q.order = off;
+  if (ordered) off = a256(off + group_ws_bytes(n_rays));
   Q.total = off;
   return Q;
 }
@@ -396,7 +399,7 @@ nbvh_status nbvh_build(const nbvh_config* cfg, const float* leaf_boxes_host, uin
   hipDeviceProp_t prop;
   ctx->n_cu = (hipGetDeviceProperties(&prop, dev) == hipSuccess) ? prop.multiProcessorCount : 256;
   if (ctx->n_cu <= 0) ctx->n_cu = 256;
-  ctx->tune = nbvh_tuning{8, 0, 0, 8, 64, 0, 1, 8, 0, 0, 2};
+  ctx->tune = nbvh_tuning{8, 0, 0, 8, 64, 0, 1, 8, 0, 0, 2, 0};
   void* sp = nullptr;
   s = scratch_for_current_device(&sp);  // set-up of the no-allocation query on this device
   if (s != NBVH_OK) {
@@ -457,7 +460,7 @@ nbvh_status nbvh_calibrate_fp8(nbvh_ctx* ctx, const nbvh_probe* probes, uint64_t
 
 size_t nbvh_workspace_bytes(const nbvh_ctx* ctx, uint64_t max_rays, uint64_t max_segments, uint64_t max_batch) {
   if (!ctx) return 0;
-  size_t q = query_layout(max_rays, max_segments).total;
+  size_t q = query_layout(max_rays, max_segments, ctx->tune.query_order != 0).total;
   const int prec = ctx->cfg.precision == NBVH_FP8 ? NBVH_BF16 : ctx->cfg.precision;
   size_t t = train_ws_bytes(ctx->dev, prec, max_batch, ctx->tune);
   size_t l = std::max(a256((max_batch / 256 + 2) * 16), group_ws_bytes(max_batch));
@@ -489,7 +492,8 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbv
   if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
   if ((n_rays && (!rays || !hits)) || !ws) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
   if (seg_capacity > 0xffffffffull) seg_capacity = 0xffffffffull;
-  const QueryLayout Q = query_layout(n_rays, seg_capacity);
+  const bool ordered = ctx->tune.query_order != 0;
+  const QueryLayout Q = query_layout(n_rays, seg_capacity, ordered);
   if (ws_bytes < Q.total) return set_error("workspace too small: need %zu, got %zu", Q.total, ws_bytes), NBVH_ERR_CAPACITY;
   if (n_rays == 0) return NBVH_OK;
   LaunchCtx L = make_launch(ctx, stream);
@@ -498,7 +502,8 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbv
   uint32_t* misc = (uint32_t*)(w + Q.misc);
   nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
   s = launch_traverse(L, rays, (uint32_t)n_rays, offsets, segs, seg_capacity, hits, (uint32_t*)(w + Q.active), misc + 0,
-                      (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12, (float*)(w + Q.staging));
+                      (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12, (float*)(w + Q.staging),
+                      ordered ? w + Q.order : nullptr);
   if (s != NBVH_OK) return s;
   return launch_query_eval(L, rays, offsets, segs, (const uint32_t*)(w + Q.active), misc + 0, misc + 1, hits,
                            (uint32_t)n_rays, seg_capacity);
@@ -510,7 +515,7 @@ nbvh_status nbvh_query_noalloc(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_r
   if (s != NBVH_OK) return s;
   if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
   if (seg_capacity > 0xffffffffull) seg_capacity = 0xffffffffull;
-  const size_t need = query_layout(n_rays, seg_capacity).total;
+  const size_t need = query_layout(n_rays, seg_capacity, ctx->tune.query_order != 0).total;
   if (need > kNoAllocBytes)
     return set_error("query of %llu rays with %llu segments needs %zu bytes of scratch; the no-allocation query "
                      "holds %zu",
@@ -535,7 +540,8 @@ nbvh_status nbvh_query_traced(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_ra
   if (n_rays > 0xfffffff0ull) return set_error("too many rays"), NBVH_ERR_UNSUPPORTED;
   if ((n_rays && (!rays || !hits)) || !ws) return set_error("NULL buffer"), NBVH_ERR_INVALID_ARG;
   if (seg_capacity > 0xffffffffull) seg_capacity = 0xffffffffull;
-  const QueryLayout Q = query_layout(n_rays, seg_capacity);
+  const bool ordered = ctx->tune.query_order != 0;
+  const QueryLayout Q = query_layout(n_rays, seg_capacity, ordered);
   if (ws_bytes < Q.total) return set_error("workspace too small: need %zu, got %zu", Q.total, ws_bytes), NBVH_ERR_CAPACITY;
   if (n_rays == 0) return NBVH_OK;
   LaunchCtx L = make_launch(ctx, stream);
@@ -544,7 +550,8 @@ nbvh_status nbvh_query_traced(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_ra
   uint32_t* misc = (uint32_t*)(w + Q.misc);
   nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
   s = launch_traverse(L, rays, (uint32_t)n_rays, offsets, segs, seg_capacity, hits, (uint32_t*)(w + Q.active), misc + 0,
-                      (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12, (float*)(w + Q.staging));
+                      (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12, (float*)(w + Q.staging),
+                      ordered ? w + Q.order : nullptr);
   if (s != NBVH_OK) return s;
   if (trace->seg_offsets_dev &&
       hipMemcpyAsync(trace->seg_offsets_dev, offsets, (n_rays + 1) * 4, hipMemcpyDeviceToDevice, L.stream) != hipSuccess)
@@ -802,6 +809,7 @@ nbvh_status nbvh_set_tuning(nbvh_ctx* ctx, const nbvh_tuning* t) {
   if (t->query_pairs != 0 && t->query_pairs != 1) return set_error("query_pairs must be 0 or 1"), NBVH_ERR_INVALID_ARG;
   if (t->query_lds_kb < 0 || t->query_lds_kb > 64) return set_error("query_lds_kb in 0..64"), NBVH_ERR_INVALID_ARG;
   if (t->traverse_mode < 0 || t->traverse_mode > 2) return set_error("traverse_mode must be 0, 1 or 2"), NBVH_ERR_INVALID_ARG;
+  if (t->query_order != 0 && t->query_order != 1) return set_error("query_order must be 0 or 1"), NBVH_ERR_INVALID_ARG;
   ctx->tune = *t;
   return NBVH_OK;
 }

@@ -692,10 +692,80 @@ nbvh_status launch_exclusive_scan(hipStream_t s, const uint32_t* in, uint32_t n,
 
 size_t traverse_staging_bytes(uint64_t n_rays) { return (size_t)n_rays * kStage * 3 * sizeof(float); }
 
+// Sort keys of the active rays: the Morton code of the origin's cell on a
+// 256^3 grid over the hash-grid cube (clamped); entries past n_active get the
+// largest key, so a stable sort keeps them behind every active ray.
+__device__ inline uint32_t spread8(uint32_t v) {
+  v = (v | (v << 8)) & 0x00F00Fu;
+  v = (v | (v << 4)) & 0x0C30C3u;
+  v = (v | (v << 2)) & 0x249249u;
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_order_keys(const nbvh_ray* __restrict__ rays, const uint32_t* __restrict__ active,
+                                                    const uint32_t* __restrict__ n_active, uint32_t n, DevCfg c,
+                                                    uint32_t* __restrict__ keys) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  uint32_t key = 0xFFFFFFFFu;
+  if (i < *n_active) {
+    const float4 o = *(const float4*)(rays + active[i]);
+    const float p[3] = {o.x, o.y, o.z};
+    key = 0u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float x = (p[a] - c.scene_lo[a]) * c.inv_side * 256.0f;
+      const uint32_t q = x > 0.0f ? (uint32_t)fminf(x, 255.0f) : 0u;  // NaN -> 0
+      key |= spread8(q) << a;
+    }
+  }
+  keys[i] = key;
+}
+
+// Reorders active[0, n_active) by origin key (6 passes of the 4-bit stable
+// radix sort that groups training probes by leaf; the last pass writes the
+// ray ids back into `active`).
+static nbvh_status order_active(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n, uint32_t* active,
+                                const uint32_t* n_active, void* ws) {
+  const uint32_t nb = (n + 255) / 256, cells = nb * kGroupDigits;
+  char* w = (char*)ws;
+  uint32_t* kbuf[2];
+  uint32_t* vbuf[2];
+  size_t off = 0;
+  for (int j = 0; j < 2; ++j) {
+    kbuf[j] = (uint32_t*)(w + off);
+    off += group_a256((size_t)n * 4);
+    vbuf[j] = (uint32_t*)(w + off);
+    off += group_a256((size_t)n * 4);
+  }
+  uint32_t* counts = (uint32_t*)(w + off);
+  off += group_a256(((size_t)cells + 1) * 4);
+  uint32_t* offs = (uint32_t*)(w + off);
+  off += group_a256(((size_t)cells + 1) * 4);
+  uint32_t* sums = (uint32_t*)(w + off);
+  off += group_a256(((size_t)cells / kScanTile + 2) * 4);
+  uint32_t* total = (uint32_t*)(w + off);
+  k_order_keys<<<nb, 256, 0, L.stream>>>(rays, active, n_active, n, L.cfg, kbuf[1]);
+  constexpr int kPasses = 6;  // 24-bit keys
+  const uint32_t* kin = kbuf[1];
+  const uint32_t* vin = active;
+  for (int p = 0; p < kPasses; ++p) {
+    uint32_t* kout = kbuf[p & 1];
+    uint32_t* vout = p == kPasses - 1 ? active : vbuf[p & 1];
+    k_group_count<<<nb, 256, 0, L.stream>>>(kin, n, 4 * p, counts);
+    nbvh_status s = launch_exclusive_scan(L.stream, counts, cells, offs, sums, total);
+    if (s != NBVH_OK) return s;
+    k_group_scatter<<<nb, 256, 0, L.stream>>>(kin, vin, n, 4 * p, offs, kout, vout);
+    kin = kout;
+    vin = vout;
+  }
+  return NBVH_OK;
+}
+
 nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n_rays, uint32_t* offsets,
                             nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
                             uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
-                            uint32_t* scratch_total, float* staging) {
+                            uint32_t* scratch_total, float* staging, void* order_ws) {
   if (segs && !staging) return set_error("traversal staging buffer missing"), NBVH_ERR_INVALID_ARG;
   ProfScope ps(L.prof, NBVH_K_TRAVERSE, L.stream);
   const int grid = (int)((n_rays + 255) / 256);
@@ -706,6 +776,10 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
     (L.cfg.inside_reverse ? k_traverse_count<true> : k_traverse_count<false>)<<<grid, 256, stack_lds(L), L.stream>>>(
         L.nodes, rays, n_rays, scratch_counts, hits, active, n_active, segs ? staging : nullptr,
         L.tune.traverse_mode);
+  if (order_ws && active && n_active && n_rays > 0) {
+    nbvh_status s = order_active(L, rays, n_rays, active, n_active, order_ws);
+    if (s != NBVH_OK) return s;
+  }
   const uint32_t n_tiles = (n_rays + kScanTile - 1) / kScanTile;
   if (n_rays > 0) k_scan_tiles<<<n_tiles, 256, 0, L.stream>>>(scratch_counts, n_rays, offsets, scratch_sums);
   k_scan_sums<<<1, 1024, 0, L.stream>>>(scratch_sums, n_tiles, scratch_total);

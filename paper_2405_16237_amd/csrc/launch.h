@@ -79,12 +79,13 @@ __global__ void k_zero_f32(float* p, uint64_t n);
 
 // `staging` (traverse_staging_bytes(n_rays), required with `segs`): sorted
 // per-ray runs kept by the counting pass so that the compaction copies them
-// instead of walking again.
+// instead of walking again. `order_ws` (nullable, group_ws_bytes(n_rays)):
+// with an active list, reorder it by the Morton code of the rays' origins.
 size_t traverse_staging_bytes(uint64_t n_rays);
 nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n_rays, uint32_t* offsets,
                             nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
                             uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
-                            uint32_t* scratch_total, float* staging);
+                            uint32_t* scratch_total, float* staging, void* order_ws = nullptr);
 
 // z_trace / u_trace (nullable): each evaluated segment's logits [cap][n_out]
 // and FP32 copy of its LDS feature row [cap][n_in] (not in FP8), at the

@@ -226,13 +226,14 @@ def test_autotuner_keeps_results(objects):
     probes = torch.from_numpy(p).cuda()
     _say("autotune")
     rep = autotune.autotune(m, rays=rays, probes=probes, reps=1)
-    assert len(rep["query"]) == 12 + 9 + 3 and len(rep["train"]) == 6 + 16
+    assert len(rep["query"]) == 12 + 9 + 6 and len(rep["train"]) == 6 + 16
     assert m.get_tuning() == rep["tuning"]
     for knobs in ({"query_waves": 4, "query_unroll": 2, "query_wgs_per_cu": 1, "query_pairs": 1},
                   {"query_waves": 8, "query_unroll": 4, "query_pairs": 0}, {"query_waves": 8, "query_unroll": 3, "query_pairs": 1},
                   {"query_waves": 8, "query_unroll": 2, "query_pairs": 0, "query_lds_kb": 24},
                   {"query_waves": 4, "query_unroll": 3, "query_pairs": 0, "query_lds_kb": 64},
-                  {"query_lds_kb": 0, "traverse_mode": 0}, {"traverse_mode": 1}):
+                  {"query_lds_kb": 0, "traverse_mode": 0}, {"traverse_mode": 1},
+                  {"traverse_mode": 2, "query_order": 1}):
         m.set_tuning(**knobs)
         got = m.query(rays).view(torch.int32)
         assert torch.equal(got, ref), knobs

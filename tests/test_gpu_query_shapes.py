@@ -205,18 +205,21 @@ def test_traverse_bitexact_frame(lib, frame, mode):
 
 
 def test_query_same_for_every_walk(lib, frame):
-    """How a wave walks the tree changes neither the segment queue nor the
-    query: the hit records are bit-identical for the three walk modes."""
+    """How a wave walks the tree and the order the rays are evaluated in
+    change neither the segment queue nor the query: the hit records are
+    bit-identical for the three walk modes, with and without origin order."""
     sc, rays = frame
     m = lib.NBVH(configs.C2_NET, sc.boxes, sc.lo, sc.side, precision="bf16")
     m.set_params(_seeded(configs.C2_NET))
     r = torch.from_numpy(rays).cuda()
     out = []
     for mode in (0, 1, 2):
-        _say("query frame subset, walk mode", mode)
-        m.set_tuning(traverse_mode=mode)
-        out.append(m.query(r).cpu().numpy().view(np.uint32))
-    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+        for order in (0, 1):
+            _say("query frame subset, walk mode", mode, "origin order", order)
+            m.set_tuning(traverse_mode=mode, query_order=order)
+            out.append(m.query(r).cpu().numpy().view(np.uint32))
+    for o in out[1:]:
+        assert np.array_equal(out[0], o)
     assert (out[0][:, 7] != 0xFFFFFFFF).sum() > 1000
 
 
@@ -272,3 +275,19 @@ def test_query_bounce_reverse(lib, bounce, precision):
     net = configs.C5_NET
     s = _check_traced(lib, net, sc, rays, _seeded(net), precision, inside="reverse")
     assert s["clear"] > 0.3 and s["segments"] > rays.shape[0]
+
+
+def test_bounce_query_same_in_origin_order(lib, bounce):
+    """Evaluating the bounce rays in the order of their origins' Morton codes
+    (query_order = 1) gives the same hit records bit for bit."""
+    sc, rays = bounce
+    net = configs.C5_NET
+    m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", inside="reverse")
+    m.set_params(_seeded(net))
+    r = torch.from_numpy(rays).cuda()
+    _say("bounce query in the caller's order and in origin order")
+    a = m.query(r).cpu().numpy().view(np.uint32)
+    m.set_tuning(query_order=1)
+    b = m.query(r).cpu().numpy().view(np.uint32)
+    assert np.array_equal(a, b)
+    assert (a[:, 7] != 0xFFFFFFFF).sum() > 1000
