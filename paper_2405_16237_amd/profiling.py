@@ -193,6 +193,13 @@ def write_counters(path: str, dirs: list, commands: list, n_cu: int = 256):
                           "TCP_PENDING_STALL_CYCLES_sum"):
                     if c in cs:
                         f.write("%s per compute unit: %.2f of the kernel's cycles\n" % (c, cs[c][1] / n_cu / cyc))
+                # a compute unit issues at most one 64-lane VALU instruction per
+                # cycle (4 SIMDs, 4 cycles each); MFMA busy cycles count per SIMD
+                if "SQ_INSTS_VALU" in cs:
+                    f.write("VALU instructions per compute unit and cycle: %.2f\n" % (cs["SQ_INSTS_VALU"][1] / n_cu / cyc))
+                if "SQ_VALU_MFMA_BUSY_CYCLES" in cs:
+                    f.write("matrix cores busy (SQ_VALU_MFMA_BUSY_CYCLES / (4 SIMDs x compute units x cycles)): %.3f\n"
+                            % (cs["SQ_VALU_MFMA_BUSY_CYCLES"][1] / (4 * n_cu * cyc)))
             if "TCP_TOTAL_CACHE_ACCESSES_sum" in cs and "TCP_TCC_READ_REQ_sum" in cs:
                 f.write("L1 miss fraction (TCP_TCC_READ_REQ / TCP_TOTAL_CACHE_ACCESSES): %.3f\n"
                         % (cs["TCP_TCC_READ_REQ_sum"][1] / cs["TCP_TOTAL_CACHE_ACCESSES_sum"][1]))
