@@ -1,7 +1,8 @@
 """The no-allocation query (nbvh_query_noalloc, workspace in a library-owned
 static device buffer) against nbvh_query with a caller workspace: the same
 kernels, so the hit records are bit-identical; two calls in a row, the second
-smaller, and a query too large for the buffer refused before any launch."""
+smaller, a query too large for the buffer refused before any launch, and a
+query in origin order (whose sort also lives in the buffer)."""
 import ctypes
 import sys
 
@@ -56,3 +57,14 @@ def test_query_noalloc_matches_query():
     assert "64" in lib.nbvh_last_error().decode() or "scratch" in lib.nbvh_last_error().decode()
     torch.cuda.synchronize()
     assert float(out.min()) == 7.0 and float(out.max()) == 7.0
+    # with the rays evaluated in origin order the scratch also holds the sort
+    m.set_tuning(query_order=1)
+    n = 20011
+    rays = torch.from_numpy(rays_all[:n].copy()).cuda()
+    _say("no-allocation query in origin order:", n, "rays")
+    ref = m.query(rays, 8 * n + 1024).cpu().numpy()
+    got = torch.full((n, 8), float("nan"), device="cuda")
+    st = lib.nbvh_query_noalloc(m.ctx, ctypes.c_void_p(rays.data_ptr()), n, ctypes.c_void_p(got.data_ptr()),
+                                8 * n + 1024, stream)
+    assert st == _abi.NBVH_OK, lib.nbvh_last_error().decode()
+    assert np.array_equal(got.cpu().numpy().view(np.uint32), ref.view(np.uint32))
