@@ -24,6 +24,10 @@ struct nbvh_ctx {
   nbvh_tuning tune;
   bool fp8_ready;  // FP8 weights and scales in aux match the current parameters
   int tree_depth;  // inner levels of the N-BVH (traversal stack entries)
+  // a second stream of the context: the training step's weight-gradient GEMMs
+  // run on it beside the table-gradient scatter (fork and join by events)
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_join;
 };
 
 namespace nbvh {
@@ -213,6 +217,9 @@ static LaunchCtx make_launch(const nbvh_ctx* ctx, void* stream) {
   LaunchCtx L;
   memset(&L, 0, sizeof(L));
   L.stream = (hipStream_t)stream;
+  L.side = ctx->side;
+  L.ev_fork = ctx->ev_fork;
+  L.ev_join = ctx->ev_join;
   L.nodes = ctx->nodes;
   L.state = (DevState*)ctx->p.state_dev;
   L.cfg = ctx->dev;
@@ -400,10 +407,17 @@ nbvh_status nbvh_build(const nbvh_config* cfg, const float* leaf_boxes_host, uin
   ctx->n_cu = (hipGetDeviceProperties(&prop, dev) == hipSuccess) ? prop.multiProcessorCount : 256;
   if (ctx->n_cu <= 0) ctx->n_cu = 256;
   ctx->tune = nbvh_tuning{8, 0, 0, 8, 64, 0, 1, 8, 0, 0, 2, 0};
+  if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+    set_error("creating the context's stream and events failed");
+    nbvh_destroy(ctx);
+    return NBVH_ERR_HIP;
+  }
   void* sp = nullptr;
   s = scratch_for_current_device(&sp);  // set-up of the no-allocation query on this device
   if (s != NBVH_OK) {
-    delete ctx;
+    nbvh_destroy(ctx);
     return s;
   }
   *out = ctx;
@@ -936,6 +950,12 @@ void nbvh_destroy(nbvh_ctx* ctx) {
     for (auto& e : ctx->prof->ev) hipEventDestroy(e);
     delete ctx->prof;
   }
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   delete ctx;
 }
 

@@ -1457,23 +1457,41 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
     }
 #undef NBVH_TT
   }
+  // The weight gradients (loss, thin GEMMs over the batch, fixed-order split
+  // reduction: HBM streaming and matrix cores) and the table gradient (LDS
+  // atomics and scattered record stores) depend only on the tile's outputs and
+  // write disjoint parts of the gradient, so the first runs on the context's
+  // second stream beside the second; the step joins both before returning.
+  // Not while the caller's stream is being captured into a graph: there the
+  // step stays on that one stream.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(L.stream, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
+  const bool fork = L.side && L.ev_fork && L.ev_join && cap == hipStreamCaptureStatusNone;
+  hipStream_t gs = L.stream;
+  if (fork) {
+    if (hipEventRecord(L.ev_fork, L.stream) != hipSuccess || hipStreamWaitEvent(L.side, L.ev_fork, 0) != hipSuccess)
+      return set_error("forking the weight-gradient stream failed"), NBVH_ERR_HIP;
+    gs = L.side;
+  }
   {
-    ProfScope ps(L.prof, NBVH_K_WGRAD, L.stream);
+    ProfScope ps(L.prof, NBVH_K_WGRAD, gs);
     if (labels)
-      k_loss_finalize<<<1, 256, 0, L.stream>>>(P.loss_part, T.n_tiles, n, L.w_hit, L.w_t, L.w_normal, L.w_albedo,
-                                               loss_dev, L.state);
+      k_loss_finalize<<<1, 256, 0, gs>>>(P.loss_part, T.n_tiles, n, L.w_hit, L.w_t, L.w_normal, L.w_albedo, loss_dev,
+                                         L.state);
     float* wpart = (float*)(w + T.wpart);
     if constexpr (sizeof(AT) == 2) {
       const WSlices slices = make_slices(c);
-      k_wgrad_rows<<<dim3(slices.n, T.nsplit), 512, 0, L.stream>>>(c, slices, P, kb, T.nsplit, wpart);
+      k_wgrad_rows<<<dim3(slices.n, T.nsplit), 512, 0, gs>>>(c, slices, P, kb, T.nsplit, wpart);
     } else {
       const WTiles tiles = make_tiles(c);
-      k_wgrad<AT><<<dim3(tiles.n, T.nsplit), 256, 0, L.stream>>>(c, tiles, P, kb, T.nsplit, wpart);
+      k_wgrad<AT><<<dim3(tiles.n, T.nsplit), 256, 0, gs>>>(c, tiles, P, kb, T.nsplit, wpart);
     }
     const uint64_t span = c.n_params - c.w_off[0];
-    k_wgrad_reduce<<<(uint32_t)((4 * span + 255) / 256), 256, 0, L.stream>>>(c, wpart, T.nsplit, L.grad, L.state);
+    k_wgrad_reduce<<<(uint32_t)((4 * span + 255) / 256), 256, 0, gs>>>(c, wpart, T.nsplit, L.grad, L.state);
   }
   nbvh_status s = launch_scatter<F>(L, T, w, probes, n, P.duT, kb, P.gmax);
+  if (fork && (hipEventRecord(L.ev_join, L.side) != hipSuccess || hipStreamWaitEvent(L.stream, L.ev_join, 0) != hipSuccess))
+    return set_error("joining the weight-gradient stream failed"), NBVH_ERR_HIP;
   if (s != NBVH_OK) return s;
   return check_launch("train");
 }

@@ -51,6 +51,8 @@ struct DevState {
 
 struct LaunchCtx {
   hipStream_t stream;
+  hipStream_t side;                // the context's second stream (nullable)
+  hipEvent_t ev_fork, ev_join;     // fork to and join from `side`
   const Node* nodes;
   DevState* state;
   DevCfg cfg;
