@@ -707,6 +707,11 @@ def run_batched(args, P, torch, configs, scene):
         m.workspace(0, 0, batches[k][0].shape[0])
         models.append(m)
     batch = P.NBVHBatch(models)
+    # rays from a sphere around the scene towards random points of its box are
+    # incoherent: the caller asks for them to be evaluated in the order of
+    # their origins and directions (grouped queries take the first object's)
+    tuning = {"query_order": 2}
+    models[0].set_tuning(**tuning)
     hits = torch.empty((R, 8), dtype=torch.float32, device="cuda")
     for i in range(args.pretrain):
         for m, (p, l) in zip(models, batches):
@@ -740,6 +745,13 @@ def run_batched(args, P, torch, configs, scene):
     step_ms = time_loop(step, args.steps)
     q_ms = time_loop(lambda i: batch.query(rays, seg_cap, hits), args.steps)
     t_ms = time_loop(lambda i: g.replay(), args.steps)
+    # the same query in the caller's order, for comparison
+    models[0].set_tuning(query_order=0)
+    batch.query(rays, seg_cap, hits)
+    q_ms_default = time_loop(lambda i: batch.query(rays, seg_cap, hits), args.steps)
+    models[0].set_tuning(**tuning)
+    batch.query(rays, seg_cap, hits)
+    log("grouped query in the caller's order: %.3f ms (with %s: %.3f ms)" % (q_ms_default, tuning, q_ms))
     # per-kernel-group device time over eager steps (the grouped query is
     # recorded by the first object's context, each training step by its own)
     ev0 = [m.read_state()["n_evaluated"] for m in models]
@@ -827,8 +839,10 @@ def run_batched(args, P, torch, configs, scene):
                                             "one parallel branch per object"),
             "rays": R, "objects": len(objs), "train_batch": nb,
             "step": "one grouped query + one graph-captured training step of every object",
+            "tuning": tuning,
         },
         "query_ms": q_ms,
+        "query_ms_default_knobs": q_ms_default,
         "train_ms": t_ms,
         "segments_per_s": evaluated / (q_ms * 1e-3),
         "train_segs_per_s": nb / (t_ms * 1e-3),

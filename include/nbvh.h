@@ -220,13 +220,16 @@ typedef struct {
                                1 = the wave together over the union of its rays' nodes (one node load
                                per wave), 2 = the wave together when its rays are coherent (directions
                                and origins close), else each lane alone (2) */
-  int32_t query_order;      /* 1 = evaluate the rays in the order of the Morton code of their origins
-                               (8 bits per axis of the hash-grid cube; a stable radix sort of the
-                               active rays after the traversal), so that rays leaving one region of
-                               the scene share a wave whatever the caller's order (bounce rays of
-                               several samples per pixel); 0 = in the caller's order. Results do not
-                               change; 1 enlarges the query workspace by about 16 bytes per ray;
-                               ignored by grouped queries (0) */
+  int32_t query_order;      /* the order the rays are traversed and evaluated in (a stable radix sort
+                               of the rays by a Morton key before the traversal; every ray keeps its
+                               index): 0 = the caller's; 1 = by the origin's cell (8 bits per axis of
+                               the box of the ray origins), so that rays leaving one region of the
+                               scene share a wave whatever the caller's order (bounce rays of several
+                               samples per pixel); 2 = by the origin's cell (6 bits per axis) and the
+                               direction's cell (6 bits per axis of its octahedral map), for
+                               incoherent rays. Results do not change; 1 and 2 enlarge the query
+                               workspace by about 16 bytes per ray; grouped queries follow the first
+                               object's setting, with one order for all objects (0) */
 } nbvh_tuning;
 
 /* Read / replace the context's launch knobs (validated). */

@@ -19,7 +19,7 @@ import torch
 
 QUERY_STAGES = [dict(query_waves=(4, 8), query_unroll=(2, 3, 4), query_pairs=(0, 1)),
                 dict(query_wgs_per_cu=(0, 1, 2), query_lds_kb=(0, 24, 64)),
-                dict(traverse_mode=(0, 1, 2), query_order=(0, 1))]
+                dict(traverse_mode=(0, 1, 2), query_order=(0, 1, 2))]
 TRAIN_STAGES = [dict(train_waves=(4, 8), wgrad_splits=(16, 32, 64)),
                 dict(scatter_lds_kb=(0, 144), scatter_hash_levels=(0, 4, 8, 12), scatter_binned=(0, 1))]
 

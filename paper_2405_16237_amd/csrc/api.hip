@@ -273,7 +273,7 @@ static QueryLayout query_layout(uint64_t n_rays, uint64_t cap, bool ordered = fa
   Q.segs = off;
   off = a256(off + cap * sizeof(nbvh_segment));
   Q.order = off;
-  if (ordered) off = a256(off + group_ws_bytes(n_rays));
+  if (ordered) off = a256(off + ray_order_bytes(n_rays));
   Q.total = off;
   return Q;
 }
@@ -517,7 +517,7 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbv
   nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
   s = launch_traverse(L, rays, (uint32_t)n_rays, offsets, segs, seg_capacity, hits, (uint32_t*)(w + Q.active), misc + 0,
                       (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12, (float*)(w + Q.staging),
-                      ordered ? w + Q.order : nullptr);
+                      nullptr, ordered ? w + Q.order : nullptr);
   if (s != NBVH_OK) return s;
   return launch_query_eval(L, rays, offsets, segs, (const uint32_t*)(w + Q.active), misc + 0, misc + 1, hits,
                            (uint32_t)n_rays, seg_capacity);
@@ -565,7 +565,7 @@ nbvh_status nbvh_query_traced(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_ra
   nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
   s = launch_traverse(L, rays, (uint32_t)n_rays, offsets, segs, seg_capacity, hits, (uint32_t*)(w + Q.active), misc + 0,
                       (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12, (float*)(w + Q.staging),
-                      ordered ? w + Q.order : nullptr);
+                      nullptr, ordered ? w + Q.order : nullptr);
   if (s != NBVH_OK) return s;
   if (trace->seg_offsets_dev &&
       hipMemcpyAsync(trace->seg_offsets_dev, offsets, (n_rays + 1) * 4, hipMemcpyDeviceToDevice, L.stream) != hipSuccess)
@@ -823,7 +823,7 @@ nbvh_status nbvh_set_tuning(nbvh_ctx* ctx, const nbvh_tuning* t) {
   if (t->query_pairs != 0 && t->query_pairs != 1) return set_error("query_pairs must be 0 or 1"), NBVH_ERR_INVALID_ARG;
   if (t->query_lds_kb < 0 || t->query_lds_kb > 64) return set_error("query_lds_kb in 0..64"), NBVH_ERR_INVALID_ARG;
   if (t->traverse_mode < 0 || t->traverse_mode > 2) return set_error("traverse_mode must be 0, 1 or 2"), NBVH_ERR_INVALID_ARG;
-  if (t->query_order != 0 && t->query_order != 1) return set_error("query_order must be 0 or 1"), NBVH_ERR_INVALID_ARG;
+  if (t->query_order < 0 || t->query_order > 2) return set_error("query_order must be 0, 1 or 2"), NBVH_ERR_INVALID_ARG;
   ctx->tune = *t;
   return NBVH_OK;
 }
@@ -858,11 +858,21 @@ nbvh_status nbvh_batch_create(nbvh_ctx* const* ctxs, uint32_t n_objects, void* d
 
 // workspace: one query part per object, then the per-object hit records
 // [object][ray] that the merge reads
+// the objects' rays are ordered as the first object's knobs ask
+static bool batch_ordered(const nbvh_batch* b) { return b->ctxs[0]->tune.query_order != 0; }
+
 static size_t batch_part_bytes(uint64_t n_rays, uint64_t cap) { return query_layout(n_rays, cap).total; }
+
+// per object: a query workspace and hit records; then, with a ray order, one
+// ray permutation that every object's traversal follows
+static size_t batch_ws_bytes(const nbvh_batch* b, uint64_t n_rays, uint64_t cap) {
+  return b->ctxs.size() * (batch_part_bytes(n_rays, cap) + a256(n_rays * sizeof(nbvh_hit))) +
+         (batch_ordered(b) ? a256(ray_order_bytes(n_rays)) : 0);
+}
 
 size_t nbvh_batch_workspace_bytes(const nbvh_batch* b, uint64_t max_rays, uint64_t seg_capacity) {
   if (!b) return 0;
-  return b->ctxs.size() * (batch_part_bytes(max_rays, seg_capacity) + a256(max_rays * sizeof(nbvh_hit)));
+  return batch_ws_bytes(b, max_rays, seg_capacity);
 }
 
 nbvh_status nbvh_batch_query(nbvh_batch* b, const nbvh_ray* rays, uint64_t n_rays, nbvh_hit* hits, uint64_t seg_capacity,
@@ -873,15 +883,23 @@ nbvh_status nbvh_batch_query(nbvh_batch* b, const nbvh_ray* rays, uint64_t n_ray
   if (seg_capacity > 0xffffffffull) seg_capacity = 0xffffffffull;
   const int n = (int)b->ctxs.size();
   const size_t part = batch_part_bytes(n_rays, seg_capacity);
-  const size_t need = n * (part + a256(n_rays * sizeof(nbvh_hit)));
+  const size_t need = batch_ws_bytes(b, n_rays, seg_capacity);
   if (ws_bytes < need) return set_error("workspace too small: need %zu, got %zu", need, ws_bytes), NBVH_ERR_CAPACITY;
   if (n_rays == 0) return NBVH_OK;
   std::vector<LaunchCtx> Ls(n);
   std::vector<const uint32_t*> offs(n), act(n), nact(n);
   std::vector<const nbvh_segment*> sg(n);
   std::vector<uint32_t*> cnt(n);
+  const bool ordered = batch_ordered(b);
   const QueryLayout Q = query_layout(n_rays, seg_capacity);
   nbvh_hit* per_obj = (nbvh_hit*)((char*)ws + n * part);
+  RayOrder ord{nullptr, nullptr};
+  if (ordered) {
+    char* ow = (char*)ws + n * (part + a256(n_rays * sizeof(nbvh_hit)));
+    nbvh_status s = launch_ray_order(make_launch(b->ctxs[0], stream), rays, (uint32_t)n_rays,
+                                     b->ctxs[0]->tune.query_order, ow, &ord);
+    if (s != NBVH_OK) return s;
+  }
   for (int k = 0; k < n; ++k) {
     nbvh_status s = require_fp8_ready(b->ctxs[k]);
     if (s != NBVH_OK) return s;
@@ -895,7 +913,7 @@ nbvh_status nbvh_batch_query(nbvh_batch* b, const nbvh_ray* rays, uint64_t n_ray
     nbvh_status s = launch_traverse(Ls[k], rays, (uint32_t)n_rays, offsets, segs, seg_capacity,
                                     per_obj + (size_t)k * n_rays, (uint32_t*)(w + Q.active), misc + 0,
                                     (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12,
-                                    (float*)(w + Q.staging));
+                                    (float*)(w + Q.staging), ordered ? &ord : nullptr);
     if (s != NBVH_OK) return s;
     offs[k] = offsets;
     sg[k] = segs;

@@ -316,14 +316,17 @@ __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__
                                                         uint32_t n_rays, uint32_t* __restrict__ counts,
                                                         nbvh_hit* __restrict__ hits, uint32_t* __restrict__ active,
                                                         uint32_t* __restrict__ n_active, float* __restrict__ staging,
-                                                        int mode) {
+                                                        int mode, const uint32_t* __restrict__ perm) {
   extern __shared__ int32_t s_stack[];
-  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = r < n_rays;
+  // thread i takes ray perm[i] (ray i without a ray order); its staged run
+  // is column i, so a wave's staging stores stay coalesced
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < n_rays;
+  const uint32_t r = (perm && live) ? perm[i] : i;
   uint32_t cnt = 0;
   RunTail tail;
   const RayPre R = load_ray_or_none(rays, r, live);
-  float* run = (staging && live) ? staging + r : nullptr;
+  float* run = (staging && live) ? staging + i : nullptr;
   walk_mode<REV>(
       mode, nodes, R, live,
       [&](int32_t leaf, float t0, float t1, bool inside) {
@@ -369,7 +372,8 @@ __global__ __launch_bounds__(256) void k_traverse_compact(const Node* __restrict
                                                           const nbvh_ray* __restrict__ rays, uint32_t n_rays,
                                                           const uint32_t* __restrict__ offsets,
                                                           const float* __restrict__ staging,
-                                                          nbvh_segment* __restrict__ segs, uint64_t capacity, int mode) {
+                                                          nbvh_segment* __restrict__ segs, uint64_t capacity, int mode,
+                                                          const uint32_t* __restrict__ inv) {
   extern __shared__ int32_t s_stack[];
   __shared__ uint16_t s_slot[4][kWaveSlots];
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -388,14 +392,14 @@ __global__ __launch_bounds__(256) void k_traverse_compact(const Node* __restrict
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (uint32_t k = lane; k < wend - wbeg; k += 64u) {
       const uint32_t e = slot[k], o = r0 + (e & 63u), i = e >> 6;
-      const float* run = staging + o;
+      const float* run = staging + (inv ? inv[o] : o);
       segs[wbeg + k] = nbvh_segment{o, __float_as_uint(run[(3 * i) * plane]), run[(3 * i + 1) * plane],
                                     run[(3 * i + 2) * plane]};
     }
     return;
   }
   if (end > beg && !live) {
-    const float* run = staging + r;
+    const float* run = staging + (inv ? inv[r] : r);
     for (uint32_t i = 0; i < end - beg; ++i)
       segs[beg + i] = nbvh_segment{r, __float_as_uint(run[(3 * i) * plane]), run[(3 * i + 1) * plane],
                                    run[(3 * i + 2) * plane]};
@@ -692,9 +696,14 @@ nbvh_status launch_exclusive_scan(hipStream_t s, const uint32_t* in, uint32_t n,
 
 size_t traverse_staging_bytes(uint64_t n_rays) { return (size_t)n_rays * kStage * 3 * sizeof(float); }
 
-// Sort keys of the active rays: the Morton code of the origin's cell on a
-// 256^3 grid over the hash-grid cube (clamped); entries past n_active get the
-// largest key, so a stable sort keeps them behind every active ray.
+// Ray order (tuning query_order): a permutation of the rays by a Morton key,
+// built before the traversal so that the counting pass takes the rays in that
+// order (its waves, and the active list it fills, hold neighbouring rays)
+// while every ray keeps its index. Keys are relative to the box of the ray
+// origins (a min/max reduction first). Order 1: the origin's cell on a 256^3
+// grid (24 bits). Order 2: five coordinates at 6 bits each (30 bits), the
+// origin's cell on a 64^3 grid and the direction's cell on a 64^2 grid of its
+// octahedral map.
 __device__ inline uint32_t spread8(uint32_t v) {
   v = (v | (v << 8)) & 0x00F00Fu;
   v = (v | (v << 4)) & 0x0C30C3u;
@@ -702,70 +711,225 @@ __device__ inline uint32_t spread8(uint32_t v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_order_keys(const nbvh_ray* __restrict__ rays, const uint32_t* __restrict__ active,
-                                                    const uint32_t* __restrict__ n_active, uint32_t n, DevCfg c,
+__device__ inline uint32_t cell_of(float x, float cells) {
+  const float y = x * cells;
+  return y > 0.0f ? (uint32_t)fminf(y, cells - 1.0f) : 0u;  // NaN -> 0
+}
+
+// order-preserving map of floats to unsigned integers
+__device__ inline uint32_t float_key(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float key_float(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+// min / max of the ray origins per axis (as float_key), one partial per
+// block, then one block folds the partials
+__device__ inline void wave_minmax(uint32_t lo[3], uint32_t hi[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[a] = min(lo[a], (uint32_t)__shfl_xor((int)lo[a], off));
+      hi[a] = max(hi[a], (uint32_t)__shfl_xor((int)hi[a], off));
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_origin_box(const nbvh_ray* __restrict__ rays, uint32_t n,
+                                                    uint32_t* __restrict__ part) {
+  __shared__ uint32_t red[4][6];
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
+  if (i < n) {
+    const float4 o = *(const float4*)(rays + i);
+    const float p[3] = {o.x, o.y, o.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = float_key(p[a]);
+  }
+  wave_minmax(lo, hi);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      red[wave][a] = lo[a];
+      red[wave][3 + a] = hi[a];
+    }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    uint32_t v = red[0][threadIdx.x];
+    for (int w = 1; w < 4; ++w)
+      v = threadIdx.x < 3 ? min(v, red[w][threadIdx.x]) : max(v, red[w][threadIdx.x]);
+    part[(size_t)blockIdx.x * 6 + threadIdx.x] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_origin_box_fold(const uint32_t* __restrict__ part, uint32_t n_parts,
+                                                         uint32_t* __restrict__ box) {
+  __shared__ uint32_t red[4][6];
+  uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
+  for (uint32_t b = threadIdx.x; b < n_parts; b += 256u)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = min(lo[a], part[(size_t)b * 6 + a]);
+      hi[a] = max(hi[a], part[(size_t)b * 6 + 3 + a]);
+    }
+  wave_minmax(lo, hi);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      red[wave][a] = lo[a];
+      red[wave][3 + a] = hi[a];
+    }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    uint32_t v = red[0][threadIdx.x];
+    for (int w = 1; w < 4; ++w)
+      v = threadIdx.x < 3 ? min(v, red[w][threadIdx.x]) : max(v, red[w][threadIdx.x]);
+    box[threadIdx.x] = v;
+  }
+}
+
+// key of ray idx[i] (ray i without a list); entries at or past *n_valid (when
+// given) get the largest key, so a stable sort keeps them behind the others
+__global__ __launch_bounds__(256) void k_order_keys(const nbvh_ray* __restrict__ rays, const uint32_t* __restrict__ idx,
+                                                    const uint32_t* __restrict__ n_valid, uint32_t n,
+                                                    const uint32_t* __restrict__ box, int order,
                                                     uint32_t* __restrict__ keys) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i >= n) return;
-  uint32_t key = 0xFFFFFFFFu;
-  if (i < *n_active) {
-    const float4 o = *(const float4*)(rays + active[i]);
-    const float p[3] = {o.x, o.y, o.z};
-    key = 0u;
+  if (n_valid && i >= *n_valid) {
+    keys[i] = 0xFFFFFFFFu;
+    return;
+  }
+  const float4* p = (const float4*)(rays + (idx ? idx[i] : i));
+  const float4 o = p[0];
+  const float ov[3] = {o.x, o.y, o.z};
+  float org[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float x = (p[a] - c.scene_lo[a]) * c.inv_side * 256.0f;
-      const uint32_t q = x > 0.0f ? (uint32_t)fminf(x, 255.0f) : 0u;  // NaN -> 0
-      key |= spread8(q) << a;
+  for (int a = 0; a < 3; ++a) {
+    const float lo = key_float(box[a]), hi = key_float(box[3 + a]);
+    org[a] = hi > lo ? (ov[a] - lo) / (hi - lo) : 0.0f;
+  }
+  uint32_t key = 0u;
+  if (order == 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) key |= spread8(cell_of(org[a], 256.0f)) << a;
+  } else {
+    const float4 d = p[1];
+    // octahedral map of the direction onto [-1, 1]^2
+    const float l1 = fabsf(d.x) + fabsf(d.y) + fabsf(d.z);
+    float u = l1 > 0.0f ? d.x / l1 : 0.0f, v = l1 > 0.0f ? d.y / l1 : 0.0f;
+    if (d.z < 0.0f) {
+      const float uu = (1.0f - fabsf(v)) * (u >= 0.0f ? 1.0f : -1.0f);
+      v = (1.0f - fabsf(u)) * (v >= 0.0f ? 1.0f : -1.0f);
+      u = uu;
     }
+    const uint32_t q[5] = {cell_of(org[0], 64.0f), cell_of(org[1], 64.0f), cell_of(org[2], 64.0f),
+                           cell_of(0.5f * (u + 1.0f), 64.0f), cell_of(0.5f * (v + 1.0f), 64.0f)};
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) key |= ((q[k] >> b) & 1u) << (5 * b + k);
   }
   keys[i] = key;
 }
 
-// Reorders active[0, n_active) by origin key (6 passes of the 4-bit stable
-// radix sort that groups training probes by leaf; the last pass writes the
-// ray ids back into `active`).
-static nbvh_status order_active(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n, uint32_t* active,
-                                const uint32_t* n_active, void* ws) {
+__global__ __launch_bounds__(256) void k_invert(const uint32_t* __restrict__ perm, uint32_t n,
+                                                uint32_t* __restrict__ inv) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i < n) inv[perm[i]] = i;
+}
+
+size_t ray_order_bytes(uint64_t n) { return group_ws_bytes(n); }
+
+// Sorts n (key, value) pairs by key with the stable 4-bit radix passes that
+// group training probes by leaf (values = the indices when vin is null); the
+// keys come from k_order_keys in the workspace's second key buffer. Returns
+// the sorted values: `vout` when given (written by the last pass), else a
+// workspace buffer. `box` receives the ray origins' box first.
+struct OrderWs {
+  uint32_t *kbuf[2], *vbuf[2], *counts, *offs, *sums, *total, *box;
+};
+
+static OrderWs order_ws(void* ws, uint32_t n) {
   const uint32_t nb = (n + 255) / 256, cells = nb * kGroupDigits;
   char* w = (char*)ws;
-  uint32_t* kbuf[2];
-  uint32_t* vbuf[2];
+  OrderWs O;
   size_t off = 0;
   for (int j = 0; j < 2; ++j) {
-    kbuf[j] = (uint32_t*)(w + off);
+    O.kbuf[j] = (uint32_t*)(w + off);
     off += group_a256((size_t)n * 4);
-    vbuf[j] = (uint32_t*)(w + off);
+    O.vbuf[j] = (uint32_t*)(w + off);
     off += group_a256((size_t)n * 4);
   }
-  uint32_t* counts = (uint32_t*)(w + off);
+  O.counts = (uint32_t*)(w + off);
   off += group_a256(((size_t)cells + 1) * 4);
-  uint32_t* offs = (uint32_t*)(w + off);
+  O.offs = (uint32_t*)(w + off);
   off += group_a256(((size_t)cells + 1) * 4);
-  uint32_t* sums = (uint32_t*)(w + off);
+  O.sums = (uint32_t*)(w + off);
   off += group_a256(((size_t)cells / kScanTile + 2) * 4);
-  uint32_t* total = (uint32_t*)(w + off);
-  k_order_keys<<<nb, 256, 0, L.stream>>>(rays, active, n_active, n, L.cfg, kbuf[1]);
-  constexpr int kPasses = 6;  // 24-bit keys
-  const uint32_t* kin = kbuf[1];
-  const uint32_t* vin = active;
-  for (int p = 0; p < kPasses; ++p) {
-    uint32_t* kout = kbuf[p & 1];
-    uint32_t* vout = p == kPasses - 1 ? active : vbuf[p & 1];
-    k_group_count<<<nb, 256, 0, L.stream>>>(kin, n, 4 * p, counts);
-    nbvh_status s = launch_exclusive_scan(L.stream, counts, cells, offs, sums, total);
+  O.total = (uint32_t*)(w + off);  // then the origin box (6 words) in the same 256 bytes
+  O.box = O.total + 16;
+  return O;
+}
+
+static nbvh_status sort_rays(const LaunchCtx& L, const nbvh_ray* rays, const uint32_t* idx, const uint32_t* n_valid,
+                             uint32_t n, int order, const OrderWs& O, uint32_t* vout, const uint32_t** sorted) {
+  const uint32_t nb = (n + 255) / 256, cells = nb * kGroupDigits;
+  // the origins' box over all rays; its per-block partials use the digit counts' space
+  k_origin_box<<<nb, 256, 0, L.stream>>>(rays, n, O.counts);
+  k_origin_box_fold<<<1, 256, 0, L.stream>>>(O.counts, nb, O.box);
+  k_order_keys<<<nb, 256, 0, L.stream>>>(rays, idx, n_valid, n, O.box, order, O.kbuf[1]);
+  const int passes = order == 1 ? 6 : 8;  // 24- or 30-bit keys
+  const uint32_t* kin = O.kbuf[1];
+  const uint32_t* vin = idx;
+  for (int p = 0; p < passes; ++p) {
+    uint32_t* vo = (p == passes - 1 && vout) ? vout : O.vbuf[p & 1];
+    k_group_count<<<nb, 256, 0, L.stream>>>(kin, n, 4 * p, O.counts);
+    nbvh_status s = launch_exclusive_scan(L.stream, O.counts, cells, O.offs, O.sums, O.total);
     if (s != NBVH_OK) return s;
-    k_group_scatter<<<nb, 256, 0, L.stream>>>(kin, vin, n, 4 * p, offs, kout, vout);
-    kin = kout;
-    vin = vout;
+    k_group_scatter<<<nb, 256, 0, L.stream>>>(kin, vin, n, 4 * p, O.offs, O.kbuf[p & 1], vo);
+    kin = O.kbuf[p & 1];
+    vin = vo;
   }
+  *sorted = vin;
   return NBVH_OK;
+}
+
+// The permutation (grouped queries: one order for every object).
+nbvh_status launch_ray_order(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n, int order, void* ws,
+                             RayOrder* out) {
+  out->perm = out->inv = nullptr;
+  if (n == 0 || order == 0) return NBVH_OK;
+  const OrderWs O = order_ws(ws, n);
+  const uint32_t* perm = nullptr;
+  nbvh_status s = sort_rays(L, rays, nullptr, nullptr, n, order, O, nullptr, &perm);
+  if (s != NBVH_OK) return s;
+  uint32_t* inv = O.kbuf[0];  // free after the last pass, which read it and wrote kbuf[1]
+  k_invert<<<(n + 255) / 256, 256, 0, L.stream>>>(perm, n, inv);
+  out->perm = perm;
+  out->inv = inv;
+  return check_launch("ray order");
+}
+
+// The active list of one object's query, reordered in place after the
+// counting pass (the pass keeps the rays' own order, so its loads and
+// stores stay coalesced; only the evaluation follows the key order).
+static nbvh_status order_active_list(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n, uint32_t* active,
+                                     const uint32_t* n_active, int order, void* ws) {
+  const uint32_t* sorted = nullptr;
+  return sort_rays(L, rays, active, n_active, n, order, order_ws(ws, n), active, &sorted);
 }
 
 nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n_rays, uint32_t* offsets,
                             nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
                             uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
-                            uint32_t* scratch_total, float* staging, void* order_ws) {
+                            uint32_t* scratch_total, float* staging, const RayOrder* order,
+                            void* active_order_ws) {
   if (segs && !staging) return set_error("traversal staging buffer missing"), NBVH_ERR_INVALID_ARG;
   ProfScope ps(L.prof, NBVH_K_TRAVERSE, L.stream);
   const int grid = (int)((n_rays + 255) / 256);
@@ -775,9 +939,9 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
   if (n_rays > 0)
     (L.cfg.inside_reverse ? k_traverse_count<true> : k_traverse_count<false>)<<<grid, 256, stack_lds(L), L.stream>>>(
         L.nodes, rays, n_rays, scratch_counts, hits, active, n_active, segs ? staging : nullptr,
-        L.tune.traverse_mode);
-  if (order_ws && active && n_active && n_rays > 0) {
-    nbvh_status s = order_active(L, rays, n_rays, active, n_active, order_ws);
+        L.tune.traverse_mode, order ? order->perm : nullptr);
+  if (active_order_ws && active && n_active && n_rays > 0 && L.tune.query_order != 0) {
+    nbvh_status s = order_active_list(L, rays, n_rays, active, n_active, L.tune.query_order, active_order_ws);
     if (s != NBVH_OK) return s;
   }
   const uint32_t n_tiles = (n_rays + kScanTile - 1) / kScanTile;
@@ -788,7 +952,7 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
   if (segs && n_rays > 0)
     (L.cfg.inside_reverse ? k_traverse_compact<true> : k_traverse_compact<false>)<<<grid, 256, stack_lds(L),
                                                                                      L.stream>>>(
-        L.nodes, rays, n_rays, offsets, staging, segs, capacity, L.tune.traverse_mode);
+        L.nodes, rays, n_rays, offsets, staging, segs, capacity, L.tune.traverse_mode, order ? order->inv : nullptr);
   return check_launch("traverse");
 }
 

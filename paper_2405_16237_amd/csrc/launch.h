@@ -79,15 +79,29 @@ void set_error(const char* fmt, ...);
 __global__ void k_zero_u32(uint32_t* p, uint32_t n);
 __global__ void k_zero_f32(float* p, uint64_t n);
 
+// A permutation of the rays (launch_ray_order): the traversal's counting pass
+// takes them in perm order; inv[r] is ray r's position in perm.
+struct RayOrder {
+  const uint32_t* perm;
+  const uint32_t* inv;
+};
+size_t ray_order_bytes(uint64_t n);
+// order: tuning query_order (0 leaves both pointers null); ws: ray_order_bytes(n)
+nbvh_status launch_ray_order(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n, int order, void* ws,
+                             RayOrder* out);
+
 // `staging` (traverse_staging_bytes(n_rays), required with `segs`): sorted
 // per-ray runs kept by the counting pass so that the compaction copies them
-// instead of walking again. `order_ws` (nullable, group_ws_bytes(n_rays)):
-// with an active list, reorder it by the Morton code of the rays' origins.
+// instead of walking again. `order` (nullable): a permutation the counting
+// pass follows. `active_order_ws` (nullable, ray_order_bytes(n_rays)): with
+// an active list and tuning query_order, sort the list by key after the
+// counting pass instead.
 size_t traverse_staging_bytes(uint64_t n_rays);
 nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n_rays, uint32_t* offsets,
                             nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
                             uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
-                            uint32_t* scratch_total, float* staging, void* order_ws = nullptr);
+                            uint32_t* scratch_total, float* staging, const RayOrder* order = nullptr,
+                            void* active_order_ws = nullptr);
 
 // z_trace / u_trace (nullable): each evaluated segment's logits [cap][n_out]
 // and FP32 copy of its LDS feature row [cap][n_in] (not in FP8), at the

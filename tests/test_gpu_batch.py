@@ -144,6 +144,29 @@ def test_batch_query_config4_shape(c4_shape, precision):
         assert dt.max() <= 1e-5 * max(1.0, np.abs(t_best[same]).max())
 
 
+def test_batch_query_same_in_any_order(objects):
+    """The grouped query gives the same hit records whether each object's
+    rays are evaluated in the caller's order or sorted by origin and
+    direction (query_order = 2, which grouped queries take from the first
+    object)."""
+    P, objs = objects
+    ms = []
+    for sc, net, params in objs:
+        m = P.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16")
+        m.set_params(params)
+        ms.append(m)
+    batch = P.NBVHBatch(ms)
+    boxes_all = np.concatenate([sc.boxes for sc, _, _ in objs])
+    rays_np, _ = configs.c4_rays(boxes_all, 50_000 + 13, seed=111)
+    rays = torch.from_numpy(rays_np).cuda()
+    _say("grouped query in the caller's order and in origin-and-direction order")
+    a = batch.query(rays).cpu().numpy().view(np.uint32)
+    ms[0].set_tuning(query_order=2)
+    b = batch.query(rays).cpu().numpy().view(np.uint32)
+    assert np.array_equal(a, b)
+    assert (a[:, 7] != 0xFFFFFFFF).sum() > 200
+
+
 @pytest.mark.parametrize("branches", [False, True])
 def test_graph_captured_batch_train_step(objects, branches):
     """The multi-object training step captured once in a HIP graph (the
@@ -226,14 +249,14 @@ def test_autotuner_keeps_results(objects):
     probes = torch.from_numpy(p).cuda()
     _say("autotune")
     rep = autotune.autotune(m, rays=rays, probes=probes, reps=1)
-    assert len(rep["query"]) == 12 + 9 + 6 and len(rep["train"]) == 6 + 16
+    assert len(rep["query"]) == 12 + 9 + 9 and len(rep["train"]) == 6 + 16
     assert m.get_tuning() == rep["tuning"]
     for knobs in ({"query_waves": 4, "query_unroll": 2, "query_wgs_per_cu": 1, "query_pairs": 1},
                   {"query_waves": 8, "query_unroll": 4, "query_pairs": 0}, {"query_waves": 8, "query_unroll": 3, "query_pairs": 1},
                   {"query_waves": 8, "query_unroll": 2, "query_pairs": 0, "query_lds_kb": 24},
                   {"query_waves": 4, "query_unroll": 3, "query_pairs": 0, "query_lds_kb": 64},
                   {"query_lds_kb": 0, "traverse_mode": 0}, {"traverse_mode": 1},
-                  {"traverse_mode": 2, "query_order": 1}):
+                  {"traverse_mode": 2, "query_order": 1}, {"query_order": 2}):
         m.set_tuning(**knobs)
         got = m.query(rays).view(torch.int32)
         assert torch.equal(got, ref), knobs

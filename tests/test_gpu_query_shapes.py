@@ -214,8 +214,8 @@ def test_query_same_for_every_walk(lib, frame):
     r = torch.from_numpy(rays).cuda()
     out = []
     for mode in (0, 1, 2):
-        for order in (0, 1):
-            _say("query frame subset, walk mode", mode, "origin order", order)
+        for order in (0, 1, 2):
+            _say("query frame subset, walk mode", mode, "ray order", order)
             m.set_tuning(traverse_mode=mode, query_order=order)
             out.append(m.query(r).cpu().numpy().view(np.uint32))
     for o in out[1:]:
@@ -279,15 +279,17 @@ def test_query_bounce_reverse(lib, bounce, precision):
 
 def test_bounce_query_same_in_origin_order(lib, bounce):
     """Evaluating the bounce rays in the order of their origins' Morton codes
-    (query_order = 1) gives the same hit records bit for bit."""
+    (query_order = 1) or of their origins' and directions' (2) gives the same
+    hit records bit for bit."""
     sc, rays = bounce
     net = configs.C5_NET
     m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", inside="reverse")
     m.set_params(_seeded(net))
     r = torch.from_numpy(rays).cuda()
-    _say("bounce query in the caller's order and in origin order")
+    _say("bounce query in the caller's order, in origin order and in origin-and-direction order")
     a = m.query(r).cpu().numpy().view(np.uint32)
-    m.set_tuning(query_order=1)
-    b = m.query(r).cpu().numpy().view(np.uint32)
-    assert np.array_equal(a, b)
+    for order in (1, 2):
+        m.set_tuning(query_order=order)
+        b = m.query(r).cpu().numpy().view(np.uint32)
+        assert np.array_equal(a, b), order
     assert (a[:, 7] != 0xFFFFFFFF).sum() > 1000
