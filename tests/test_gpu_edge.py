@@ -245,3 +245,32 @@ def test_wgrad_splits_cover_the_batch(lib, c1, precision, n):
         for splits, g in grads.items():
             kept = np.abs(g - o).max() / np.abs(o).max()
             assert kept <= 1e-4, (splits, kept)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_ray_order_edge_inputs(lib, c1, order):
+    """Ray orders on awkward inputs: no rays, one ray, a count that is not a
+    multiple of a workgroup, every origin equal (all keys equal: the stable
+    sort keeps the caller's order), and origins at infinity (which stretch the
+    origins' box; their keys clamp to a cell) all answer as the caller's order
+    does, in the single-object and the grouped query."""
+    sc = c1
+    m = lib.NBVH(configs.C1_NET, sc.boxes, sc.lo, sc.side, precision="bf16")
+    m.set_params(configs.init_params(configs.C1_NET, "uniform", 1.0, seed_features=71, seed_mlp=72))
+    cam = scene.pinhole_rays(128, 96)
+    rng = np.random.default_rng(73)
+    odd = cam[rng.permutation(cam.shape[0])[:1001]].copy()
+    odd[:5, 0:3] = np.array([np.inf, -np.inf, np.inf], np.float32)  # these miss every box
+    sets = {"none": cam[:0], "one": cam[6000:6001], "odd": odd, "same origin": cam[:777]}
+    batch = lib.NBVHBatch([m])
+    for name, rays_np in sets.items():
+        _say("ray order", order, name, rays_np.shape[0], "rays")
+        rays = torch.from_numpy(np.ascontiguousarray(rays_np)).cuda()
+        m.set_tuning(query_order=0)
+        ref = m.query(rays).cpu().numpy().view(np.uint32)
+        bref = batch.query(rays).cpu().numpy().view(np.uint32)
+        m.set_tuning(query_order=order)
+        got = m.query(rays).cpu().numpy().view(np.uint32)
+        bgot = batch.query(rays).cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, ref) and np.array_equal(bgot, bref), name
+    assert m.read_state()["flags"] == 0
