@@ -458,6 +458,9 @@ def run_single(args, W, P, torch, configs, scene):
         tr["node_visits_per_s"] = round(vpr * R / (tr["avg_ms"] * 1e-3), 1)
         tr["node_visits_sample"] = what
         log("traversal: %.2f node visits per ray, %.3g visits/s" % (vpr, tr["node_visits_per_s"]))
+    roofline["path"] = path_rooflines(net, evaluated, B, R, n_segments,
+                                      tr["node_visits_per_ray"] if tr is not None else None, q_ms, t_ms)
+    log("path rooflines:", roofline["path"])
     peaks = None
     if not args.no_peaks:
         from paper_2405_16237_amd import peaks as PK
@@ -613,6 +616,49 @@ def against_ceilings(roofline, peaks, net, evaluated, B, table_bytes):
     for key in ("ceiling", "frac_ceiling", "gathers_glanes_per_s", "mlp"):
         if key in per.get(dom, {}):
             roofline[key] = per[dom][key]
+
+
+def path_rooflines(net, evaluated, B, R, n_segments, visits_per_ray, q_ms, t_ms):
+    """Lower bounds of the query and training paths at the data-sheet peaks:
+    each stage takes at least its algorithmic bytes over HBM, its MLP FLOPs
+    over the BF16 matrix cores and its scalar arithmetic over the FP32 vector
+    units (whichever is longest); the stages run one after another, so a
+    path's bound is the sum. Algorithmic work per stage:
+      traversal: the rays, the segment queue written and read, the counts
+        (bytes); 2 slab tests of about 24 operations per node visit (vector);
+      evaluation: S*L*8 corners x F x 2 B per evaluated segment; 2 FLOPs per
+        weight and evaluated segment;
+      training tile: the same gathers and forward FLOPs per probe plus the
+        input-gradient products (2x); weight gradient: 2 FLOPs per weight and
+        probe; table gradient: one 4-byte read-modify-write per corner,
+        feature and level (all levels); Adam: 34 B per parameter.
+    `frac` = bound / measured time."""
+    S, L, F = net.n_samples, net.n_levels, net.n_features
+    mlp = sum(fi * fo for fi, fo in net.layer_dims()) * 2.0
+    hbm, mf = HBM_PEAK_GBS * 1e9, BF16_PEAK_TFLOPS * 1e12
+    valu_ops = FP32_PEAK_TFLOPS * 1e12 / 4.0  # one 32-bit operation per lane and cycle (the peak counts packed FMAs)
+
+    def bound(nbytes=0.0, flops=0.0, ops=0.0):
+        return max(nbytes / hbm, flops / mf, ops / valu_ops) * 1e3
+
+    stages_q = {
+        "traverse": bound(nbytes=R * 32 + n_segments * 16 * 2 + R * 12,
+                          ops=(visits_per_ray or 0.0) * R * 2 * 24),
+        "query_eval": bound(nbytes=evaluated * S * L * 8 * F * 2, flops=evaluated * mlp),
+    }
+    stages_t = {
+        "train_tile": bound(nbytes=B * S * L * 8 * F * 2, flops=3 * B * mlp),
+        "wgrad": bound(flops=B * mlp),
+        "table_gradient": bound(nbytes=B * S * L * 8 * F * 4 * 2),
+        "optimizer": bound(nbytes=(net.n_table_params + net.n_mlp_params) * 34),
+    }
+    q_bound, t_bound = sum(stages_q.values()), sum(stages_t.values())
+    return {
+        "query": {"bound_ms": round(q_bound, 4), "measured_ms": round(q_ms, 4), "frac": round(q_bound / q_ms, 4),
+                  "stages_ms": {k: round(v, 4) for k, v in stages_q.items()}},
+        "train": {"bound_ms": round(t_bound, 4), "measured_ms": round(t_ms, 4), "frac": round(t_bound / t_ms, 4),
+                  "stages_ms": {k: round(v, 4) for k, v in stages_t.items()}},
+    }
 
 
 def rooflines(prof, net, tune, evaluated, B, R, n_segments, workload):
