@@ -293,3 +293,24 @@ def test_bounce_query_same_in_origin_order(lib, bounce):
         b = m.query(r).cpu().numpy().view(np.uint32)
         assert np.array_equal(a, b), order
     assert (a[:, 7] != 0xFFFFFFFF).sum() > 1000
+
+
+def test_traverse_bitexact_bounce_every_walk(lib, bounce):
+    """The bounce rays' segment queue at 16,384 leaves (depth 14, reverse
+    rule) is bit-exact against the every-leaf oracle for the per-lane walk,
+    the wave-coherent walk (forced on these incoherent rays, so that every
+    wave visits the union of 64 scattered paths) and the per-wave choice."""
+    sc, rays = bounce
+    m = lib.NBVH(configs.C5_NET, sc.boxes, sc.lo, sc.side, precision="bf16", inside="reverse")
+    off_o, sr, sl, t0, t1 = oracle.traverse(rays, sc.boxes, True)
+    r = torch.from_numpy(rays).cuda()
+    for mode in (0, 1, 2):
+        _say("traverse bounce rays, 16,384 leaves, walk mode", mode)
+        m.set_tuning(traverse_mode=mode)
+        off, segs = m.traverse(r, int(off_o[-1]) + 16)
+        off = off.cpu().numpy().astype(np.uint32).astype(np.uint64)
+        sg = segs[: int(off_o[-1])].cpu().numpy()
+        assert np.array_equal(off, off_o), mode
+        assert np.array_equal(sg[:, 0].astype(np.uint32), sr)
+        assert np.array_equal(sg[:, 1].view(np.uint32), sl)
+        assert np.array_equal(sg[:, 2].view(np.float32), t0) and np.array_equal(sg[:, 3].view(np.float32), t1)
