@@ -333,8 +333,8 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays_dev, uint64_t n_rays,
  * same kernels and results, with the query's workspace taken from a
  * library-owned static device buffer of 64 MiB instead of a caller workspace.
  * Each GPU the library runs on holds its own copy until the process ends.
- * The workspace of a query is 12 bytes per ray for offsets, counts and the
- * active list, 192 bytes per ray of traversal staging, 16 bytes per segment
+ * The workspace of a query is 16 bytes per ray for offsets, counts, the
+ * active list and its positions, 192 bytes per ray of traversal staging, 16 bytes per segment
  * of capacity, plus a few hundred bytes of counters and scan partials,
  * each part rounded up to 256 bytes; a query needing more than 64 MiB returns
  * NBVH_ERR_CAPACITY before enqueuing anything (about 200,000 rays at 8

@@ -249,7 +249,7 @@ static LaunchCtx make_launch(const nbvh_ctx* ctx, void* stream) {
 
 // query workspace carve-up
 struct QueryLayout {
-  size_t offsets, counts, active, sums, misc, staging, segs, order, total;
+  size_t offsets, counts, active, pos, sums, sums2, misc, staging, segs, order, total;
 };
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -264,7 +264,11 @@ static QueryLayout query_layout(uint64_t n_rays, uint64_t cap, bool ordered = fa
   off = a256(off + n_rays * 4);
   Q.active = off;
   off = a256(off + n_rays * 4);
+  Q.pos = off;
+  off = a256(off + (n_rays + 1) * 4);
   Q.sums = off;
+  off = a256(off + (n_rays / 1024 + 2) * 4);
+  Q.sums2 = off;
   off = a256(off + (n_rays / 1024 + 2) * 4);
   Q.misc = off;
   off = a256(off + 16 * 4);
@@ -517,7 +521,7 @@ nbvh_status nbvh_query(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_rays, nbv
   nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
   s = launch_traverse(L, rays, (uint32_t)n_rays, offsets, segs, seg_capacity, hits, (uint32_t*)(w + Q.active), misc + 0,
                       (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12, (float*)(w + Q.staging),
-                      nullptr, ordered ? w + Q.order : nullptr);
+                      nullptr, ordered ? w + Q.order : nullptr, (uint32_t*)(w + Q.pos), (uint32_t*)(w + Q.sums2));
   if (s != NBVH_OK) return s;
   return launch_query_eval(L, rays, offsets, segs, (const uint32_t*)(w + Q.active), misc + 0, misc + 1, hits,
                            (uint32_t)n_rays, seg_capacity);
@@ -565,7 +569,7 @@ nbvh_status nbvh_query_traced(nbvh_ctx* ctx, const nbvh_ray* rays, uint64_t n_ra
   nbvh_segment* segs = (nbvh_segment*)(w + Q.segs);
   s = launch_traverse(L, rays, (uint32_t)n_rays, offsets, segs, seg_capacity, hits, (uint32_t*)(w + Q.active), misc + 0,
                       (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12, (float*)(w + Q.staging),
-                      nullptr, ordered ? w + Q.order : nullptr);
+                      nullptr, ordered ? w + Q.order : nullptr, (uint32_t*)(w + Q.pos), (uint32_t*)(w + Q.sums2));
   if (s != NBVH_OK) return s;
   if (trace->seg_offsets_dev &&
       hipMemcpyAsync(trace->seg_offsets_dev, offsets, (n_rays + 1) * 4, hipMemcpyDeviceToDevice, L.stream) != hipSuccess)
@@ -913,7 +917,8 @@ nbvh_status nbvh_batch_query(nbvh_batch* b, const nbvh_ray* rays, uint64_t n_ray
     nbvh_status s = launch_traverse(Ls[k], rays, (uint32_t)n_rays, offsets, segs, seg_capacity,
                                     per_obj + (size_t)k * n_rays, (uint32_t*)(w + Q.active), misc + 0,
                                     (uint32_t*)(w + Q.counts), (uint32_t*)(w + Q.sums), misc + 12,
-                                    (float*)(w + Q.staging), ordered ? &ord : nullptr);
+                                    (float*)(w + Q.staging), ordered ? &ord : nullptr, nullptr,
+                                    (uint32_t*)(w + Q.pos), (uint32_t*)(w + Q.sums2));
     if (s != NBVH_OK) return s;
     offs[k] = offsets;
     sg[k] = segs;

@@ -306,16 +306,15 @@ __device__ inline RayPre load_ray_or_none(const nbvh_ray* rays, uint32_t r, bool
 }
 
 // counts[r] = leaves crossed. If `hits` is given (full query), rays with no
-// segment get their miss record here and rays with segments are appended to
-// `active` (wave-aggregated atomic). If `staging` is given, the first
-// kStage segments of ray r are also kept there, sorted, so that the
-// compaction after the scan need not walk the tree again.
+// segment get their miss record here (rays with segments are listed by the
+// compaction, at positions from a scan of the counts). If `staging` is
+// given, the first kStage segments of ray r are also kept there, sorted, so
+// that the compaction after the scan need not walk the tree again.
 constexpr uint32_t kStage = 16;
 template <bool REV>
 __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__ nodes, const nbvh_ray* __restrict__ rays,
                                                         uint32_t n_rays, uint32_t* __restrict__ counts,
-                                                        nbvh_hit* __restrict__ hits, uint32_t* __restrict__ active,
-                                                        uint32_t* __restrict__ n_active, float* __restrict__ staging,
+                                                        nbvh_hit* __restrict__ hits, float* __restrict__ staging,
                                                         int mode, const uint32_t* __restrict__ perm) {
   extern __shared__ int32_t s_stack[];
   // thread i takes ray perm[i] (ray i without a ray order); its staged run
@@ -342,21 +341,6 @@ __global__ __launch_bounds__(256) void k_traverse_count(const Node* __restrict__
       h[1] = make_float4(0.f, 0.f, 0.f, __uint_as_float(NBVH_MISS));
     }
   }
-  if (active) {
-    const bool want = live && cnt > 0;
-    const uint64_t mask = __ballot(want);
-    if (mask) {
-      const int lane = threadIdx.x & 63;
-      const int leader = __ffsll((unsigned long long)mask) - 1;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(n_active, (uint32_t)__popcll(mask));
-      base = __shfl(base, leader);
-      if (want) {
-        const uint32_t rank = __popcll(mask & ((1ull << lane) - 1ull));
-        active[base + rank] = r;
-      }
-    }
-  }
 }
 
 // Compaction from the staging runs: rays with more than kStage segments walk
@@ -373,12 +357,17 @@ __global__ __launch_bounds__(256) void k_traverse_compact(const Node* __restrict
                                                           const uint32_t* __restrict__ offsets,
                                                           const float* __restrict__ staging,
                                                           nbvh_segment* __restrict__ segs, uint64_t capacity, int mode,
-                                                          const uint32_t* __restrict__ inv) {
+                                                          const uint32_t* __restrict__ inv,
+                                                          const uint32_t* __restrict__ apos,
+                                                          uint32_t* __restrict__ active) {
   extern __shared__ int32_t s_stack[];
   __shared__ uint16_t s_slot[4][kWaveSlots];
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if ((uint64_t)offsets[n_rays] > capacity) return;  // overflow flagged by the scan (uniform)
   const uint32_t beg = r < n_rays ? offsets[r] : 0u, end = r < n_rays ? offsets[r + 1] : 0u;
+  // the rays with segments at their positions among them (in ray order, or
+  // in the order the counting pass followed)
+  if (active && end > beg) active[apos[inv ? inv[r] : r]] = r;
   const bool live = end - beg > kStage;
   const size_t plane = n_rays;
   if (__ballot(live) == 0ull) {
@@ -562,6 +551,89 @@ __global__ __launch_bounds__(256) void k_scan_add(uint32_t* __restrict__ out, ui
   if (i == 0) {
     const uint32_t t = *total;
     out[n] = t;
+    if (state) {
+      state->last_n_segments = t;
+      if ((uint64_t)t > capacity) atomicOr(&state->flags, NBVH_FLAG_CAPACITY);
+    }
+  }
+}
+
+// The traversal's two scans at once: segment offsets of the counts and, for
+// the active-ray list, positions among the rays with a segment (tile scans,
+// one block per scan of the tile sums, add; the totals go to total_seg and
+// total_ray).
+// (positions follow the ray order `perm` when one is given: pos[i] is the
+// place of ray perm[i])
+__global__ __launch_bounds__(256) void k_scan2_tiles(const uint32_t* __restrict__ in, uint32_t n,
+                                                     const uint32_t* __restrict__ perm, uint32_t* __restrict__ out,
+                                                     uint32_t* __restrict__ pos, uint32_t* __restrict__ sums_seg,
+                                                     uint32_t* __restrict__ sums_ray) {
+  __shared__ uint32_t sh[8];
+  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems], g[kScanItems], s = 0, f = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const bool ok = base + i < n;
+    v[i] = ok ? in[base + i] : 0u;
+    g[i] = ok ? ((perm ? in[perm[base + i]] : v[i]) > 0u ? 1u : 0u) : 0u;
+    s += v[i];
+    f += g[i];
+  }
+  uint32_t total_s, total_f;
+  uint32_t ex = block_exclusive_scan(s, sh, total_s);
+  uint32_t ef = block_exclusive_scan(f, sh, total_f);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) {
+      out[base + i] = ex;
+      pos[base + i] = ef;
+    }
+    ex += v[i];
+    ef += g[i];
+  }
+  if (threadIdx.x == 0) {
+    sums_seg[blockIdx.x] = total_s;
+    sums_ray[blockIdx.x] = total_f;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan2_sums(uint32_t* __restrict__ sums_seg, uint32_t* __restrict__ sums_ray,
+                                                     uint32_t n_tiles, uint32_t* __restrict__ total_seg,
+                                                     uint32_t* __restrict__ total_ray) {
+  __shared__ uint32_t sh[16];
+  __shared__ uint32_t carry;
+  uint32_t* sums = blockIdx.x == 0 ? sums_seg : sums_ray;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < n_tiles; base += blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t v = (i < n_tiles) ? sums[i] : 0u;
+    uint32_t total;
+    uint32_t ex = block_exclusive_scan(v, sh, total);
+    const uint32_t c0 = carry;
+    if (i < n_tiles) sums[i] = ex + c0;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c0 + total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *(blockIdx.x == 0 ? total_seg : total_ray) = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan2_add(uint32_t* __restrict__ out, uint32_t* __restrict__ pos, uint32_t n,
+                                                   const uint32_t* __restrict__ sums_seg,
+                                                   const uint32_t* __restrict__ sums_ray,
+                                                   const uint32_t* __restrict__ total_seg,
+                                                   const uint32_t* __restrict__ total_ray, uint64_t capacity,
+                                                   DevState* __restrict__ state) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    out[i] += sums_seg[i / kScanTile];
+    pos[i] += sums_ray[i / kScanTile];
+  }
+  if (i == 0) {
+    const uint32_t t = *total_seg;
+    out[n] = t;
+    pos[n] = *total_ray;
     if (state) {
       state->last_n_segments = t;
       if ((uint64_t)t > capacity) atomicOr(&state->flags, NBVH_FLAG_CAPACITY);
@@ -929,8 +1001,10 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
                             nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
                             uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
                             uint32_t* scratch_total, float* staging, const RayOrder* order,
-                            void* active_order_ws) {
+                            void* active_order_ws, uint32_t* scratch_pos, uint32_t* scratch_sums2) {
   if (segs && !staging) return set_error("traversal staging buffer missing"), NBVH_ERR_INVALID_ARG;
+  if (active && (!n_active || !segs || !scratch_pos || !scratch_sums2))
+    return set_error("active-ray list without its buffers"), NBVH_ERR_INVALID_ARG;
   ProfScope ps(L.prof, NBVH_K_TRAVERSE, L.stream);
   const int grid = (int)((n_rays + 255) / 256);
   if (n_active) {
@@ -938,21 +1012,32 @@ nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n
   }
   if (n_rays > 0)
     (L.cfg.inside_reverse ? k_traverse_count<true> : k_traverse_count<false>)<<<grid, 256, stack_lds(L), L.stream>>>(
-        L.nodes, rays, n_rays, scratch_counts, hits, active, n_active, segs ? staging : nullptr,
-        L.tune.traverse_mode, order ? order->perm : nullptr);
-  if (active_order_ws && active && n_active && n_rays > 0 && L.tune.query_order != 0) {
-    nbvh_status s = order_active_list(L, rays, n_rays, active, n_active, L.tune.query_order, active_order_ws);
-    if (s != NBVH_OK) return s;
-  }
+        L.nodes, rays, n_rays, scratch_counts, hits, segs ? staging : nullptr, L.tune.traverse_mode,
+        order ? order->perm : nullptr);
   const uint32_t n_tiles = (n_rays + kScanTile - 1) / kScanTile;
-  if (n_rays > 0) k_scan_tiles<<<n_tiles, 256, 0, L.stream>>>(scratch_counts, n_rays, offsets, scratch_sums);
-  k_scan_sums<<<1, 1024, 0, L.stream>>>(scratch_sums, n_tiles, scratch_total);
-  k_scan_add<<<grid > 0 ? grid : 1, 256, 0, L.stream>>>(offsets, n_rays, scratch_sums, scratch_total, capacity,
-                                                        L.state);
+  if (active) {
+    // offsets and the active-list positions in one set of scan launches
+    if (n_rays > 0)
+      k_scan2_tiles<<<n_tiles, 256, 0, L.stream>>>(scratch_counts, n_rays, order ? order->perm : nullptr, offsets,
+                                                   scratch_pos, scratch_sums, scratch_sums2);
+    k_scan2_sums<<<2, 1024, 0, L.stream>>>(scratch_sums, scratch_sums2, n_tiles, scratch_total, n_active);
+    k_scan2_add<<<grid > 0 ? grid : 1, 256, 0, L.stream>>>(offsets, scratch_pos, n_rays, scratch_sums, scratch_sums2,
+                                                           scratch_total, n_active, capacity, L.state);
+  } else {
+    if (n_rays > 0) k_scan_tiles<<<n_tiles, 256, 0, L.stream>>>(scratch_counts, n_rays, offsets, scratch_sums);
+    k_scan_sums<<<1, 1024, 0, L.stream>>>(scratch_sums, n_tiles, scratch_total);
+    k_scan_add<<<grid > 0 ? grid : 1, 256, 0, L.stream>>>(offsets, n_rays, scratch_sums, scratch_total, capacity,
+                                                          L.state);
+  }
   if (segs && n_rays > 0)
     (L.cfg.inside_reverse ? k_traverse_compact<true> : k_traverse_compact<false>)<<<grid, 256, stack_lds(L),
                                                                                      L.stream>>>(
-        L.nodes, rays, n_rays, offsets, staging, segs, capacity, L.tune.traverse_mode, order ? order->inv : nullptr);
+        L.nodes, rays, n_rays, offsets, staging, segs, capacity, L.tune.traverse_mode, order ? order->inv : nullptr,
+        active ? scratch_pos : nullptr, active);
+  if (active_order_ws && active && n_rays > 0 && L.tune.query_order != 0) {
+    nbvh_status s = order_active_list(L, rays, n_rays, active, n_active, L.tune.query_order, active_order_ws);
+    if (s != NBVH_OK) return s;
+  }
   return check_launch("traverse");
 }
 

@@ -94,14 +94,17 @@ nbvh_status launch_ray_order(const LaunchCtx& L, const nbvh_ray* rays, uint32_t 
 // per-ray runs kept by the counting pass so that the compaction copies them
 // instead of walking again. `order` (nullable): a permutation the counting
 // pass follows. `active_order_ws` (nullable, ray_order_bytes(n_rays)): with
-// an active list and tuning query_order, sort the list by key after the
-// counting pass instead.
+// an active list and tuning query_order, sort the list by key once it is
+// built instead. With `active` (the list of rays with a segment,
+// in ray order; its length goes to *n_active), `segs`, scratch_pos
+// (n_rays + 1 words) and scratch_sums2 (like scratch_sums) are required.
 size_t traverse_staging_bytes(uint64_t n_rays);
 nbvh_status launch_traverse(const LaunchCtx& L, const nbvh_ray* rays, uint32_t n_rays, uint32_t* offsets,
                             nbvh_segment* segs, uint64_t capacity, nbvh_hit* hits, uint32_t* active,
                             uint32_t* n_active, uint32_t* scratch_counts, uint32_t* scratch_sums,
                             uint32_t* scratch_total, float* staging, const RayOrder* order = nullptr,
-                            void* active_order_ws = nullptr);
+                            void* active_order_ws = nullptr, uint32_t* scratch_pos = nullptr,
+                            uint32_t* scratch_sums2 = nullptr);
 
 // z_trace / u_trace (nullable): each evaluated segment's logits [cap][n_out]
 // and FP32 copy of its LDS feature row [cap][n_in] (not in FP8), at the
