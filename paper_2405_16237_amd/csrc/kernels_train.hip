@@ -47,6 +47,7 @@ struct TrainLayout {
   int n_lds, hash_end;
   uint32_t lds_floats, n_bins;
   uint64_t max_records;
+  bool rec8;  // binned records of two-feature tables: 8 bytes (24-bit values) instead of 12
   size_t counts, offsets, scan_sums, rec_idx, rec_val;
 };
 static int coarse_lds_levels(const DevCfg& c, size_t budget_bytes, uint32_t* n_floats);
@@ -83,6 +84,7 @@ static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_bat
   if (T.hash_end > c.n_levels) T.hash_end = c.n_levels;
   T.n_bins = 0;
   T.max_records = 0;
+  T.rec8 = c.n_features == 2 && precision != NBVH_FP32;
   T.counts = T.offsets = T.scan_sums = T.rec_idx = T.rec_val = off;
   if (tune.scatter_binned && T.hash_end < c.n_levels) {
     const uint64_t off0 = c.level_off[T.hash_end];
@@ -95,10 +97,10 @@ static TrainLayout train_layout(const DevCfg& c, int precision, uint64_t max_bat
     off = align256(off + (cells + 1) * 4);
     T.scan_sums = off;
     off = align256(off + (cells / 1024 + 4) * 4);
-    T.rec_idx = off;  // F = 2 keeps the entry inside its 12-byte record
+    T.rec_idx = off;  // F = 2 keeps the entry inside its record
     if (c.n_features != 2) off = align256(off + T.max_records * 2);
     T.rec_val = off;
-    off = align256(off + T.max_records * (c.n_features == 2 ? 12 : c.n_features * 4));
+    off = align256(off + T.max_records * (c.n_features == 2 ? (T.rec8 ? 8 : 12) : c.n_features * 4));
   }
   T.total = off;
   return T;
@@ -824,6 +826,46 @@ __device__ inline void level_runs(const DevCfg& c, int l, const nbvh_probe* __re
   }
 }
 
+// Binned records of two-feature tables: 12 bytes (entry, two FP32 values), or
+// for the reduced-precision paths 8 bytes: each value rounded to nearest even
+// on its 16 upper mantissa bits (relative error at most 2^-16, far below the
+// BF16 activations' and table's own rounding) and the 13-bit entry split over
+// the two freed low bytes. A finite value is never rounded up to infinity.
+__device__ inline uint32_t round_f24(float v) {
+  const uint32_t b = __float_as_uint(v);
+  uint32_t r = b + 0x7fu + ((b >> 8) & 1u);
+  if ((r & 0x7f800000u) == 0x7f800000u) r = b;
+  return r & 0xffffff00u;
+}
+
+template <bool R8>
+struct BinRecord;
+template <>
+struct BinRecord<false> {
+  typedef uint3 T;
+  __device__ static T pack(uint32_t e, float v0, float v1) { return uint3{e, __float_as_uint(v0), __float_as_uint(v1)}; }
+  __device__ static void unpack(const T& r, uint32_t& e, float& v0, float& v1) {
+    e = r.x;
+    v0 = __uint_as_float(r.y);
+    v1 = __uint_as_float(r.z);
+  }
+  __device__ static T none() { return uint3{0xffffffffu, 0u, 0u}; }
+};
+template <>
+struct BinRecord<true> {
+  typedef uint2 T;
+  __device__ static T pack(uint32_t e, float v0, float v1) {
+    return uint2{round_f24(v0) | (e & 0xffu), round_f24(v1) | (e >> 8)};
+  }
+  __device__ static void unpack(const T& r, uint32_t& e, float& v0, float& v1) {
+    e = (r.x == 0xffffffffu) ? 0xffffffffu : ((r.x & 0xffu) | ((r.y & 0xffu) << 8));
+    v0 = __uint_as_float(r.x & 0xffffff00u);
+    v1 = __uint_as_float(r.y & 0xffffff00u);
+  }
+  __device__ static T none() { return uint2{0xffffffffu, 0u}; }
+};
+static_assert(kBinChunk <= (1u << 13), "an 8-byte record holds a 13-bit entry");
+
 struct BinArgs {
   int l_begin;        // first binned level
   uint32_t off0;      // its first parameter
@@ -852,7 +894,7 @@ __global__ __launch_bounds__(256) void k_bin_count(DevCfg c, BinArgs A, const nb
 }
 
 // pass 2: write every record at its place: offsets = exclusive scan of counts
-template <int F>
+template <int F, bool R8>
 __global__ __launch_bounds__(256) void k_bin_write(DevCfg c, BinArgs A, const nbvh_probe* __restrict__ probes,
                                                    uint32_t n, const float* __restrict__ duT, uint64_t ldb,
                                                    const uint32_t* __restrict__ offsets, uint16_t* __restrict__ rec_idx,
@@ -867,8 +909,9 @@ __global__ __launch_bounds__(256) void k_bin_write(DevCfg c, BinArgs A, const nb
       const uint32_t rel = idx - A.off0;
       const uint32_t slot = atomicAdd(&cursor[rel / kBinChunk], 1u);
       if constexpr (F == 2) {
-        // one 12-byte record (entry, value pair): one store per contribution
-        ((uint3*)rec_val)[slot] = uint3{rel % kBinChunk, __float_as_uint(v[0]), __float_as_uint(v[1])};
+        // one record (entry, value pair): one store per contribution
+        typedef BinRecord<R8> Rec;
+        ((typename Rec::T*)rec_val)[slot] = Rec::pack(rel % kBinChunk, v[0], v[1]);
       } else {
         rec_idx[slot] = (uint16_t)(rel % kBinChunk);
 #pragma unroll
@@ -888,16 +931,18 @@ __global__ __launch_bounds__(256) void k_bin_write(DevCfg c, BinArgs A, const nb
 constexpr int kStagedBins = 1024;
 constexpr int kStageCap = 256 * 8;
 
+template <bool R8>
 __global__ __launch_bounds__(256) void k_bin_write_staged(DevCfg c, BinArgs A, const nbvh_probe* __restrict__ probes,
                                                           uint32_t n, const float* __restrict__ duT, uint64_t ldb,
                                                           const uint32_t* __restrict__ offsets,
-                                                          uint3* __restrict__ rec) {
+                                                          typename BinRecord<R8>::T* __restrict__ rec) {
   constexpr int F = 2;
+  typedef BinRecord<R8> Rec;
   __shared__ uint32_t cursor[kStagedBins];  // next slot of each bin for this workgroup
   __shared__ uint32_t cnt[kStagedBins];     // the round's records per bin
   __shared__ uint32_t off[kStagedBins];     // their exclusive offsets in the stage
   __shared__ uint32_t sbase[kStagedBins];   // slot of the round's first record of each bin
-  __shared__ uint3 stage[kStageCap];
+  __shared__ typename Rec::T stage[kStageCap];
   __shared__ uint32_t slot_of[kStageCap];
   __shared__ uint32_t wtot[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1007,7 +1052,7 @@ __global__ __launch_bounds__(256) void k_bin_write_staged(DevCfg c, BinArgs A, c
         for (int k = 0; k < 8; ++k) {
           const uint32_t bin = rel[k] / kBinChunk;
           const uint32_t i = off[bin] + rank[k];
-          stage[i] = uint3{rel[k] % kBinChunk, __float_as_uint(v0[k]), __float_as_uint(v1[k])};
+          stage[i] = Rec::pack(rel[k] % kBinChunk, v0[k], v1[k]);
           slot_of[i] = sbase[bin] + rank[k];
         }
       }
@@ -1020,7 +1065,7 @@ __global__ __launch_bounds__(256) void k_bin_write_staged(DevCfg c, BinArgs A, c
 
 // pass 3: one workgroup per bin accumulates in LDS (64-bit fixed point) and
 // updates its chunk with plain read-modify-writes
-template <int F>
+template <int F, bool R8>
 __global__ __launch_bounds__(1024) void k_bin_reduce(BinArgs A, const uint32_t* __restrict__ offsets, uint32_t n_wgs,
                                                      const uint16_t* __restrict__ rec_idx,
                                                      const float* __restrict__ rec_val, uint64_t n_table,
@@ -1044,10 +1089,9 @@ __global__ __launch_bounds__(1024) void k_bin_reduce(BinArgs A, const uint32_t* 
       const uint32_t rr = r + u * blockDim.x;
       const bool ok = rr < r1;
       if constexpr (F == 2) {
-        const uint3 rec = ok ? ((const uint3*)rec_val)[rr] : uint3{0xffffffffu, 0u, 0u};
-        ix[u] = rec.x;
-        v[u][0] = __uint_as_float(rec.y);
-        v[u][1] = __uint_as_float(rec.z);
+        typedef BinRecord<R8> Rec;
+        const typename Rec::T rec = ok ? ((const typename Rec::T*)rec_val)[rr] : Rec::none();
+        Rec::unpack(rec, ix[u], v[u][0], v[u][1]);
       } else {
         ix[u] = ok ? (uint32_t)rec_idx[rr] : 0xffffffffu;
 #pragma unroll
@@ -1115,19 +1159,33 @@ static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char
     const uint32_t cells = T.n_bins * (uint32_t)kBinWgs;
     nbvh_status s = launch_exclusive_scan(L.stream, counts, cells, offsets, sums, sums + cells / 1024 + 3);
     if (s != NBVH_OK) return s;
-    if (F == 2 && T.n_bins <= (uint32_t)kStagedBins)
-      k_bin_write_staged<<<kBinWgs, 256, 0, L.stream>>>(c, A, probes, n, duT, ldb, offsets, (uint3*)(w + T.rec_val));
-    else
-      k_bin_write<F><<<kBinWgs, 256, hist_lds, L.stream>>>(c, A, probes, n, duT, ldb, offsets,
-                                                          (uint16_t*)(w + T.rec_idx), (float*)(w + T.rec_val));
+    if (F == 2 && T.n_bins <= (uint32_t)kStagedBins) {
+      if (T.rec8)
+        k_bin_write_staged<true><<<kBinWgs, 256, 0, L.stream>>>(c, A, probes, n, duT, ldb, offsets,
+                                                                (uint2*)(w + T.rec_val));
+      else
+        k_bin_write_staged<false><<<kBinWgs, 256, 0, L.stream>>>(c, A, probes, n, duT, ldb, offsets,
+                                                                 (uint3*)(w + T.rec_val));
+    } else if (F == 2 && T.rec8) {
+      k_bin_write<F, true><<<kBinWgs, 256, hist_lds, L.stream>>>(c, A, probes, n, duT, ldb, offsets,
+                                                                (uint16_t*)(w + T.rec_idx), (float*)(w + T.rec_val));
+    } else {
+      k_bin_write<F, false><<<kBinWgs, 256, hist_lds, L.stream>>>(c, A, probes, n, duT, ldb, offsets,
+                                                                 (uint16_t*)(w + T.rec_idx), (float*)(w + T.rec_val));
+    }
   }
   {
     ProfScope ps(L.prof, NBVH_K_SCATTER_REDUCE, L.stream);
     // per entry: at most n probes x S runs
     const uint32_t log2_terms = (uint32_t)(32 - __builtin_clz(n * (uint32_t)c.n_samples - 1u));
-    k_bin_reduce<F><<<T.n_bins, 1024, 0, L.stream>>>(A, offsets, kBinWgs, (const uint16_t*)(w + T.rec_idx),
-                                                     (const float*)(w + T.rec_val), c.n_table, gmax, log2_terms,
-                                                     c.n_samples, L.state, L.grad);
+    if (F == 2 && T.rec8)
+      k_bin_reduce<F, true><<<T.n_bins, 1024, 0, L.stream>>>(A, offsets, kBinWgs, (const uint16_t*)(w + T.rec_idx),
+                                                             (const float*)(w + T.rec_val), c.n_table, gmax,
+                                                             log2_terms, c.n_samples, L.state, L.grad);
+    else
+      k_bin_reduce<F, false><<<T.n_bins, 1024, 0, L.stream>>>(A, offsets, kBinWgs, (const uint16_t*)(w + T.rec_idx),
+                                                              (const float*)(w + T.rec_val), c.n_table, gmax,
+                                                              log2_terms, c.n_samples, L.state, L.grad);
   }
   return check_launch("scatter");
 }
