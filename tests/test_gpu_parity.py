@@ -369,6 +369,36 @@ def test_table_gradient_scatter_paths(lib, c1, path, order):
     assert np.abs(g - ref).max() <= 1e-5 * np.abs(ref).max(), np.abs(g - ref).max() / np.abs(ref).max()
 
 
+def test_bf16_gradient_records(lib, c1):
+    """On the BF16 path the binned levels' contributions travel as 8-byte
+    records, each value rounded to a 24-bit float (at most 2^-16 relative).
+    Every level binned against every level summed from the FP32 contributions
+    (LDS hash, then direct atomics), on the same BF16 forward: the table
+    gradients differ only by that rounding and FP32 summation order, far
+    inside the BF16 path's own 2e-2 bound."""
+    sc, _ = c1
+    net = NETS["c2"]
+    params = _params(net, scale=1.0)
+    p, _ = scene.leaf_probes(sc.boxes, 40, seed=17)
+    n = p.shape[0]
+    dz = (np.random.default_rng(19).normal(size=(n, net.n_out)) / n).astype(np.float32)
+    nt = net.n_table_params
+    routes = {"records": dict(scatter_lds_kb=0, scatter_hash_levels=0, scatter_binned=1),
+              "fp32 sums": dict(scatter_lds_kb=0, scatter_hash_levels=32, scatter_binned=0)}
+    g = {}
+    for name, knobs in routes.items():
+        m = lib.NBVH(net, sc.boxes, sc.lo, sc.side, precision="bf16", loss_scale=1024.0)
+        m.set_params(params)
+        m.set_tuning(**knobs)
+        m.backward(torch.from_numpy(p).cuda(), torch.from_numpy(dz).cuda())
+        g[name] = m.unpad(m.unscaled_grad())[:nt]
+    a, b = g["records"], g["fp32 sums"]
+    err = float(np.abs(a - b).max() / np.abs(b).max())
+    _say("bf16 table gradient, 8-byte records vs FP32 sums: max |dg| / max |g| = %.3g" % err)
+    assert np.abs(b).max() > 0
+    assert err <= 2e-4, err
+
+
 def _blocks(net):
     """(name, slice) of each parameter block of the unpadded layout."""
     out = [("table", slice(0, net.n_table_params))]
