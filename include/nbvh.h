@@ -478,11 +478,12 @@ nbvh_status nbvh_optimizer_step(nbvh_ctx* ctx, void* stream);
  * total weighted, albedo included). Here and in nbvh_backward, a batch
  * whose binned table-gradient pass would need more than 2^32 records
  * (n * binned levels * n_samples * 8) returns NBVH_ERR_UNSUPPORTED before
- * any launch; split such batches. Both calls run the weight-gradient
- * kernels on a second stream that the context owns, forked from `stream`
- * after the training tile and joined back into it after the table-gradient
- * kernels, so work the caller enqueues on `stream` afterwards sees both;
- * while `stream` is being captured into a graph they use `stream` alone. */
+ * any launch; split such batches. Both calls run the table gradient's
+ * hash-route levels and the weight-gradient kernels on a second stream that
+ * the context owns, forked from `stream` after the training tile and joined
+ * back into it after the other table-gradient kernels, so work the caller
+ * enqueues on `stream` afterwards sees all of them; while `stream` is being
+ * captured into a graph they use `stream` alone. */
 nbvh_status nbvh_train_step(nbvh_ctx* ctx, const nbvh_probe* probes_dev, const nbvh_label* labels_dev,
                             uint64_t n, float* loss_dev, void* ws_dev, size_t ws_bytes, void* stream);
 

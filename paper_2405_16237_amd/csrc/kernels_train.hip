@@ -1116,6 +1116,23 @@ __global__ __launch_bounds__(1024) void k_bin_reduce(BinArgs A, const uint32_t* 
   }
 }
 
+// The hash-route levels [n_lds, hash_end) of the table gradient, on stream s
+// (they write only their own levels' entries, so they may run beside the
+// other routes).
+template <int F>
+static void launch_scatter_hash(const LaunchCtx& L, const TrainLayout& T, const nbvh_probe* probes, uint32_t n,
+                                const float* duT, uint64_t ldb, const uint32_t* gmax, hipStream_t s) {
+  if (T.hash_end <= T.n_lds) return;
+  ProfScope ps(L.prof, NBVH_K_SCATTER, s);
+  // small batches: one workgroup per (tile, level), so that the chip fills
+  const uint32_t tiles = (n + kHashTile - 1) / kHashTile;
+  const uint32_t split = tiles < 4u * (uint32_t)L.n_cu ? (uint32_t)(T.hash_end - T.n_lds) : 1u;
+  k_scatter_hash<F><<<dim3(tiles, split), kHashTile, 0, s>>>(L.cfg, T.n_lds, T.hash_end, probes, n, duT, ldb, gmax,
+                                                             L.state, L.grad);
+}
+
+// The other levels of the table gradient: [0, n_lds) held in LDS and
+// [hash_end, L) binned or by pairs, on the context's stream.
 template <int F>
 static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char* w, const nbvh_probe* probes,
                                   uint32_t n, const float* duT, uint64_t ldb, const uint32_t* gmax) {
@@ -1126,13 +1143,6 @@ static nbvh_status launch_scatter(const LaunchCtx& L, const TrainLayout& T, char
       const size_t lds = (size_t)T.lds_floats * 4;
       (void)hipFuncSetAttribute((const void*)k_scatter_lds<F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       k_scatter_lds<F><<<L.n_cu, 1024, lds, L.stream>>>(c, T.n_lds, T.lds_floats, probes, n, duT, ldb, L.grad);
-    }
-    if (T.hash_end > T.n_lds) {
-      // small batches: one workgroup per (tile, level), so that the chip fills
-      const uint32_t tiles = (n + kHashTile - 1) / kHashTile;
-      const uint32_t split = tiles < 4u * (uint32_t)L.n_cu ? (uint32_t)(T.hash_end - T.n_lds) : 1u;
-      k_scatter_hash<F><<<dim3(tiles, split), kHashTile, 0, L.stream>>>(c, T.n_lds, T.hash_end, probes, n, duT, ldb,
-                                                                        gmax, L.state, L.grad);
     }
     if (T.hash_end >= c.n_levels) return check_launch("scatter");
     if (T.n_bins == 0) {
@@ -1518,10 +1528,11 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
   // The weight gradients (loss, thin GEMMs over the batch, fixed-order split
   // reduction: HBM streaming and matrix cores) and the table gradient (LDS
   // atomics and scattered record stores) depend only on the tile's outputs and
-  // write disjoint parts of the gradient, so the first runs on the context's
-  // second stream beside the second; the step joins both before returning.
-  // Not while the caller's stream is being captured into a graph: there the
-  // step stays on that one stream.
+  // write disjoint parts of the gradient, and so do the table gradient's hash
+  // route and its other routes; the hash route and then the weight gradients
+  // run on the context's second stream beside the other routes, and the step
+  // joins both before returning. Not while the caller's stream is being
+  // captured into a graph: there the step stays on that one stream.
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(L.stream, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
   const bool fork = L.side && L.ev_fork && L.ev_join && cap == hipStreamCaptureStatusNone;
@@ -1531,6 +1542,7 @@ static nbvh_status train_t(const LaunchCtx& L, const nbvh_probe* probes, const n
       return set_error("forking the weight-gradient stream failed"), NBVH_ERR_HIP;
     gs = L.side;
   }
+  launch_scatter_hash<F>(L, T, probes, n, P.duT, kb, P.gmax, gs);
   {
     ProfScope ps(L.prof, NBVH_K_WGRAD, gs);
     if (labels)
